@@ -1,0 +1,364 @@
+"""FP64 CPU oracle for the cavity-coupled Landau-Lifshitz-Gilbert hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only tests/, the smoke check and the CPU-baseline
+leg of the benchmark may import this module; the product path never does, and
+this module shares no code with the HIP library.
+
+Plain, slow, obviously correct: every step is the formula written out in
+numpy float64, in the order the paper states the problem.
+
+  * LLG in Landau-Lifshitz form with Gilbert damping, Eq. (llg):
+        dm/dt = -gamma/(1+alpha^2) [ m x B + alpha m x (m x B) ] .
+  * Effective field (sum of contributions listed after Eq. (llg)): Zeeman,
+    exchange, uniaxial anisotropy, demagnetisation, plus the cavity field
+    B_rms (alpha + alpha^*) that the mean-field equations add,
+    Eqs. (eqmotionspinclasical)-(eqmotionaclasical); the cavity field enters
+    both the precession and the damping term (end of section "The LLG
+    equation in Mumax3").
+  * Cavity mode, Eq. (eqmotionaclasical) with the loss omega_c -> omega_c -
+    i kappa of section "Introducing the effect of the cavity": with
+    S_i = -Ms_i V_c m_i / gamma (moment mu = -gamma S, M = mu/V_c),
+        d alpha/dt = -(i wc + kappa) alpha + i (V_c/hbar) sum_i Ms_i m_i.B_rms
+                     - i eps(t)            (eps: optional cavity drive).
+  * Time integration: classic RK4 (fixed step) or Dormand-Prince 5(4) with
+    FSAL on the joint state (m, alpha); m renormalised after every accepted
+    step; time-dependent terms evaluated at the stage times.
+  * The integrated-out (memory-kernel) form of the cavity field, Eqs.
+    (bcav)-(gammafinal), and the paper's rectangle-rule recursion,
+    Eqs. (Sdiscrete)-(gammadiscretefinal), are provided for cross-checks.
+
+Readings where the paper is silent: gamma = 1.7595e11 rad/(s T); open
+(Neumann) exchange boundaries; zero padding 2n per axis; DP45 error norm
+max(max_i |m5-m4|_2, |a5-a4|/max(1,|a5|)) with controller
+dt <- dt*clamp(0.9 (tol/err)^(1/5), 0.2, 5), no growth right after a
+rejection; sinc(0) = 1.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import demag as _demag
+
+DRIVE_NONE, DRIVE_SINC, DRIVE_CW = 0, 1, 2
+
+# Dormand & Prince (1980) RK5(4)7M tableau.
+DP_C = np.array([0.0, 1 / 5, 3 / 10, 4 / 5, 8 / 9, 1.0, 1.0])
+DP_A = [
+    [],
+    [1 / 5],
+    [3 / 40, 9 / 40],
+    [44 / 45, -56 / 15, 32 / 9],
+    [19372 / 6561, -25360 / 2187, 64448 / 6561, -212 / 729],
+    [9017 / 3168, -355 / 33, 46732 / 5247, 49 / 176, -5103 / 18656],
+    [35 / 384, 0.0, 500 / 1113, 125 / 192, -2187 / 6784, 11 / 84],
+]
+DP_B5 = np.array([35 / 384, 0.0, 500 / 1113, 125 / 192, -2187 / 6784, 11 / 84,
+                  0.0])
+DP_B4 = np.array([5179 / 57600, 0.0, 7571 / 16695, 393 / 640,
+                  -92097 / 339200, 187 / 2100, 1 / 40])
+
+
+def drive_shape(kind, w, t):
+    """Time profile f(t) of a drive: sinc(w t) with sinc(0)=1, or cos(w t)."""
+    if kind == DRIVE_NONE:
+        return 0.0
+    if kind == DRIVE_SINC:
+        x = w * t
+        return 1.0 if x == 0.0 else math.sin(x) / x
+    if kind == DRIVE_CW:
+        return math.cos(w * t)
+    raise ValueError(kind)
+
+
+def normalise(m):
+    return m / np.sqrt((m * m).sum(axis=0))
+
+
+class CavityLLG:
+    """The joint (m, alpha) right-hand side and integrators for one Problem.
+
+    m has shape (3, nz, ny, nx); alpha is a Python complex.
+    demag: 'fft' (zero-padded FFT convolution), 'direct' (brute force), or
+    'auto' (direct for <= 64 cells)."""
+
+    def __init__(self, prob, demag="auto"):
+        self.p = prob
+        self.shape = (prob.nz, prob.ny, prob.nx)
+        self.ms = prob.ms_array()
+        self.ku = prob.ku_array()
+        self.vc = prob.dx * prob.dy * prob.dz
+        self.u = np.asarray(prob.anis_u, dtype=np.float64)
+        self.brms = np.asarray(prob.brms, dtype=np.float64)
+        self.nfull = None
+        self.kf = None
+        self.demag_mode = None
+        if prob.enable_demag:
+            ncell = prob.nx * prob.ny * prob.nz
+            mode = demag
+            if mode == "auto":
+                mode = "direct" if ncell <= 64 else "fft"
+            self.demag_mode = mode
+            self.nfull = _demag.tensor_full(prob.nx, prob.ny, prob.nz,
+                                            prob.dx, prob.dy, prob.dz)
+            if mode == "fft":
+                self.kf = _demag.demag_kernel_fft(self.nfull, self.shape)
+        self.nevals = 0
+
+    # ---------------------------------------------------------------- fields
+    def zeeman(self, t):
+        p = self.p
+        b = np.asarray(p.bext, dtype=np.float64)
+        f = drive_shape(p.fdrive_kind, p.fdrive_w, t)
+        b = b + p.fdrive_amp * f * np.asarray(p.fdrive_dir, dtype=np.float64)
+        return b.reshape(3, 1, 1, 1) * np.ones((1,) + self.shape)
+
+    def exchange(self, m):
+        """B_ex,i = (2A/Ms_i) sum_neighbours (m_j - m_i)/d^2, open boundary."""
+        p = self.p
+        lap = np.zeros_like(m)
+        for axis, d in ((3, p.dx), (2, p.dy), (1, p.dz)):
+            if m.shape[axis] < 2:
+                continue
+            diff = np.diff(m, axis=axis) / (d * d)
+            lo = [slice(None)] * 4
+            hi = [slice(None)] * 4
+            lo[axis] = slice(0, -1)
+            hi[axis] = slice(1, None)
+            lap[tuple(lo)] += diff
+            lap[tuple(hi)] -= diff
+        return 2.0 * p.aex / self.ms * lap
+
+    def anisotropy(self, m):
+        """Uniaxial: B_a = (2 Ku/Ms) (u.m) u."""
+        um = np.einsum("c,czyx->zyx", self.u, m)
+        return (2.0 * self.ku / self.ms * um)[None] * self.u.reshape(3, 1, 1,
+                                                                      1)
+
+    def demag(self, m):
+        if self.demag_mode is None:
+            return np.zeros_like(m)
+        M = self.ms * m
+        if self.demag_mode == "direct":
+            return _demag.demag_field_direct(M, self.nfull, self.p.mu0)
+        return _demag.demag_field_fft(M, self.kf, self.p.mu0)
+
+    def cavity_field(self, a):
+        """B_cav = B_rms (alpha + alpha^*)."""
+        return (self.brms * 2.0 * a.real).reshape(3, 1, 1, 1) * np.ones(
+            (1,) + self.shape)
+
+    def effective_field(self, m, a, t):
+        return (self.zeeman(t) + self.exchange(m) + self.anisotropy(m)
+                + self.demag(m) + self.cavity_field(a))
+
+    def coupling_sum(self, m):
+        """F = sum_i Ms_i m_i . B_rms  (A m^-1 T)."""
+        return float((self.ms * np.einsum("c,czyx->zyx", self.brms, m)).sum())
+
+    # -------------------------------------------------------------- dynamics
+    def torque(self, m, B):
+        p = self.p
+        mxB = np.cross(m, B, axis=0)
+        mxmxB = np.cross(m, mxB, axis=0)
+        return -p.gamma / (1.0 + p.alpha ** 2) * (mxB + p.alpha * mxmxB)
+
+    def cavity_rate(self, a, F, t):
+        p = self.p
+        eps = p.cdrive_amp * drive_shape(p.cdrive_kind, p.cdrive_w, t)
+        return (-(1j * p.wc + p.kappa) * a + 1j * (self.vc / p.hbar) * F
+                - 1j * eps)
+
+    def rhs(self, m, a, t):
+        self.nevals += 1
+        B = self.effective_field(m, a, t)
+        return self.torque(m, B), self.cavity_rate(a, self.coupling_sum(m), t)
+
+    def energy(self, m, a, t=0.0):
+        """Total energy of Eq. (startH) in the classical limit (J):
+        Zeeman + exchange + anisotropy + demag - V_c 2Re(a) F + hbar wc |a|^2.
+        """
+        p = self.p
+        vc = self.vc
+        ez = -vc * (self.ms * (m * self.zeeman(t)).sum(axis=0)).sum()
+        ex = 0.0
+        for axis, d in ((3, p.dx), (2, p.dy), (1, p.dz)):
+            if m.shape[axis] >= 2:
+                ex += vc * p.aex * (np.diff(m, axis=axis) ** 2).sum() / (d * d)
+        um = np.einsum("c,czyx->zyx", self.u, m)
+        ea = -vc * (self.ku * um * um).sum()
+        ed = -0.5 * vc * (self.ms * (m * self.demag(m)).sum(axis=0)).sum()
+        ec = -vc * 2.0 * a.real * self.coupling_sum(m) + \
+            p.hbar * p.wc * abs(a) ** 2
+        return float(ez + ex + ea + ed + ec)
+
+    # ----------------------------------------------------------- integrators
+    def step_rk4(self, m, a, t, dt):
+        k1m, k1a = self.rhs(m, a, t)
+        k2m, k2a = self.rhs(m + 0.5 * dt * k1m, a + 0.5 * dt * k1a,
+                            t + 0.5 * dt)
+        k3m, k3a = self.rhs(m + 0.5 * dt * k2m, a + 0.5 * dt * k2a,
+                            t + 0.5 * dt)
+        k4m, k4a = self.rhs(m + dt * k3m, a + dt * k3a, t + dt)
+        mn = m + dt / 6.0 * (k1m + 2 * k2m + 2 * k3m + k4m)
+        an = a + dt / 6.0 * (k1a + 2 * k2a + 2 * k3a + k4a)
+        return normalise(mn), an
+
+    def dp45_attempt(self, m, a, t, h, k1m, k1a):
+        """One Dormand-Prince attempt.  Returns (m5, a5, err, k7m, k7a) with
+        m5 not yet renormalised and k7 = f(t+h, m5, a5) (FSAL)."""
+        km = [k1m]
+        ka = [k1a]
+        for s in range(1, 7):
+            ms_ = m + h * sum(DP_A[s][j] * km[j] for j in range(s)
+                              if DP_A[s][j] != 0.0)
+            as_ = a + h * sum(DP_A[s][j] * ka[j] for j in range(s))
+            if s == 6:
+                m5, a5 = ms_, as_
+            dm, da = self.rhs(ms_, as_, t + DP_C[s] * h)
+            km.append(dm)
+            ka.append(da)
+        e = DP_B5 - DP_B4
+        errm_vec = h * sum(e[j] * km[j] for j in range(7) if e[j] != 0.0)
+        errm = float(np.sqrt((errm_vec ** 2).sum(axis=0)).max())
+        erra = abs(h * sum(e[j] * ka[j] for j in range(7))) / max(1.0,
+                                                                   abs(a5))
+        return m5, a5, max(errm, erra), km[6], ka[6]
+
+    # ------------------------------------------------------------------ runs
+    def record(self, t, m, a):
+        mm = m.reshape(3, -1).mean(axis=1)
+        return [t, mm[0], mm[1], mm[2], a.real, a.imag]
+
+    def run_rk4(self, m0, a0, dt, nsteps, record_every=0, t0=0.0):
+        """Fixed-step RK4.  Records (t, <m>, Re a, Im a) for the initial state
+        and after every `record_every`-th step."""
+        m = np.asarray(m0, dtype=np.float64).copy()
+        a = complex(a0)
+        t = t0
+        rec = [self.record(t, m, a)] if record_every else []
+        for n in range(1, nsteps + 1):
+            m, a = self.step_rk4(m, a, t, dt)
+            t = t0 + n * dt
+            if record_every and n % record_every == 0:
+                rec.append(self.record(t, m, a))
+        return m, a, t, np.array(rec)
+
+    def run_dp45(self, m0, a0, t_end, tol, dt0, record_every=0, t0=0.0,
+                 dt_min=1e-20, dt_max=1e-10, max_attempts=10 ** 7):
+        """Adaptive Dormand-Prince from t0 to t_end (last step truncated to
+        land on t_end).  Returns m, a, t, records, accepted dt list, stats."""
+        m = np.asarray(m0, dtype=np.float64).copy()
+        a = complex(a0)
+        t = t0
+        k1m, k1a = self.rhs(m, a, t)
+        dt = dt0
+        prev_rej = False
+        rec = [self.record(t, m, a)] if record_every else []
+        dts = []
+        nacc = nrej = 0
+        for _ in range(max_attempts):
+            if t >= t_end:
+                break
+            h = min(dt, t_end - t)
+            m5, a5, err, k7m, k7a = self.dp45_attempt(m, a, t, h, k1m, k1a)
+            if not (math.isfinite(err) and np.isfinite(m5).all()):
+                err = math.inf
+            if err <= tol:
+                fac = 5.0 if err == 0.0 else min(5.0, max(
+                    0.2, 0.9 * (tol / err) ** 0.2))
+                if prev_rej:
+                    fac = min(fac, 1.0)
+                t = t + h
+                m = normalise(m5)
+                a = a5
+                k1m, k1a = k7m, k7a
+                dts.append(h)
+                nacc += 1
+                prev_rej = False
+                if record_every and nacc % record_every == 0:
+                    rec.append(self.record(t, m, a))
+            else:
+                fac = 0.2 if not math.isfinite(err) else max(
+                    0.2, 0.9 * (tol / err) ** 0.2)
+                prev_rej = True
+                nrej += 1
+            dt = min(dt_max, h * fac)
+            if dt < dt_min:
+                raise FloatingPointError("time step underflow")
+        return m, a, t, np.array(rec), np.array(dts), dict(accepted=nacc,
+                                                           rejected=nrej)
+
+    def run_dp45_replay(self, m0, a0, dts, t0=0.0):
+        """Dormand-Prince with a prescribed sequence of accepted step sizes
+        (every step accepted, FSAL and renormalisation as in run_dp45)."""
+        m = np.asarray(m0, dtype=np.float64).copy()
+        a = complex(a0)
+        t = t0
+        k1m, k1a = self.rhs(m, a, t)
+        for h in dts:
+            m5, a5, err, k1m, k1a = self.dp45_attempt(m, a, t, h, k1m, k1a)
+            t += h
+            m = normalise(m5)
+            a = a5
+        return m, a, t
+
+
+# ---------------------------------------------------------------------------
+# Integrated-out cavity (the paper's memory-kernel form), for cross-checks.
+# ---------------------------------------------------------------------------
+def memory_gamma(ts, Fs, prob, a0):
+    """Gamma(t_n) of Eq. (gammafinal) by the trapezoid rule on samples
+    F(t_k) = sum_i Ms_i m_i(t_k).B_rms, for every sample time t_n:
+      Gamma(t) = 2 e^{-kappa t} Re(a0 e^{-i wc t})
+                 - (2 V_c/hbar) int_0^t e^{kappa (tau-t)} sin(wc (tau-t)) F dtau
+    """
+    vc = prob.dx * prob.dy * prob.dz
+    out = np.empty(len(ts))
+    for n, t in enumerate(ts):
+        tau = ts[: n + 1]
+        integrand = np.exp(prob.kappa * (tau - t)) * np.sin(
+            prob.wc * (tau - t)) * Fs[: n + 1]
+        integral = np.trapezoid(integrand, tau) if n > 0 else 0.0
+        out[n] = (2.0 * math.exp(-prob.kappa * t)
+                  * (a0 * np.exp(-1j * prob.wc * t)).real
+                  - 2.0 * vc / prob.hbar * integral)
+    return out
+
+
+def alpha_a_posteriori(ts, Fs, prob, a0):
+    """alpha(t) recovered from the magnetisation history (trapezoid rule):
+      alpha = a0 e^{-(kappa + i wc) t}
+              + i (V_c/hbar) int_0^t e^{(kappa + i wc)(tau - t)} F dtau ."""
+    vc = prob.dx * prob.dy * prob.dz
+    out = np.empty(len(ts), dtype=complex)
+    for n, t in enumerate(ts):
+        tau = ts[: n + 1]
+        integrand = np.exp((prob.kappa + 1j * prob.wc) * (tau - t)) * Fs[
+            : n + 1]
+        integral = np.trapezoid(integrand, tau) if n > 0 else 0.0
+        out[n] = a0 * np.exp(-(prob.kappa + 1j * prob.wc) * t) + \
+            1j * vc / prob.hbar * integral
+    return out
+
+
+def memory_gamma_recursive(ts, Fs, prob, x0, p0):
+    """The paper's O(1)-per-step recursion, Eqs. (Sdiscrete), (Cdiscrete) and
+    (gammadiscretefinal), on uniformly spaced samples t_n = n dt:
+      S_n = S_{n-1} + e^{kappa t_n} sin(wc t_n) F_n dt ,  S_0 = C_0 = 0
+      C_n = C_{n-1} + e^{kappa t_n} cos(wc t_n) F_n dt
+      Gamma_n = e^{-kappa t_n} cos(wc t_n) (x0 - 2 V_c S_n / hbar)
+              - e^{-kappa t_n} sin(wc t_n) (p0 - 2 V_c C_n / hbar)."""
+    vc = prob.dx * prob.dy * prob.dz
+    dt = ts[1] - ts[0]
+    S = C = 0.0
+    out = np.empty(len(ts))
+    for n, t in enumerate(ts):
+        if n > 0:
+            S += math.exp(prob.kappa * t) * math.sin(prob.wc * t) * Fs[n] * dt
+            C += math.exp(prob.kappa * t) * math.cos(prob.wc * t) * Fs[n] * dt
+        ek = math.exp(-prob.kappa * t)
+        out[n] = (ek * math.cos(prob.wc * t) * (x0 - 2 * vc * S / prob.hbar)
+                  - ek * math.sin(prob.wc * t) * (p0 - 2 * vc * C / prob.hbar))
+    return out

@@ -1,0 +1,390 @@
+"""Pins of the FP64 LLG + cavity oracle against results fixed by the paper and
+by the mathematics: the Dicke model's polariton frequencies, equilibrium
+magnetisation and threshold (section "Benchmark", Eqs. (dickeeqmag) and
+(dickepolaritons)), Kittel frequencies, the exchange eigenmode, energy
+conservation of Eq. (startH), cavity free decay and CW drive, the equivalence
+of the explicit cavity ODE with the paper's memory-kernel form (Eqs. (bcav),
+(gammafinal)) and its a-posteriori alpha, and integrator orders.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import demag as D
+from oracle.llg import CavityLLG, DRIVE_CW, normalise
+from paper_2410_00966_amd import inputs as I
+
+WC = 2 * math.pi * 10e9
+
+
+def _jacobian_freqs(o, m_eq, a_eq, damped=False):
+    """Eigenvalues of the oracle's RHS linearised about (m_eq, a_eq); the
+    state is parametrised by (m_x, m_y, Re a, Im a) with |m| = 1."""
+    sgn = 1.0 if m_eq[2] >= 0 else -1.0
+
+    def f(v):
+        mx, my, ar, ai = v
+        mz = sgn * math.sqrt(1 - mx * mx - my * my)
+        m = np.array([mx, my, mz]).reshape(3, 1, 1, 1)
+        dm, da = o.rhs(m, complex(ar, ai), 0.0)
+        return np.array([dm[0, 0, 0, 0], dm[1, 0, 0, 0], da.real, da.imag])
+
+    v0 = np.array([m_eq[0], m_eq[1], a_eq.real, a_eq.imag])
+    J = np.zeros((4, 4))
+    for j in range(4):
+        h = 1e-7 * (1.0 if j < 2 else max(1.0, abs(a_eq)))
+        e = np.zeros(4)
+        e[j] = h
+        J[:, j] = (f(v0 + e) - f(v0 - e)) / (2 * h)
+    return np.linalg.eigvals(J)
+
+
+def _dicke_normal(wz, wc, lam):
+    r = math.sqrt((wz ** 2 - wc ** 2) ** 2 + 16 * lam ** 2 * wz * wc)
+    return (math.sqrt((wz ** 2 + wc ** 2 - r) / 2),
+            math.sqrt((wz ** 2 + wc ** 2 + r) / 2))
+
+
+def _dicke_super(wz, wc, mu):
+    """Superradiant polaritons with the inner sign read as a difference."""
+    A = wz ** 2 / mu ** 2 + wc ** 2
+    r = math.sqrt((wz ** 2 / mu ** 2 - wc ** 2) ** 2 + 4 * wz ** 2 * wc ** 2)
+    return math.sqrt((A - r) / 2), math.sqrt((A + r) / 2)
+
+
+@pytest.mark.parametrize("detune", [0.7, 1.0, 1.3])
+@pytest.mark.parametrize("ratio", [0.02, 0.3, 0.8])
+def test_dicke_normal_phase_polaritons(detune, ratio):
+    wz = detune * WC
+    lam = ratio * math.sqrt(WC * wz) / 2
+    p, _ = I.dicke_macrospin(wz, WC, lam)
+    ev = _jacobian_freqs(CavityLLG(p), [0, 0, 1], 0j)
+    got = np.sort(np.abs(ev.imag))[::2]
+    assert np.allclose(got, _dicke_normal(wz, WC, lam), rtol=1e-9)
+    assert np.abs(ev.real).max() < 1e-6 * WC
+
+
+@pytest.mark.parametrize("ratio", [1.2, 1.4, 2.0])
+def test_dicke_superradiant_polaritons(ratio):
+    wz = WC
+    lamc = math.sqrt(WC * wz) / 2
+    lam = ratio * lamc
+    mu = (lamc / lam) ** 2
+    p, _ = I.dicke_macrospin(wz, WC, lam)
+    o = CavityLLG(p)
+    mx = math.sqrt(1 - mu * mu)
+    m = np.array([mx, 0.0, mu]).reshape(3, 1, 1, 1)
+    a = complex(o.vc / p.hbar * o.coupling_sum(m) / p.wc, 0.0)
+    dm, da = o.rhs(m, a, 0.0)
+    assert np.abs(dm).max() < 1e-9 * WC and abs(da) < 1e-9 * WC
+    ev = _jacobian_freqs(o, [mx, 0, mu], a)
+    got = np.sort(np.abs(ev.imag))[::2]
+    assert np.allclose(got, _dicke_super(wz, WC, mu), rtol=1e-8)
+
+
+def test_superradiant_formula_as_printed_is_inconsistent():
+    """The printed superradiant branch adds inside the square root, which
+    makes Omega_-^2 negative for every coupling; the difference reading used
+    above is the one the linearisation confirms."""
+    wz = WC
+    for ratio in (1.2, 1.4, 2.0):
+        mu = 1.0 / ratio ** 2
+        A = wz ** 2 / mu ** 2 + WC ** 2
+        printed = A - math.sqrt(A ** 2 + 4 * wz ** 2 * WC ** 2)
+        assert printed < 0
+
+
+def _relax_macrospin(wz, lam, kappa, alpha, m0, t_end, dt):
+    p, m = I.dicke_macrospin(wz, WC, lam, kappa=kappa, alpha=alpha, m0=m0)
+    o = CavityLLG(p)
+    m, a, t, _ = o.run_rk4(m.astype(np.float64), 0j, dt, int(t_end / dt))
+    return m[:, 0, 0, 0], a
+
+
+def test_dicke_superradiant_equilibrium_with_loss():
+    """Above threshold the damped macrospin settles at |m_x| = sqrt(1-mu^2)
+    with mu = (lambda_c(kappa)/lambda)^2, lambda_c(kappa) =
+    sqrt(wz (wc^2+kappa^2)/wc)/2 (the lossless threshold of Eq. (dickeeqmag)
+    shifted by the cavity loss)."""
+    wz = WC
+    kappa = 0.3 * WC
+    lamc = 0.5 * math.sqrt(wz * (WC ** 2 + kappa ** 2) / WC)
+    lam = 1.4 * lamc
+    mu = (lamc / lam) ** 2
+    m, a = _relax_macrospin(wz, lam, kappa, 0.3, [0.2, 0.1, 0.97], 4e-9,
+                            2e-13)
+    assert abs(m[0]) == pytest.approx(math.sqrt(1 - mu * mu), abs=1e-6)
+    assert m[2] == pytest.approx(mu, abs=1e-6)
+
+
+def test_dicke_normal_phase_relaxes_to_zero():
+    wz = WC
+    kappa = 0.3 * WC
+    lamc = 0.5 * math.sqrt(wz * (WC ** 2 + kappa ** 2) / WC)
+    m, a = _relax_macrospin(wz, 0.9 * lamc, kappa, 0.3, [0.2, 0.1, 0.97],
+                            4e-9, 2e-13)
+    assert abs(m[0]) < 1e-6 and m[2] == pytest.approx(1.0, abs=1e-9)
+
+
+def test_threshold_position_with_loss():
+    """Just above lambda_c(kappa) the normal state is unstable (a Jacobian
+    eigenvalue with positive real part at zero damping in the magnet), just
+    below it is not.  The shift from the lossless threshold is resolved."""
+    wz = WC
+    kappa = 0.5 * WC
+    lamc = 0.5 * math.sqrt(wz * (WC ** 2 + kappa ** 2) / WC)
+    for ratio, unstable in ((0.995, False), (1.005, True)):
+        p, _ = I.dicke_macrospin(wz, WC, ratio * lamc, kappa=kappa)
+        ev = _jacobian_freqs(CavityLLG(p), [0, 0, 1], 0j)
+        assert (ev.real.max() > 1e-6 * WC) == unstable
+
+
+def test_kittel_prism_with_demag():
+    """Single non-cubic cell with demag: omega = gamma sqrt((B + (Nxx-Nzz)
+    mu0 Ms)(B + (Nyy-Nzz) mu0 Ms)), factors from Aharoni's formula."""
+    p = I.Problem(nx=1, ny=1, nz=1, dx=6e-9, dy=4e-9, dz=2e-9, ms=8e5,
+                  alpha=0.0, bext=(0, 0, 1.5))
+    o = CavityLLG(p)
+    a, b, c = 3e-9, 2e-9, 1e-9
+    Nzz = D.aharoni_prism_factor(a, b, c)
+    Nxx = D.aharoni_prism_factor(b, c, a)
+    Nyy = D.aharoni_prism_factor(c, a, b)
+    mu0ms = p.mu0 * p.ms
+    w = p.gamma * math.sqrt((1.5 + (Nxx - Nzz) * mu0ms) *
+                            (1.5 + (Nyy - Nzz) * mu0ms))
+    ev = _jacobian_freqs(o, [0, 0, 1], 0j)
+    assert np.abs(ev.imag).max() == pytest.approx(w, rel=1e-9)
+
+
+def test_kittel_anisotropy_and_damping():
+    """Uniaxial anisotropy along the field: omega = gamma (B + 2Ku/Ms)/(1+a^2),
+    decay rate alpha * omega."""
+    alpha = 0.05
+    p = I.Problem(nx=1, ny=1, nz=1, dx=5e-9, dy=5e-9, dz=5e-9, ms=8e5,
+                  ku1=3e4, anis_u=(0, 0, 1), alpha=alpha, bext=(0, 0, 0.2),
+                  enable_demag=False)
+    ev = _jacobian_freqs(CavityLLG(p), [0, 0, 1], 0j)
+    w0 = p.gamma * (0.2 + 2 * 3e4 / 8e5)
+    mag = ev[np.argmax(np.abs(ev.imag))]
+    assert abs(mag.imag) == pytest.approx(w0 / (1 + alpha ** 2), rel=1e-9)
+    assert mag.real == pytest.approx(-alpha * w0 / (1 + alpha ** 2),
+                                     rel=1e-7)
+
+
+@pytest.mark.parametrize("mode", [1, 3, 7])
+def test_exchange_neumann_cosine_mode(mode):
+    """The open-boundary discrete Laplacian has eigenvectors
+    cos(pi p (i+1/2)/N); the small-angle precession rate of that mode is
+    gamma (B + (2A/Ms)(2/d^2)(1 - cos(pi p/N)))."""
+    N, d = 16, 3e-9
+    p = I.Problem(nx=N, ny=1, nz=1, dx=d, dy=d, dz=d, ms=8e5, aex=1.3e-11,
+                  alpha=0.0, bext=(0, 0, 0.5), enable_demag=False)
+    o = CavityLLG(p)
+    v = np.cos(np.pi * mode * (np.arange(N) + 0.5) / N)
+    eps = 1e-6
+    m = np.zeros((3, 1, 1, N))
+    m[0, 0, 0] = eps * v
+    m[2] = 1.0
+    m = normalise(m)
+    dm, _ = o.rhs(m, 0j, 0.0)
+    w = p.gamma * (0.5 + 2 * p.aex / p.ms * 2 / d ** 2 *
+                   (1 - math.cos(math.pi * mode / N)))
+    # dm_y/dt = -gamma (m x B)_y = -gamma (mz Bx - mx Bz) -> +w eps v
+    assert np.allclose(dm[1, 0, 0] / (eps * v), w, rtol=1e-5)
+
+
+def _conservative_problem():
+    p = I.Problem(nx=4, ny=3, nz=2, dx=3e-9, dy=4e-9, dz=2.5e-9, ms=8e5,
+                  aex=1.3e-11, alpha=0.0, ku1=2e4, anis_u=(0.6, 0.0, 0.8),
+                  bext=(0.02, 0.05, 0.1), enable_demag=True)
+    p.wc = 2 * math.pi * 12e9
+    p.kappa = 0.0
+    p.brms = (0.0, 3e-3, 1e-3)
+    m0 = I.tilted_uniform_state(p.shape, 40.0, 0.2, seed=11)
+    return p, m0.astype(np.float64)
+
+
+def test_energy_conserved_at_zero_damping_and_loss():
+    """Eq. (startH) in the classical limit is conserved when alpha = kappa = 0
+    and fields are static; RK4 drift falls >= 16x when dt halves."""
+    p, m0 = _conservative_problem()
+    o = CavityLLG(p, demag="direct")
+    a0 = 0.3 + 0.2j
+    E0 = o.energy(m0, a0)
+    drifts = []
+    for dt, n in ((4e-14, 200), (2e-14, 400)):
+        m, a, _, _ = o.run_rk4(m0, a0, dt, n)
+        drifts.append(abs(o.energy(m, a) - E0))
+    scale = abs(E0)
+    assert drifts[1] / scale < 3e-6
+    assert 12.0 < drifts[0] / drifts[1] < 64.0
+
+
+def test_norm_preserved_after_steps():
+    p, m0 = _conservative_problem()
+    o = CavityLLG(p)
+    m, _, _, _ = o.run_rk4(m0, 0j, 1e-14, 10)
+    assert np.abs(np.sqrt((m * m).sum(0)) - 1).max() < 1e-15
+
+
+def test_cavity_free_decay():
+    p = I.Problem(nx=2, ny=2, nz=1, dx=5e-9, dy=5e-9, dz=5e-9,
+                  enable_demag=False, aex=0.0, bext=(0, 0, 0.1))
+    p.wc, p.kappa = WC, 0.02 * WC
+    o = CavityLLG(p)
+    a0 = 0.7 - 0.4j
+    m0 = np.zeros((3, 1, 2, 2))
+    m0[2] = 1
+    _, a, t, _ = o.run_rk4(m0, a0, 2e-13, 500)
+    assert abs(a - a0 * np.exp(-(1j * p.wc + p.kappa) * t)) < 1e-9
+
+
+def test_cavity_cw_drive_closed_form():
+    """da/dt = -(i wc + kappa) a - i eps0 cos(wd t): exact solution."""
+    p = I.Problem(nx=1, ny=1, nz=1, dx=5e-9, dy=5e-9, dz=5e-9,
+                  enable_demag=False, bext=(0, 0, 0.1))
+    p.wc, p.kappa = WC, 0.05 * WC
+    p.cdrive_kind, p.cdrive_amp, p.cdrive_w = DRIVE_CW, 0.01 * WC, 0.9 * WC
+    o = CavityLLG(p)
+    m0 = np.zeros((3, 1, 1, 1))
+    m0[2] = 1
+    _, a, t, _ = o.run_rk4(m0, 0j, 1e-13, 3000)
+    lam = 1j * p.wc + p.kappa
+    e0, wd = p.cdrive_amp, p.cdrive_w
+    # particular solution of a' + lam a = -i e0 (e^{i wd t} + e^{-i wd t})/2
+    cp = -0.5j * e0 / (lam + 1j * wd)
+    cm = -0.5j * e0 / (lam - 1j * wd)
+    exact = cp * np.exp(1j * wd * t) + cm * np.exp(-1j * wd * t) - \
+        (cp + cm) * np.exp(-lam * t)
+    assert abs(a - exact) < 1e-9 * max(1.0, abs(exact))
+
+
+def test_memory_kernel_form_equals_explicit_ode():
+    """Gamma(t) of Eq. (gammafinal), evaluated on the recorded coupling sum
+    F(t) of an explicit (m, alpha) run, equals 2 Re alpha(t); alpha recovered
+    a posteriori equals the integrated alpha.  The paper's rectangle-rule
+    recursion converges to the same Gamma at first order in dt."""
+    from oracle.llg import (memory_gamma, alpha_a_posteriori,
+                            memory_gamma_recursive)
+    wz = WC
+    lam = 0.3 * math.sqrt(WC * wz) / 2
+    p, m0 = I.dicke_macrospin(wz, WC, lam, kappa=0.05 * WC, alpha=0.01)
+    p.x0, p.p0 = 0.8, -0.3
+    a0 = complex(p.x0 / 2, -p.p0 / 2)
+    o = CavityLLG(p)
+    dt = 2e-14
+    m = m0.astype(np.float64)
+    a = a0
+    ts, Fs, As = [0.0], [o.coupling_sum(m)], [a]
+    for n in range(1, 3001):
+        m, a = o.step_rk4(m, a, (n - 1) * dt, dt)
+        ts.append(n * dt)
+        Fs.append(o.coupling_sum(m))
+        As.append(a)
+    ts, Fs, As = np.array(ts), np.array(Fs), np.array(As)
+    G = memory_gamma(ts, Fs, p, a0)
+    scale = np.abs(2 * As.real).max()
+    assert np.abs(G - 2 * As.real).max() < 1e-5 * scale
+    aa = alpha_a_posteriori(ts, Fs, p, a0)
+    assert np.abs(aa - As).max() < 1e-5 * np.abs(As).max()
+    errs = []
+    for stride in (4, 2):
+        sub = slice(None, None, stride)
+        Gr = memory_gamma_recursive(ts[sub], Fs[sub], p, p.x0, p.p0)
+        errs.append(np.abs(Gr - 2 * As[sub].real).max())
+    assert errs[1] < 0.7 * errs[0]          # first order: ~halves with dt
+    assert errs[1] < 0.05 * scale
+
+
+def _order_problem():
+    p = I.Problem(nx=3, ny=2, nz=1, dx=4e-9, dy=4e-9, dz=4e-9, ms=8e5,
+                  alpha=0.1, bext=(0.05, 0.0, 0.3))
+    p.wc, p.kappa, p.brms = WC, 0.01 * WC, (2e-3, 0.0, 0.0)
+    m0 = I.tilted_uniform_state(p.shape, 30.0, 0.1, seed=3)
+    return p, m0.astype(np.float64)
+
+
+def test_rk4_is_fourth_order():
+    p, m0 = _order_problem()
+    o = CavityLLG(p)
+    T = 2e-12
+    ref, aref, _, _ = o.run_rk4(m0, 0.1j, T / 1024, 1024)
+    errs = []
+    for n in (16, 32, 64):
+        m, a, _, _ = o.run_rk4(m0, 0.1j, T / n, n)
+        errs.append(np.abs(m - ref).max())
+    slopes = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(slopes > 3.6) and np.all(slopes < 4.5)
+
+
+def test_dp45_local_error_order_five():
+    """Local error of one Dormand-Prince step (5th-order solution) scales as
+    h^6; its embedded estimate scales as h^5."""
+    p, m0 = _order_problem()
+    o = CavityLLG(p)
+    k1m, k1a = o.rhs(m0, 0.1j, 0.0)
+    errs, ests = [], []
+    for h in (4e-13, 2e-13, 1e-13):
+        m5, a5, est, _, _ = o.dp45_attempt(m0, 0.1j, 0.0, h, k1m, k1a)
+        ref, _, _, _ = o.run_rk4(m0, 0.1j, h / 256, 256)
+        # compare before renormalisation effects: both are unit to O(h^6)
+        errs.append(np.abs(normalise(m5) - ref).max())
+        ests.append(est)
+    s_err = np.log2(errs[0] / errs[1]), np.log2(errs[1] / errs[2])
+    s_est = np.log2(ests[0] / ests[1]), np.log2(ests[1] / ests[2])
+    assert min(s_err) > 5.3 and min(s_est) > 4.5
+
+
+def test_dp45_adaptive_tracks_fine_reference():
+    p, m0 = _order_problem()
+    o = CavityLLG(p)
+    T = 5e-11
+    m, a, t, _, dts, st = o.run_dp45(m0, 0.1j, T, 1e-7, 1e-14)
+    ref, aref, _, _ = o.run_rk4(m0, 0.1j, T / 4000, 4000)
+    assert t == pytest.approx(T, rel=1e-15)
+    assert np.abs(m - ref).max() < 1e-5
+    assert st["accepted"] == len(dts) > 10
+    # replaying the accepted steps reproduces the adaptive run exactly
+    mr, ar, tr = o.run_dp45_replay(m0, 0.1j, dts)
+    assert np.abs(mr - m).max() == 0.0 and ar == a
+
+
+def _golden_rows():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden",
+                        "dicke_worked_example.txt")
+    rows = []
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            rows.append([float(v) for v in line.split()])
+    return rows
+
+
+@pytest.mark.parametrize("row", _golden_rows())
+def test_golden_dicke_worked_example(row):
+    """The oracle's macrospin reproduces the paper's Dicke benchmark values
+    at the worked-example parameters (fixture with citation)."""
+    ratio, zc, mx_eq, om_m, om_p = row
+    wz = zc * WC
+    lamc = math.sqrt(WC * wz) / 2
+    lam = ratio * lamc
+    p, _ = I.dicke_macrospin(wz, WC, lam)
+    o = CavityLLG(p)
+    if ratio > 1:
+        mu = (lamc / lam) ** 2
+        m_eq = [math.sqrt(1 - mu * mu), 0.0, mu]
+        a_eq = complex(o.vc / p.hbar * o.coupling_sum(
+            np.array(m_eq).reshape(3, 1, 1, 1)) / p.wc, 0.0)
+    else:
+        m_eq, a_eq = [0.0, 0.0, 1.0], 0j
+    ev = _jacobian_freqs(o, m_eq, a_eq)
+    got = np.sort(np.abs(ev.imag))[::2] / WC
+    assert got[0] == pytest.approx(om_m, rel=1e-8)
+    assert got[1] == pytest.approx(om_p, rel=1e-8)
+    if ratio > 1:
+        # relax with a little magnet damping and a weak cavity loss
+        kappa = 1e-3 * WC
+        m, _ = _relax_macrospin(wz, lam, kappa, 0.5, [0.3, 0.0, 0.95],
+                                4e-9, 2e-13)
+        assert abs(m[0]) == pytest.approx(mx_eq, abs=2e-6)

@@ -1,0 +1,69 @@
+"""Plant plausible mistakes in the oracle (on the CPU, by monkeypatching) and
+check that the pins catch each one: a wrong coupling sign, a dropped damping
+prefactor, a periodic instead of open exchange boundary, a transposed
+demag-tensor component and a wrong Dormand-Prince weight."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import demag as D
+from oracle import llg as L
+from paper_2410_00966_amd import inputs as I
+
+import os, sys
+sys.path.insert(0, os.path.dirname(__file__))
+import test_oracle_llg as T  # noqa: E402
+
+
+def test_flipped_coupling_sign_breaks_polaritons(monkeypatch):
+    orig = L.CavityLLG.cavity_rate
+
+    def flipped(self, a, F, t):
+        return orig(self, a, -F, t)
+    monkeypatch.setattr(L.CavityLLG, "cavity_rate", flipped)
+    with pytest.raises(AssertionError):
+        T.test_dicke_normal_phase_polaritons(1.0, 0.3)
+
+
+def test_dropped_damping_prefactor_breaks_kittel(monkeypatch):
+    def torque(self, m, B):
+        mxB = np.cross(m, B, axis=0)
+        return -self.p.gamma * (mxB + self.p.alpha * np.cross(m, mxB, axis=0))
+    monkeypatch.setattr(L.CavityLLG, "torque", torque)
+    with pytest.raises(AssertionError):
+        T.test_kittel_anisotropy_and_damping()
+
+
+def test_periodic_exchange_breaks_cosine_mode(monkeypatch):
+    def exchange(self, m):
+        p = self.p
+        lap = np.zeros_like(m)
+        for axis, d in ((3, p.dx), (2, p.dy), (1, p.dz)):
+            if m.shape[axis] > 1:
+                lap += (np.roll(m, 1, axis) + np.roll(m, -1, axis)
+                        - 2 * m) / (d * d)
+        return 2 * p.aex / self.ms * lap
+    monkeypatch.setattr(L.CavityLLG, "exchange", exchange)
+    with pytest.raises(AssertionError):
+        T.test_exchange_neumann_cosine_mode(3)
+
+
+def test_swapped_tensor_component_breaks_aharoni(monkeypatch):
+    orig = D.tensor_newell
+
+    def swapped(X, Y, Z, dx, dy, dz):
+        N = orig(X, Y, Z, dx, dy, dz)
+        return N[[1, 0, 2, 3, 4, 5]]
+    monkeypatch.setattr(D, "tensor_newell", swapped)
+    import test_oracle_demag as TD
+    with pytest.raises(AssertionError):
+        TD.test_self_term_equals_aharoni_prism((2.0, 1.0, 0.5))
+
+
+def test_wrong_dp_weight_breaks_order(monkeypatch):
+    b5 = L.DP_B5.copy()
+    b5[2] *= 1.001
+    monkeypatch.setattr(L, "DP_B5", b5)
+    with pytest.raises(AssertionError):
+        T.test_dp45_local_error_order_five()
