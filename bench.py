@@ -1,0 +1,194 @@
+"""Benchmark: cavity-LLG cell-steps/s on one MI355X.
+
+Workload: textured film, 1024 x 1024 x 2 cells of 4 nm (Ms 8e5 A/m,
+A 1.3e-11 J/m), 64 seeded vortex/domain-wall centres relaxed for 0.5 ns at
+alpha = 0.5 (untimed), then alpha = 0.02, B_ext 20 mT along x, one cavity mode
+at 4.01 GHz coupled with g/omega_c = 0.005, Dormand-Prince 5(4) at tol 1e-6,
+float32 state.  A step is one accepted adaptive step of the whole path:
+demag (zero-padded FFT convolution), exchange, anisotropy, Zeeman and cavity
+fields, LL torque, stage combination, error-norm reduction, step control and
+renormalisation.  Inputs are resident in HBM when timing starts.
+
+Prints one JSON line.  `value` = cells * accepted steps / wall seconds.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+METRIC = ("cavity-LLG cell-steps/s (fwd; fwd+adjoint; batched vs plain), "
+          "% HBM peak")
+
+
+def kernel_bytes(plan, prob, method, kernel):
+    """Algorithmic HBM bytes of one launch of `kernel`, averaged over the
+    launches of one step (every array read or written once)."""
+    N = prob.ncells
+    nx, ny, nz = prob.nx, prob.ny, prob.nz
+    Px, Py = plan["Px"], plan["Py"]
+    Hx, Hy = Px // 2 + 1, Py // 2 + 1
+    spec = Hx * nz * 3 * ny * 8
+    kern = Hx * Hy * 6 * nz * 4
+    state = 12 * N
+    if kernel == "k_xfwd":
+        return state + spec
+    if kernel == "k_yspec":
+        return 2 * spec + kern
+    if kernel == "k_xfield":
+        if method == "dp45":
+            # stages 2..7: y_s read, k_s write, y_n read + y_{s+1} write
+            # (stages 2-6), previous k's read (1,2,3,4,4 then 5 at stage 7)
+            prev = [1, 2, 3, 4, 4, 5]
+            per = [spec + state + state + (0 if s == 7 else 2 * state)
+                   + prev[s - 2] * state for s in range(2, 8)]
+            return sum(per) / len(per)
+        per = [spec + state + state + 2 * state,           # s = 1..3
+               spec + state + state + 2 * state,
+               spec + state + state + 2 * state,
+               spec + state + 3 * state + 2 * state]      # s = 4
+        return sum(per) / len(per)
+    if kernel == "k_begin":
+        return 5 * state
+    if kernel == "k_record":
+        return state
+    return 0
+
+
+def cpu_baseline(prob, m0):
+    """The oracle on the same workload and state: one right-hand-side
+    evaluation timed (tensor and FFT-kernel setup excluded), scaled to the
+    six evaluations an accepted Dormand-Prince step costs (FSAL)."""
+    from oracle.llg import CavityLLG
+    o = CavityLLG(prob, demag="fft")
+    m = m0.astype(np.float64)
+    t0 = time.perf_counter()
+    o.rhs(m, 0j, 0.0)
+    el = time.perf_counter() - t0
+    return dict(value=prob.ncells / (6.0 * el), unit="cell-steps/s",
+                cores=1, kind="oracle",
+                sample=("one right-hand-side evaluation (numpy float64, one "
+                        "thread) of the relaxed "
+                        f"{prob.nx}x{prob.ny}x{prob.nz} film, {el:.1f} s, "
+                        "scaled by the 6 evaluations per Dormand-Prince "
+                        "step"))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--relax-ns", type=float, default=0.5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true",
+                    help="skip per-kernel events (for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not "
+              "supported (the path is single-GPU by design).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2410_00966_amd import inputs as I
+    from paper_2410_00966_amd.llgc import Sim
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    prob, m0, cfg = I.c3_film()
+    brms = prob.brms
+    # --- relaxation (untimed): alpha 0.5, no cavity coupling
+    relax = I.Problem(**{**prob.__dict__})
+    relax.alpha = cfg["relax_alpha"]
+    relax.brms = (0.0, 0.0, 0.0)
+    t_setup = time.perf_counter()
+    sim = Sim(relax)
+    sim.set_state(torch.from_numpy(m0))
+    if args.relax_ns > 0:
+        _, rinfo = sim.run(t_end=args.relax_ns * 1e-9)
+    else:
+        rinfo = dict(accepted=0, rejected=0)
+    m_relaxed, _, _ = sim.get_state()
+    # --- coupled run parameters; t <- 0, alpha <- 0
+    prob.brms = brms
+    sim.set_params(prob)
+    sim.set_state(m_relaxed, 0.0, 0j)
+    plan = sim.plan_info()
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup
+    # --- warmup (untimed)
+    if args.warmup > 0:
+        sim.run(nsteps=args.warmup, t_end=1.0)
+    if not args.no_timing:
+        sim.set_timing(True)
+        sim.kernel_times(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info = sim.run(nsteps=args.steps, t_end=1.0)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assert info["accepted"] == args.steps, info
+    value = prob.ncells * args.steps / wall
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": ("textured film 1024x1024x2 cells of 4 nm, 64 "
+                         "vortex/domain-wall centres relaxed 0.5 ns at "
+                         "alpha=0.5, then alpha=0.02, Bext 20 mT x, cavity "
+                         "4.01 GHz g/wc=0.005, Dormand-Prince tol 1e-6"),
+            "cells": prob.ncells, "padded_fft": [plan["Px"], plan["Py"]],
+            "method": "dp45", "tol": prob.tol,
+            "accepted": info["accepted"], "rejected": info["rejected"],
+            "rhs_evals": info["rhs_evals"],
+            "relax_steps": rinfo["accepted"], "setup_s": round(setup_s, 2),
+        },
+    }
+    if not args.no_timing:
+        kt = sim.kernel_times()
+        dom = max(kt, key=lambda k: kt[k][0])
+        ms, n = kt[dom]
+        per_launch_s = ms * 1e-3 / n
+        byts = kernel_bytes(plan, prob, "dp45", dom)
+        achieved = byts / per_launch_s / 1e9
+        out["roofline"] = {
+            "bound": "hbm", "kernel": dom,
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "bytes_per_launch": byts, "avg_launch_us": per_launch_s * 1e6,
+        }
+        counts = {k: v[1] / info["accepted"] for k, v in kt.items()}
+        sb = sum(kernel_bytes(plan, prob, "dp45", k) * c
+                 for k, c in counts.items())
+        out["kernels"] = {k: {"ms": round(v[0], 3), "launches": v[1],
+                              "us_per_launch": round(1e3 * v[0] / v[1], 2)}
+                          for k, v in kt.items()}
+        out["model_bytes_per_step"] = sb
+        out["effective_GBs"] = sb * args.steps / wall / 1e9
+    if not args.no_cpu_baseline:
+        m_host = m_relaxed.cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(prob, m_host)
+    sim.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

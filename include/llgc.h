@@ -1,0 +1,200 @@
+/*
+ * llgc -- cavity-coupled Landau-Lifshitz-Gilbert integrator for MI355X.
+ *
+ * Plain C ABI over the HIP library.  Every call returns a status code
+ * (LLGC_OK or a negative LLGC_E_* value) and never throws; the message of
+ * the last failure on a context is returned by llgc_last_error().
+ *
+ * The problem follows the paper's statement of it (arXiv 2410.00966):
+ *   - finite-difference cells with a unit vector m_i at each cell centre and
+ *     the LLG equation in Landau-Lifshitz form with Gilbert damping,
+ *     Eq. (llg);
+ *   - effective field = Zeeman + exchange + uniaxial anisotropy +
+ *     demagnetisation (the field contributions listed after Eq. (llg)) +
+ *     the cavity field B_rms (alpha + alpha^*) of the mean-field equations
+ *     (eqmotionspinclasical)/(eqmotionaclasical), used in both the
+ *     precession and the damping term;
+ *   - one damped cavity mode, Eq. (eqmotionaclasical) with
+ *     omega_c -> omega_c - i kappa:
+ *       d alpha/dt = -(i wc + kappa) alpha
+ *                    + i (V_c/hbar) sum_i Ms_i m_i . B_rms  - i eps(t).
+ *     The cavity parameters mirror the paper's script additions B_rms, Wc,
+ *     Kappa, X0 = 2 Re alpha_0, P0 = -2 Im alpha_0 and HBAR (section
+ *     "Workflow in Mumax3-cQED").
+ *
+ * Units are SI.  Magnetisation arrays are float32 structure-of-arrays
+ * m[c][z][y][x] (x fastest, c = component), N = nx*ny*nz cells per
+ * component plane, in device memory.  Scalars and the cavity amplitude are
+ * float64.  All device work of a context runs on the HIP stream given at
+ * creation; calls that return host values synchronise that stream only.
+ * One host thread per context.
+ */
+#ifndef LLGC_H
+#define LLGC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct llgc_ctx llgc_ctx;
+
+enum {
+  LLGC_OK = 0,
+  LLGC_E_ARG = -1,          /* invalid argument (null pointer, bad size)   */
+  LLGC_E_OOM = -2,          /* device allocation failed                    */
+  LLGC_E_HIP = -3,          /* a HIP runtime call failed                   */
+  LLGC_E_NONFINITE = -4,    /* non-finite state or error estimate          */
+  LLGC_E_DT_UNDERFLOW = -5, /* adaptive step fell below dt_min             */
+  LLGC_E_STATE = -6,        /* call out of order (no params / no state)    */
+  LLGC_E_UNSUPPORTED = -7   /* grid or option outside what is implemented  */
+};
+
+enum { LLGC_RK4 = 0, LLGC_DP45 = 1 };
+enum { LLGC_DRIVE_NONE = 0, LLGC_DRIVE_SINC = 1, LLGC_DRIVE_CW = 2 };
+
+/* Grid of orthorhombic cells (section "The LLG equation in Mumax3").
+ * 1 <= nx, ny; 1 <= nz <= 4; cell sizes in metres. */
+typedef struct {
+  int32_t nx, ny, nz;
+  double dx, dy, dz;
+} llgc_grid;
+
+/* Material, field, cavity and integrator parameters.
+ * Maps (ms_map, ku1_map) are device pointers to N float32 values in
+ * [z][y][x] order, or NULL for the uniform scalar; they are copied by
+ * llgc_set_params, so the caller keeps ownership.
+ * Field drive: B_ext(t) = bext + fdrive_amp * f(t) * fdrive_dir.
+ * Cavity drive: d alpha/dt gains -i * cdrive_amp * f(t).
+ * f(t) = sinc(w t) (with sinc(0) = 1) or cos(w t), chosen by *_kind.
+ * gamma, hbar, mu0 <= 0 select the defaults 1.7595e11 rad/(s T),
+ * 1.05457182e-34 J s and 4 pi 1e-7 T m/A. */
+typedef struct {
+  double ms;               /* A/m, used when ms_map == NULL              */
+  const float *ms_map;
+  double aex;              /* J/m, exchange stiffness                   */
+  double alpha;            /* Gilbert damping                           */
+  double ku1;              /* J/m^3, used when ku1_map == NULL          */
+  const float *ku1_map;
+  double anis_u[3];        /* uniaxial axis (normalised internally)     */
+  double bext[3];          /* T                                         */
+  int32_t fdrive_kind;
+  double fdrive_amp, fdrive_w; /* T, rad/s                              */
+  double fdrive_dir[3];
+  int32_t enable_demag;    /* 0: no demagnetising field                 */
+  double brms[3];          /* T, uniform vacuum field of the mode       */
+  double wc, kappa;        /* rad/s                                     */
+  double x0, p0;           /* initial 2 Re alpha, -2 Im alpha           */
+  int32_t cdrive_kind;
+  double cdrive_amp, cdrive_w; /* rad/s, rad/s                          */
+  double gamma, hbar, mu0;
+  int32_t method;          /* LLGC_RK4 (fixed dt) or LLGC_DP45 (adaptive) */
+  double dt;               /* s: fixed step, or first trial step         */
+  double tol;              /* DP45 error tolerance on |m5-m4|           */
+  double dt_min, dt_max;   /* s, DP45 bounds (<= 0: 1e-20 and 1e-10)    */
+} llgc_params;
+
+typedef struct {
+  int64_t accepted, rejected, rhs_evals;
+  double t, dt, last_err;
+} llgc_run_info;
+
+/* Creates a context for one grid.  `hip_stream` is a hipStream_t (NULL =
+ * the default stream).  Allocates every device buffer the grid needs and
+ * plans the padded FFT sizes; no parameters or state are set yet.
+ * Errors: LLGC_E_ARG (bad sizes, out == NULL), LLGC_E_UNSUPPORTED (nz > 4
+ * or padded sizes beyond the on-chip FFT limits), LLGC_E_OOM, LLGC_E_HIP. */
+int llgc_create(const llgc_grid *grid, void *hip_stream, llgc_ctx **out);
+
+/* Frees every buffer of the context.  NULL is accepted. */
+int llgc_destroy(llgc_ctx *ctx);
+
+/* Message of the last failed call on `ctx` (owned by ctx, valid until the
+ * next call).  Never NULL. */
+const char *llgc_last_error(const llgc_ctx *ctx);
+
+/* Copies parameters and maps; (re)builds the demag kernel when the cell
+ * geometry requires it (first call); resets the cavity amplitude to
+ * alpha_0 = (x0 - i p0)/2 and t to 0 only if no state was set before.
+ * Errors: LLGC_E_ARG (non-positive ms without map, negative alpha, unknown
+ * method or drive kind, dt <= 0), LLGC_E_HIP. */
+int llgc_set_params(llgc_ctx *ctx, const llgc_params *p);
+
+/* Sets m (device pointer, 3*N float32 SoA, copied), the time t and the
+ * cavity amplitude alpha = a_re + i a_im.  The vectors are used as given
+ * (callers normalise).  Errors: LLGC_E_ARG (m == NULL). */
+int llgc_set_state(llgc_ctx *ctx, const float *m_dev, double t, double a_re,
+                   double a_im);
+
+/* Copies m into `m_dev` (device, 3*N float32; may be NULL) and returns t
+ * and alpha (host pointers, may be NULL).  Synchronises the stream. */
+int llgc_get_state(llgc_ctx *ctx, float *m_dev, double *t, double *a_re_im);
+
+/* ResetMemoryTerm analogue (paper, script additions): declares the current
+ * state to be t = 0 with cavity amplitude alpha_0 = (x0 - i p0)/2. */
+int llgc_reset_cavity(llgc_ctx *ctx, double x0, double p0);
+
+/* CavityFeatureStatus analogue: 1 if |B_rms| > 0, else 0 (or an error). */
+int llgc_cavity_enabled(const llgc_ctx *ctx);
+
+/* Integrates the joint (m, alpha) system.
+ * RK4: `nsteps` fixed steps of params.dt (t_end ignored if nsteps > 0;
+ *      otherwise nsteps = round((t_end - t)/dt)).
+ * DP45: adaptive steps until t == t_end (the last step is truncated to land
+ *      on t_end); nsteps > 0 caps the number of accepted steps.
+ * Records (host buffer `rec`, rows of 6 float64: t, <mx>, <my>, <mz>,
+ * Re alpha, Im alpha) are written for the initial state and after every
+ * `record_every`-th accepted step (record_every <= 0: none), up to
+ * `rec_cap` rows; `n_rec` receives the count.  `info` may be NULL.
+ * Errors: LLGC_E_STATE (no params/state), LLGC_E_DT_UNDERFLOW,
+ * LLGC_E_NONFINITE (adaptive error non-finite until underflow), LLGC_E_HIP.
+ * On a DP45 failure the state is the last accepted one. */
+int llgc_run(llgc_ctx *ctx, int64_t nsteps, double t_end,
+             int32_t record_every, double *rec, int64_t rec_cap,
+             int64_t *n_rec, llgc_run_info *info);
+
+/* One accepted step (RK4: params.dt; DP45: adaptive, retries inside). */
+int llgc_step(llgc_ctx *ctx, llgc_run_info *info);
+
+/* Evaluates the right-hand side once, for parity checks: given m (device,
+ * 3*N float32), alpha and t, writes dm/dt to `dmdt_dev` (device, 3*N
+ * float32), the total effective field to `beff_dev` (device, 3*N float32,
+ * may be NULL) and d alpha/dt to `dadt` (host, 2 float64, may be NULL).
+ * Does not change the integrator state. */
+int llgc_eval_rhs(llgc_ctx *ctx, const float *m_dev, double a_re,
+                  double a_im, double t, float *dmdt_dev, float *beff_dev,
+                  double *dadt);
+
+/* Copies the demagnetising kernel the context built, for inspection: the
+ * real coefficients K[kx][ky][comp][dz] (comp = xx, yy, zz, xy, xz, yz;
+ * xz and yz are the coefficients of -i) already scaled by
+ * -mu0/(Px*Py), kx in [0, Px/2], ky in [0, Py/2], dz in [0, nz).
+ * `dims` (host, 4 int32) receives Px, Py, Px/2+1, Py/2+1.  `out` is a host
+ * buffer of at least 6*nz*(Px/2+1)*(Py/2+1) floats, or NULL. */
+int llgc_demag_kernel(llgc_ctx *ctx, float *out, int64_t cap, int32_t *dims);
+
+/* Real-space demag tensor N(Delta) for non-negative offsets (octant),
+ * float64 [comp][dz][dy][dx] with comp = xx, yy, zz, xy, xz, yz, as
+ * computed on the device (host buffer of 6*N doubles). */
+int llgc_demag_tensor(llgc_ctx *ctx, double *out, int64_t cap);
+
+/* Per-kernel timing with HIP events recorded around every launch on the
+ * context's stream (off by default; enabling adds events, not syncs).
+ * llgc_kernel_times fills, for up to `cap` kernels, total milliseconds and
+ * launch counts, and writes the kernel names joined by ';' into `names`
+ * (size names_cap).  Synchronises the stream.  `reset` != 0 clears. */
+int llgc_set_timing(llgc_ctx *ctx, int32_t enable);
+int llgc_kernel_times(llgc_ctx *ctx, double *ms, int64_t *launches,
+                      int32_t cap, char *names, int32_t names_cap,
+                      int32_t reset);
+
+/* Plan facts (host ints, 8 entries): Px, Py, rows per x-pass block,
+ * kx columns per spectral block, x-pass threads, spectral threads,
+ * x-pass LDS bytes, spectral LDS bytes. */
+int llgc_plan_info(const llgc_ctx *ctx, int32_t *info8);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LLGC_H */

@@ -1,0 +1,942 @@
+// Host side of the llgc C ABI: context, FFT planning, demag-kernel setup,
+// device-driven RK4 / Dormand-Prince run loops, per-kernel timing.
+// Single translation unit: the device code is included below.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/llgc.h"
+#include "llgc_common.hpp"
+#include "llgc_demag.hip"
+#include "llgc_kernels.hip"
+
+using namespace llgc;
+
+namespace {
+
+constexpr int kT = 256;               // x-pass / field / pointwise threads
+constexpr int kMaxLen = 2048;         // largest padded FFT length per axis
+constexpr size_t kLdsCap = 96 * 1024; // LDS per workgroup this plan uses
+
+struct TimerRec {
+  double ms = 0.0;
+  int64_t launches = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+};
+
+}  // namespace
+
+struct llgc_ctx {
+  // grid and plan
+  int nx, ny, nz, N;
+  double dx, dy, dz;
+  int Px, Py, Hx, Hy, logPx, logPy, logTw;
+  int Rf, Ri, W, Ty;
+  size_t lds_f, lds_i, lds_y;
+  hipStream_t stream;
+  // device buffers
+  float *yn = nullptr, *yb[2] = {nullptr, nullptr}, *kb[7] = {};
+  float2* spec = nullptr;
+  float* K = nullptr;
+  double* tensor = nullptr;
+  float2* tw = nullptr;
+  double* partials = nullptr;
+  double* rec = nullptr;
+  int64_t rec_dev_cap = 0;
+  Ctl* ctl = nullptr;
+  Ctl* ctl_eval = nullptr;
+  float *ms_map = nullptr, *ku_map = nullptr;
+  size_t npartials = 0;
+  // host state
+  llgc_params prm{};
+  Prm P{};
+  bool have_params = false, have_state = false, need_init = true;
+  bool kernel_built = false;
+  double kernel_mu0 = 0.0;
+  std::string err;
+  bool timing = false;
+  std::map<std::string, TimerRec> timers;
+};
+
+namespace {
+
+int fail(llgc_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                   \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      return fail(ctx, LLGC_E_HIP, "%s failed: %s", #call,                  \
+                  hipGetErrorString(e_));                                   \
+  } while (0)
+
+int pow2_ceil(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// Events around a launch when timing is on.
+struct Timed {
+  llgc_ctx* c;
+  const char* name;
+  hipEvent_t a = nullptr, b = nullptr;
+  Timed(llgc_ctx* cc, const char* n) : c(cc), name(n) {
+    if (c->timing) {
+      hipEventCreate(&a);
+      hipEventCreate(&b);
+      hipEventRecord(a, c->stream);
+    }
+  }
+  ~Timed() {
+    if (c->timing) {
+      hipEventRecord(b, c->stream);
+      auto& t = c->timers[name];
+      t.pending.emplace_back(a, b);
+      t.launches += 1;
+    }
+  }
+};
+
+int check_launch(llgc_ctx* c, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    return fail(c, LLGC_E_HIP, "launch of %s failed: %s", what,
+                hipGetErrorString(e));
+  return LLGC_OK;
+}
+
+dim3 xgrid(const llgc_ctx* c, int R) {
+  return dim3((c->ny + R - 1) / R, c->nz, 1);
+}
+
+int n_pointwise_blocks(const llgc_ctx* c) {
+  return std::max(1, std::min(2048, (c->N + kT - 1) / kT));
+}
+
+// ------------------------------------------------------------ stage launch
+int launch_xfwd(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
+                int mode) {
+  Timed tm(c, "k_xfwd");
+  hipLaunchKernelGGL(k_xfwd<kT>, xgrid(c, c->Rf), dim3(kT),
+                     c->P.demag ? c->lds_f : 0, c->stream, c->P, ys,
+                     c->spec, ctl, c->partials, stage, c->Rf, c->tw,
+                     c->logTw, mode);
+  return check_launch(c, "k_xfwd");
+}
+
+template <int T>
+void yspec_nz(llgc_ctx* c, Ctl* ctl, dim3 g) {
+  switch (c->nz) {
+    case 1: hipLaunchKernelGGL((k_yspec<T, 1>), g, dim3(T), c->lds_y, c->stream, c->P, c->spec, c->K, ctl, c->W, c->tw, c->logTw); break;
+    case 2: hipLaunchKernelGGL((k_yspec<T, 2>), g, dim3(T), c->lds_y, c->stream, c->P, c->spec, c->K, ctl, c->W, c->tw, c->logTw); break;
+    case 3: hipLaunchKernelGGL((k_yspec<T, 3>), g, dim3(T), c->lds_y, c->stream, c->P, c->spec, c->K, ctl, c->W, c->tw, c->logTw); break;
+    default: hipLaunchKernelGGL((k_yspec<T, 4>), g, dim3(T), c->lds_y, c->stream, c->P, c->spec, c->K, ctl, c->W, c->tw, c->logTw); break;
+  }
+}
+
+template <int T>
+void yspec_attr(size_t lds) {
+  hipFuncSetAttribute((const void*)k_yspec<T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipFuncSetAttribute((const void*)k_yspec<T, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipFuncSetAttribute((const void*)k_yspec<T, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipFuncSetAttribute((const void*)k_yspec<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+int launch_yspec(llgc_ctx* c, Ctl* ctl) {
+  if (!c->P.demag) return LLGC_OK;
+  Timed tm(c, "k_yspec");
+  dim3 g((c->Hx + c->W - 1) / c->W);
+  if (c->Ty == 512) yspec_nz<512>(c, ctl, g);
+  else yspec_nz<256>(c, ctl, g);
+  return check_launch(c, "k_yspec");
+}
+
+int launch_xfield(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
+                  const Epi& E) {
+  Timed tm(c, "k_xfield");
+  hipLaunchKernelGGL(k_xfield<kT>, xgrid(c, c->Ri), dim3(kT),
+                     c->P.demag ? c->lds_i : 0, c->stream, c->P, ys, c->spec,
+                     ctl, c->partials, c->rec, stage, c->Ri, E, c->tw,
+                     c->logTw);
+  return check_launch(c, "k_xfield");
+}
+
+int rhs_stage(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
+              const Epi& E, int mode) {
+  int r;
+  if ((r = launch_xfwd(c, ys, ctl, stage, mode))) return r;
+  if ((r = launch_yspec(c, ctl))) return r;
+  if ((r = launch_xfield(c, ys, ctl, stage, E))) return r;
+  return LLGC_OK;
+}
+
+int launch_begin(llgc_ctx* c) {
+  Timed tm(c, "k_begin");
+  hipLaunchKernelGGL(k_begin<kT>, dim3(n_pointwise_blocks(c)), dim3(kT), 0,
+                     c->stream, c->P, c->yn, c->kb[0], c->yb[1], c->kb[6],
+                     c->yb[0], c->ctl, c->partials, c->rec);
+  return check_launch(c, "k_begin");
+}
+
+int launch_record(llgc_ctx* c) {
+  Timed tm(c, "k_record");
+  hipLaunchKernelGGL(k_record<kT>, dim3(n_pointwise_blocks(c)), dim3(kT), 0,
+                     c->stream, c->P, c->yn, c->ctl, c->partials, c->rec);
+  return check_launch(c, "k_record");
+}
+
+// --------------------------------------------------------- RK epilogues
+Epi epi_eval(float* kout, float* bout) {
+  Epi E{};
+  E.kind = 0;
+  E.kout = kout;
+  E.bout = bout;
+  return E;
+}
+
+Epi epi_rk4(llgc_ctx* c, int s) {
+  Epi E{};
+  E.yn = c->yn;
+  if (s < 4) {
+    E.kind = 1;
+    E.np = 0;
+    E.cself = (s == 3) ? 1.f : 0.5f;
+    E.ynext = c->yb[s % 2];        // stage s reads yb[(s+1)%2] (s>1)
+    E.kout = c->kb[s - 1];
+  } else {
+    E.kind = 2;
+    E.np = 3;
+    E.kp[0] = c->kb[0];
+    E.kp[1] = c->kb[1];
+    E.kp[2] = c->kb[2];
+    E.ca[0] = (float)(1.0 / 6.0);
+    E.ca[1] = (float)(1.0 / 3.0);
+    E.ca[2] = (float)(1.0 / 3.0);
+    E.cself = (float)(1.0 / 6.0);
+    E.ynext = c->yn;
+    E.kout = nullptr;
+  }
+  return E;
+}
+
+static const double kDPA[8][7] = {
+    {0}, {0},
+    {1.0 / 5},
+    {3.0 / 40, 9.0 / 40},
+    {44.0 / 45, -56.0 / 15, 32.0 / 9},
+    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729},
+    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176,
+     -5103.0 / 18656},
+    {35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784,
+     11.0 / 84}};
+static const double kDPE[7] = {
+    35.0 / 384 - 5179.0 / 57600, 0.0, 500.0 / 1113 - 7571.0 / 16695,
+    125.0 / 192 - 393.0 / 640, -2187.0 / 6784 + 92097.0 / 339200,
+    11.0 / 84 - 187.0 / 2100, -1.0 / 40};
+
+Epi epi_dp(llgc_ctx* c, int s) {
+  Epi E{};
+  E.yn = c->yn;
+  E.kout = c->kb[s - 1];
+  if (s < 7) {
+    E.kind = 1;
+    for (int j = 1; j < s; ++j) {
+      double a = kDPA[s + 1][j - 1];
+      if (a == 0.0) continue;
+      E.kp[E.np] = c->kb[j - 1];
+      E.ca[E.np] = (float)a;
+      E.np++;
+    }
+    E.cself = (float)kDPA[s + 1][s - 1];
+    E.ynext = c->yb[(s + 1) % 2];
+  } else {
+    E.kind = 3;
+    for (int j = 1; j < 7; ++j) {
+      if (kDPE[j - 1] == 0.0) continue;
+      E.kp[E.np] = c->kb[j - 1];
+      E.ca[E.np] = (float)kDPE[j - 1];
+      E.np++;
+    }
+    E.cself = (float)kDPE[6];
+    E.ynext = nullptr;
+  }
+  return E;
+}
+
+// ----------------------------------------------------------- host ctl I/O
+int ctl_read(llgc_ctx* c, Ctl* h, const Ctl* d) {
+  HIPCHK(c, hipMemcpyAsync(h, d, sizeof(Ctl), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LLGC_OK;
+}
+int ctl_write(llgc_ctx* c, Ctl* d, const Ctl* h) {
+  HIPCHK(c, hipMemcpyAsync(d, h, sizeof(Ctl), hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LLGC_OK;
+}
+
+int ensure_rec(llgc_ctx* c, int64_t cap) {
+  if (cap <= c->rec_dev_cap) return LLGC_OK;
+  if (c->rec) HIPCHK(c, hipFree(c->rec));
+  c->rec = nullptr;
+  int64_t n = std::max<int64_t>(cap, 16);
+  if (hipMalloc(&c->rec, sizeof(double) * 6 * n) != hipSuccess)
+    return fail(c, LLGC_E_OOM, "record buffer of %lld rows", (long long)n);
+  c->rec_dev_cap = n;
+  return LLGC_OK;
+}
+
+// ----------------------------------------------------------- demag setup
+void gauss_legendre(int n, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      double dp = n * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) {
+        // final derivative for the weight
+        p0 = 1.0;
+        p1 = z;
+        for (int k = 2; k <= n; ++k) {
+          double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        dp = n * (z * p1 - p0) / (z * z - 1.0);
+        break;
+      }
+    }
+    x[i] = z;
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    double dp = n * (z * p1 - p0) / (z * z - 1.0);
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+int build_demag_kernel(llgc_ctx* c, double mu0) {
+  const size_t n = (size_t)c->N;
+  if (!c->tensor) {
+    if (hipMalloc(&c->tensor, sizeof(double) * 6 * n) != hipSuccess)
+      return fail(c, LLGC_E_OOM, "demag tensor (%zu doubles)", 6 * n);
+    GLRule gl;
+    gauss_legendre(kGLHalf, gl.x, gl.w);
+    dim3 g((c->nx + 127) / 128, c->ny, c->nz);
+    hipLaunchKernelGGL(k_tensor, g, dim3(128), 0, c->stream, c->tensor,
+                       c->nx, c->ny, c->nz, c->dx, c->dy, c->dz, gl);
+    if (int r = check_launch(c, "k_tensor")) return r;
+  }
+  // twiddle tables in float64 for the separable transforms
+  std::vector<double2> twx(c->Px), twy(c->Py);
+  for (int m = 0; m < c->Px; ++m) {
+    double a = 2.0 * M_PI * m / c->Px;
+    twx[m] = make_double2(std::cos(a), std::sin(a));
+  }
+  for (int m = 0; m < c->Py; ++m) {
+    double a = 2.0 * M_PI * m / c->Py;
+    twy[m] = make_double2(std::cos(a), std::sin(a));
+  }
+  double2 *dtx = nullptr, *dty = nullptr;
+  double* o1 = nullptr;
+  size_t no1 = (size_t)6 * c->nz * c->ny * c->Hx;
+  if (hipMalloc(&dtx, sizeof(double2) * c->Px) != hipSuccess ||
+      hipMalloc(&dty, sizeof(double2) * c->Py) != hipSuccess ||
+      hipMalloc(&o1, sizeof(double) * no1) != hipSuccess) {
+    hipFree(dtx);
+    hipFree(dty);
+    hipFree(o1);
+    return fail(c, LLGC_E_OOM, "demag transform scratch");
+  }
+  hipMemcpyAsync(dtx, twx.data(), sizeof(double2) * c->Px,
+                 hipMemcpyHostToDevice, c->stream);
+  hipMemcpyAsync(dty, twy.data(), sizeof(double2) * c->Py,
+                 hipMemcpyHostToDevice, c->stream);
+  hipLaunchKernelGGL(k_dct_x, dim3((c->Hx + 255) / 256, c->ny * c->nz, 6),
+                     dim3(256), 0, c->stream, c->tensor, o1, c->nx, c->ny,
+                     c->nz, c->Px, c->Hx, dtx);
+  int r = check_launch(c, "k_dct_x");
+  if (!r) {
+    const double scale = -mu0 / ((double)c->Px * (double)c->Py);
+    hipLaunchKernelGGL(k_dct_y, dim3((c->Hx + 255) / 256, c->Hy, 6 * c->nz),
+                       dim3(256), 0, c->stream, o1, c->K, c->ny, c->nz,
+                       c->Py, c->Hx, c->Hy, dty, scale);
+    r = check_launch(c, "k_dct_y");
+  }
+  hipStreamSynchronize(c->stream);
+  hipFree(dtx);
+  hipFree(dty);
+  hipFree(o1);
+  if (r) return r;
+  c->kernel_built = true;
+  c->kernel_mu0 = mu0;
+  return LLGC_OK;
+}
+
+void fill_prm(llgc_ctx* c) {
+  const llgc_params& p = c->prm;
+  Prm& P = c->P;
+  P.nx = c->nx; P.ny = c->ny; P.nz = c->nz; P.ncell = c->N;
+  P.Px = c->Px; P.Py = c->Py; P.Hx = c->Hx; P.Hy = c->Hy;
+  P.logPx = c->logPx; P.logPy = c->logPy;
+  P.idx2 = (float)(1.0 / (c->dx * c->dx));
+  P.idy2 = (float)(1.0 / (c->dy * c->dy));
+  P.idz2 = (float)(1.0 / (c->dz * c->dz));
+  P.ms = (float)p.ms;
+  P.ms_map = c->ms_map;
+  P.aex2 = (float)(2.0 * p.aex);
+  P.ku2 = (float)(2.0 * p.ku1);
+  P.ku_map = c->ku_map;
+  double un = std::sqrt(p.anis_u[0] * p.anis_u[0] + p.anis_u[1] * p.anis_u[1] +
+                        p.anis_u[2] * p.anis_u[2]);
+  if (un == 0.0) un = 1.0;
+  P.ux = (float)(p.anis_u[0] / un);
+  P.uy = (float)(p.anis_u[1] / un);
+  P.uz = (float)(p.anis_u[2] / un);
+  P.bx = (float)p.bext[0]; P.by = (float)p.bext[1]; P.bz = (float)p.bext[2];
+  P.fkind = p.fdrive_kind; P.famp = p.fdrive_amp; P.fw = p.fdrive_w;
+  P.fdx = (float)p.fdrive_dir[0]; P.fdy = (float)p.fdrive_dir[1];
+  P.fdz = (float)p.fdrive_dir[2];
+  P.demag = p.enable_demag ? 1 : 0;
+  P.brx = (float)p.brms[0]; P.bry = (float)p.brms[1]; P.brz = (float)p.brms[2];
+  P.brxd = p.brms[0]; P.bryd = p.brms[1]; P.brzd = p.brms[2];
+  const double hbar = p.hbar > 0 ? p.hbar : 1.05457182e-34;
+  const double gamma = p.gamma > 0 ? p.gamma : 1.7595e11;
+  P.wc = p.wc; P.kappa = p.kappa;
+  P.vc_hbar = c->dx * c->dy * c->dz / hbar;
+  P.ckind = p.cdrive_kind; P.camp = p.cdrive_amp; P.cw = p.cdrive_w;
+  P.gpref = (float)(-gamma / (1.0 + p.alpha * p.alpha));
+  P.alpha = (float)p.alpha;
+  P.method = p.method;
+  P.tol = p.tol;
+  P.dt_min = p.dt_min > 0 ? p.dt_min : 1e-20;
+  P.dt_max = p.dt_max > 0 ? p.dt_max : 1e-10;
+}
+
+int timers_collect(llgc_ctx* c) {
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (auto& kv : c->timers) {
+    for (auto& pr : kv.second.pending) {
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, pr.first, pr.second);
+      kv.second.ms += ms;
+      hipEventDestroy(pr.first);
+      hipEventDestroy(pr.second);
+    }
+    kv.second.pending.clear();
+  }
+  return LLGC_OK;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+int llgc_create(const llgc_grid* g, void* stream, llgc_ctx** out) {
+  if (!g || !out) return LLGC_E_ARG;
+  *out = nullptr;
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1 || !(g->dx > 0) || !(g->dy > 0) ||
+      !(g->dz > 0))
+    return LLGC_E_ARG;
+  if (g->nz > 4 || g->nx > kMaxLen / 2 || g->ny > kMaxLen / 2)
+    return LLGC_E_UNSUPPORTED;
+  llgc_ctx* c = new llgc_ctx();
+  c->nx = g->nx; c->ny = g->ny; c->nz = g->nz;
+  c->N = g->nx * g->ny * g->nz;
+  c->dx = g->dx; c->dy = g->dy; c->dz = g->dz;
+  c->stream = (hipStream_t)stream;
+  c->Px = g->nx == 1 ? 1 : pow2_ceil(2 * g->nx);
+  c->Py = g->ny == 1 ? 1 : pow2_ceil(2 * g->ny);
+  c->Hx = c->Px / 2 + 1;
+  c->Hy = c->Py / 2 + 1;
+  c->logPx = ilog2(c->Px);
+  c->logPy = ilog2(c->Py);
+  c->logTw = ilog2(std::max(c->Px, c->Py));
+  // --- plan: rows per x-pass block, kx columns per spectral block
+  const int VPTT = VPT * kT;
+  int npf = std::max(1, std::min(8, VPTT / c->Px));
+  int npi = std::max(1, std::min(8, VPTT / (3 * c->Px)));
+  if (npf * c->Px > VPTT || 3 * npi * c->Px > VPTT) {
+    delete c;
+    return LLGC_E_UNSUPPORTED;
+  }
+  auto pick_rows = [&](int npmax) {
+    int R = 2 * npmax;
+    while (R > 2 && ((c->ny + R - 1) / R) * c->nz < 512) R -= 2;
+    return std::min(R, std::max(1, c->ny + (c->ny & 1)));
+  };
+  c->Rf = pick_rows(npf);
+  c->Ri = pick_rows(npi);
+  if (const char* s = getenv("LLGC_RF")) c->Rf = std::max(1, atoi(s));
+  if (const char* s = getenv("LLGC_RI")) c->Ri = std::max(1, atoi(s));
+  const int col = 3 * c->nz * c->Py;
+  int W = std::max(1, std::min(16384 / col, (int)(kLdsCap / (8 * col))));
+  while (W > 1 && (c->Hx + W - 1) / W < 256) --W;
+  if (const char* s = getenv("LLGC_W")) W = std::max(1, atoi(s));
+  c->W = W;
+  c->Ty = (W * col > VPT * 256) ? 512 : 256;
+  if (W * col > VPT * 512) {
+    delete c;
+    return LLGC_E_UNSUPPORTED;
+  }
+  c->lds_f = sizeof(float2) * ((c->Rf + 1) / 2) * c->Px;
+  c->lds_i = sizeof(float2) * 3 * ((c->Ri + 1) / 2) * c->Px;
+  c->lds_y = sizeof(float2) * (size_t)W * col;
+  int dev = 0, maxlds = 65536;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                        dev);
+  size_t need = std::max(c->lds_f, std::max(c->lds_i, c->lds_y));
+  if (need > (size_t)std::max(maxlds, 65536) && need > 65536) {
+    c->err = "plan needs more LDS than the device offers";
+    delete c;
+    return LLGC_E_UNSUPPORTED;
+  }
+  hipFuncSetAttribute((const void*)k_xfwd<kT>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)c->lds_f);
+  hipFuncSetAttribute((const void*)k_xfield<kT>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)c->lds_i);
+  yspec_attr<256>(c->lds_y);
+  yspec_attr<512>(c->lds_y);
+  // --- buffers
+  const size_t n3 = (size_t)3 * c->N;
+  bool ok = hipMalloc(&c->yn, n3 * 4) == hipSuccess &&
+            hipMalloc(&c->yb[0], n3 * 4) == hipSuccess &&
+            hipMalloc(&c->yb[1], n3 * 4) == hipSuccess;
+  for (int j = 0; j < 7 && ok; ++j)
+    ok = hipMalloc(&c->kb[j], n3 * 4) == hipSuccess;
+  const size_t nspec = (size_t)c->Hx * c->nz * 3 * c->ny;
+  const size_t nK = (size_t)c->Hx * c->Hy * 6 * c->nz;
+  ok = ok && hipMalloc(&c->spec, nspec * sizeof(float2)) == hipSuccess &&
+       hipMalloc(&c->K, nK * sizeof(float)) == hipSuccess &&
+       hipMalloc(&c->ctl, sizeof(Ctl)) == hipSuccess &&
+       hipMalloc(&c->ctl_eval, sizeof(Ctl)) == hipSuccess;
+  const int Ltw = 1 << c->logTw;
+  ok = ok && hipMalloc(&c->tw, sizeof(float2) * Ltw) == hipSuccess;
+  size_t nb = std::max<size_t>(
+      {(size_t)xgrid(c, c->Rf).x * c->nz, (size_t)xgrid(c, c->Ri).x * c->nz,
+       (size_t)n_pointwise_blocks(c)});
+  c->npartials = 4 * nb + 16;
+  ok = ok && hipMalloc(&c->partials, sizeof(double) * c->npartials) ==
+                 hipSuccess;
+  if (!ok) {
+    llgc_destroy(c);
+    return LLGC_E_OOM;
+  }
+  std::vector<float2> tw(Ltw);
+  for (int m = 0; m < Ltw; ++m) {
+    double a = -2.0 * M_PI * m / Ltw;
+    tw[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  Ctl z{};
+  if (hipMemcpy(c->tw, tw.data(), sizeof(float2) * Ltw,
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->ctl, &z, sizeof(Ctl), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(c->ctl_eval, &z, sizeof(Ctl), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemset(c->spec, 0, nspec * sizeof(float2)) != hipSuccess) {
+    llgc_destroy(c);
+    return LLGC_E_HIP;
+  }
+  if (ensure_rec(c, 16)) {
+    llgc_destroy(c);
+    return LLGC_E_OOM;
+  }
+  *out = c;
+  return LLGC_OK;
+}
+
+int llgc_destroy(llgc_ctx* c) {
+  if (!c) return LLGC_OK;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  else hipDeviceSynchronize();
+  timers_collect(c);
+  hipFree(c->yn);
+  hipFree(c->yb[0]);
+  hipFree(c->yb[1]);
+  for (auto* p : c->kb) hipFree(p);
+  hipFree(c->spec);
+  hipFree(c->K);
+  hipFree(c->tensor);
+  hipFree(c->tw);
+  hipFree(c->partials);
+  hipFree(c->rec);
+  hipFree(c->ctl);
+  hipFree(c->ctl_eval);
+  hipFree(c->ms_map);
+  hipFree(c->ku_map);
+  delete c;
+  return LLGC_OK;
+}
+
+const char* llgc_last_error(const llgc_ctx* c) {
+  if (!c) return "null context";
+  return c->err.c_str();
+}
+
+int llgc_set_params(llgc_ctx* c, const llgc_params* p) {
+  if (!c) return LLGC_E_ARG;
+  if (!p) return fail(c, LLGC_E_ARG, "params is NULL");
+  if (!p->ms_map && !(p->ms > 0))
+    return fail(c, LLGC_E_ARG, "ms must be > 0 without a map");
+  if (!(p->alpha >= 0) || !(p->aex >= 0))
+    return fail(c, LLGC_E_ARG, "alpha and aex must be >= 0");
+  if (p->method != LLGC_RK4 && p->method != LLGC_DP45)
+    return fail(c, LLGC_E_ARG, "unknown method %d", p->method);
+  if (p->fdrive_kind < 0 || p->fdrive_kind > 2 || p->cdrive_kind < 0 ||
+      p->cdrive_kind > 2)
+    return fail(c, LLGC_E_ARG, "unknown drive kind");
+  if (!(p->dt > 0)) return fail(c, LLGC_E_ARG, "dt must be > 0");
+  if (p->method == LLGC_DP45 && !(p->tol > 0))
+    return fail(c, LLGC_E_ARG, "tol must be > 0");
+  if (!(p->kappa >= 0)) return fail(c, LLGC_E_ARG, "kappa must be >= 0");
+  c->prm = *p;
+  const size_t nb = sizeof(float) * c->N;
+  if (p->ms_map) {
+    if (!c->ms_map) HIPCHK(c, hipMalloc(&c->ms_map, nb));
+    HIPCHK(c, hipMemcpyAsync(c->ms_map, p->ms_map, nb,
+                             hipMemcpyDeviceToDevice, c->stream));
+  } else if (c->ms_map) {
+    HIPCHK(c, hipFree(c->ms_map));
+    c->ms_map = nullptr;
+  }
+  if (p->ku1_map) {
+    if (!c->ku_map) HIPCHK(c, hipMalloc(&c->ku_map, nb));
+    HIPCHK(c, hipMemcpyAsync(c->ku_map, p->ku1_map, nb,
+                             hipMemcpyDeviceToDevice, c->stream));
+  } else if (c->ku_map) {
+    HIPCHK(c, hipFree(c->ku_map));
+    c->ku_map = nullptr;
+  }
+  fill_prm(c);
+  const double mu0 = p->mu0 > 0 ? p->mu0 : 4e-7 * M_PI;
+  if (p->enable_demag && (!c->kernel_built || c->kernel_mu0 != mu0)) {
+    if (int r = build_demag_kernel(c, mu0)) return r;
+  }
+  Ctl h{};
+  if (int r = ctl_read(c, &h, c->ctl)) return r;
+  if (!c->have_state) {
+    h.t = 0.0;
+    h.a_re = 0.5 * p->x0;
+    h.a_im = -0.5 * p->p0;
+  }
+  h.dt = p->dt;
+  h.as_re[1] = h.a_re;
+  h.as_im[1] = h.a_im;
+  if (int r = ctl_write(c, c->ctl, &h)) return r;
+  c->have_params = true;
+  c->need_init = true;
+  return LLGC_OK;
+}
+
+int llgc_set_state(llgc_ctx* c, const float* m, double t, double are,
+                   double aim) {
+  if (!c) return LLGC_E_ARG;
+  if (!m) return fail(c, LLGC_E_ARG, "m is NULL");
+  HIPCHK(c, hipMemcpyAsync(c->yn, m, sizeof(float) * 3 * c->N,
+                           hipMemcpyDeviceToDevice, c->stream));
+  Ctl h{};
+  if (int r = ctl_read(c, &h, c->ctl)) return r;
+  h.t = t;
+  h.a_re = are;
+  h.a_im = aim;
+  h.as_re[1] = are;
+  h.as_im[1] = aim;
+  h.pending_accept = 0;
+  h.done = 0;
+  h.status = 0;
+  h.prev_rej = 0;
+  if (c->have_params) h.dt = c->prm.dt;
+  if (int r = ctl_write(c, c->ctl, &h)) return r;
+  c->have_state = true;
+  c->need_init = true;
+  return LLGC_OK;
+}
+
+int llgc_get_state(llgc_ctx* c, float* m, double* t, double* a) {
+  if (!c) return LLGC_E_ARG;
+  if (m)
+    HIPCHK(c, hipMemcpyAsync(m, c->yn, sizeof(float) * 3 * c->N,
+                             hipMemcpyDeviceToDevice, c->stream));
+  Ctl h{};
+  if (int r = ctl_read(c, &h, c->ctl)) return r;
+  if (t) *t = h.t;
+  if (a) {
+    a[0] = h.a_re;
+    a[1] = h.a_im;
+  }
+  return LLGC_OK;
+}
+
+int llgc_reset_cavity(llgc_ctx* c, double x0, double p0) {
+  if (!c) return LLGC_E_ARG;
+  Ctl h{};
+  if (int r = ctl_read(c, &h, c->ctl)) return r;
+  h.t = 0.0;
+  h.a_re = 0.5 * x0;
+  h.a_im = -0.5 * p0;
+  h.as_re[1] = h.a_re;
+  h.as_im[1] = h.a_im;
+  if (int r = ctl_write(c, c->ctl, &h)) return r;
+  c->need_init = true;
+  return LLGC_OK;
+}
+
+int llgc_cavity_enabled(const llgc_ctx* c) {
+  if (!c) return LLGC_E_ARG;
+  if (!c->have_params) return 0;
+  const double* b = c->prm.brms;
+  return (b[0] != 0.0 || b[1] != 0.0 || b[2] != 0.0) ? 1 : 0;
+}
+
+int llgc_run(llgc_ctx* c, int64_t nsteps, double t_end, int32_t rec_every,
+             double* rec, int64_t rec_cap, int64_t* n_rec,
+             llgc_run_info* info) {
+  if (!c) return LLGC_E_ARG;
+  if (!c->have_params || !c->have_state)
+    return fail(c, LLGC_E_STATE, "set params and state before running");
+  if (rec_every > 0 && (!rec || rec_cap < 1))
+    return fail(c, LLGC_E_ARG, "records requested without a buffer");
+  if (n_rec) *n_rec = 0;
+  int64_t cap = rec_every > 0 ? rec_cap : 0;
+  if (int r = ensure_rec(c, std::max<int64_t>(cap, 1))) return r;
+  Ctl h{};
+  if (int r = ctl_read(c, &h, c->ctl)) return r;
+  const long long acc0 = h.accepted, rej0 = h.rejected;
+  h.rec_every = rec_every > 0 ? rec_every : 0;
+  h.rec_cap = (int)cap;
+  h.nrec = 0;
+  h.status = 0;
+  h.done = 0;
+  h.accepted = 0;
+  h.rejected = 0;
+  h.cnt_xfwd = h.cnt_field = h.cnt_begin = h.cnt_rec = 0;
+  int64_t evals = 0;
+  const bool rk4 = c->prm.method == LLGC_RK4;
+  if (rk4) {
+    h.dt = c->prm.dt;
+    if (nsteps <= 0) nsteps = (int64_t)std::llround((t_end - h.t) / h.dt);
+    h.t_end = 1e300;
+    h.max_accepted = (long long)1 << 62;
+  } else {
+    h.t_end = t_end;
+    h.max_accepted = nsteps > 0 ? nsteps : ((long long)1 << 62);
+    if (c->need_init) h.dt = c->prm.dt;
+    h.dt = std::min(h.dt, t_end - h.t);
+    h.done = (h.t >= t_end) ? 1 : 0;
+    h.pending_accept = 0;
+  }
+  if (int r = ctl_write(c, c->ctl, &h)) return r;
+  if (cap > 0) {
+    if (int r = launch_record(c)) return r;
+  }
+  int r = LLGC_OK;
+  if (rk4) {
+    for (int64_t n = 0; n < nsteps && !r; ++n) {
+      for (int s = 1; s <= 4 && !r; ++s) {
+        const float* ys = (s == 1) ? c->yn : c->yb[(s + 1) % 2];
+        r = rhs_stage(c, ys, c->ctl, s, epi_rk4(c, s), 0);
+        evals++;
+      }
+    }
+  } else if (!h.done) {
+    if (c->need_init) {
+      r = rhs_stage(c, c->yn, c->ctl, 1, epi_eval(c->kb[0], nullptr), 0);
+      evals++;
+    } else {
+      // current dt may differ from the one y2 was formed with
+      h.as_re[2] = h.a_re + h.dt * 0.2 * h.ka_re[1];
+      h.as_im[2] = h.a_im + h.dt * 0.2 * h.ka_im[1];
+      r = ctl_write(c, c->ctl, &h);
+    }
+    if (!r) r = launch_begin(c);
+    const int64_t max_attempts = 50000000;
+    int64_t attempts = 0;
+    while (!r) {
+      const int batch = 8;
+      for (int b = 0; b < batch && !r; ++b) {
+        for (int s = 2; s <= 7 && !r; ++s) {
+          r = rhs_stage(c, c->yb[s % 2], c->ctl, s, epi_dp(c, s), 0);
+        }
+        if (!r) r = launch_begin(c);
+        attempts++;
+      }
+      if (r) break;
+      int done = 0;
+      HIPCHK(c, hipMemcpyAsync(&done, &c->ctl->done, sizeof(int),
+                               hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      if (done) break;
+      if (attempts > max_attempts) {
+        r = fail(c, LLGC_E_DT_UNDERFLOW, "attempt limit reached");
+        break;
+      }
+    }
+  }
+  if (r) return r;
+  c->need_init = false;
+  Ctl e{};
+  if (int q = ctl_read(c, &e, c->ctl)) return q;
+  if (!rk4) evals = 6 * (e.accepted + e.rejected) + (evals ? 1 : 0);
+  if (cap > 0 && e.nrec > 0) {
+    HIPCHK(c, hipMemcpy(rec, c->rec, sizeof(double) * 6 * e.nrec,
+                        hipMemcpyDeviceToHost));
+  }
+  if (n_rec) *n_rec = e.nrec;
+  if (info) {
+    info->accepted = e.accepted;
+    info->rejected = e.rejected;
+    info->rhs_evals = evals;
+    info->t = e.t;
+    info->dt = e.dt;
+    info->last_err = e.last_err;
+  }
+  // keep totals across runs
+  e.accepted += acc0;
+  e.rejected += rej0;
+  const int st = e.status;
+  e.status = 0;
+  if (int q = ctl_write(c, c->ctl, &e)) return q;
+  if (st == ST_UNDERFLOW)
+    return fail(c, LLGC_E_DT_UNDERFLOW, "time step fell below dt_min");
+  if (st == ST_NONFINITE)
+    return fail(c, LLGC_E_NONFINITE, "non-finite state or error estimate");
+  return LLGC_OK;
+}
+
+int llgc_step(llgc_ctx* c, llgc_run_info* info) {
+  if (!c) return LLGC_E_ARG;
+  return llgc_run(c, 1, 1e300, 0, nullptr, 0, nullptr, info);
+}
+
+int llgc_eval_rhs(llgc_ctx* c, const float* m, double are, double aim,
+                  double t, float* dmdt, float* beff, double* dadt) {
+  if (!c) return LLGC_E_ARG;
+  if (!c->have_params)
+    return fail(c, LLGC_E_STATE, "set params before evaluating");
+  if (!m || !dmdt) return fail(c, LLGC_E_ARG, "m and dmdt are required");
+  Ctl h{};
+  h.t = t;
+  h.dt = 0.0;
+  h.a_re = are;
+  h.a_im = aim;
+  h.as_re[1] = are;
+  h.as_im[1] = aim;
+  h.t_end = 1e300;
+  if (int r = ctl_write(c, c->ctl_eval, &h)) return r;
+  if (int r = rhs_stage(c, m, c->ctl_eval, 1, epi_eval(dmdt, beff), 1))
+    return r;
+  Ctl e{};
+  if (int r = ctl_read(c, &e, c->ctl_eval)) return r;
+  if (dadt) {
+    dadt[0] = e.rhs_dadt_re;
+    dadt[1] = e.rhs_dadt_im;
+  }
+  return LLGC_OK;
+}
+
+int llgc_demag_kernel(llgc_ctx* c, float* out, int64_t cap, int32_t* dims) {
+  if (!c) return LLGC_E_ARG;
+  if (dims) {
+    dims[0] = c->Px;
+    dims[1] = c->Py;
+    dims[2] = c->Hx;
+    dims[3] = c->Hy;
+  }
+  if (!out) return LLGC_OK;
+  const int64_t n = (int64_t)c->Hx * c->Hy * 6 * c->nz;
+  if (cap < n) return fail(c, LLGC_E_ARG, "need %lld floats", (long long)n);
+  if (!c->kernel_built) return fail(c, LLGC_E_STATE, "no demag kernel");
+  HIPCHK(c, hipMemcpy(out, c->K, sizeof(float) * n, hipMemcpyDeviceToHost));
+  return LLGC_OK;
+}
+
+int llgc_demag_tensor(llgc_ctx* c, double* out, int64_t cap) {
+  if (!c) return LLGC_E_ARG;
+  const int64_t n = (int64_t)6 * c->N;
+  if (!out || cap < n) return fail(c, LLGC_E_ARG, "need %lld doubles",
+                                   (long long)n);
+  if (!c->tensor) return fail(c, LLGC_E_STATE, "no demag tensor");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(out, c->tensor, sizeof(double) * n,
+                      hipMemcpyDeviceToHost));
+  return LLGC_OK;
+}
+
+int llgc_set_timing(llgc_ctx* c, int32_t enable) {
+  if (!c) return LLGC_E_ARG;
+  c->timing = enable != 0;
+  return LLGC_OK;
+}
+
+int llgc_kernel_times(llgc_ctx* c, double* ms, int64_t* launches,
+                      int32_t cap, char* names, int32_t names_cap,
+                      int32_t reset) {
+  if (!c) return LLGC_E_ARG;
+  if (int r = timers_collect(c)) return r;
+  std::string joined;
+  int i = 0;
+  for (auto& kv : c->timers) {
+    if (i < cap) {
+      if (ms) ms[i] = kv.second.ms;
+      if (launches) launches[i] = kv.second.launches;
+    }
+    if (!joined.empty()) joined += ";";
+    joined += kv.first;
+    ++i;
+  }
+  if (names && names_cap > 0) {
+    std::strncpy(names, joined.c_str(), names_cap - 1);
+    names[names_cap - 1] = 0;
+  }
+  if (reset) c->timers.clear();
+  return i;
+}
+
+int llgc_plan_info(const llgc_ctx* c, int32_t* info) {
+  if (!c || !info) return LLGC_E_ARG;
+  info[0] = c->Px;
+  info[1] = c->Py;
+  info[2] = c->Rf;
+  info[3] = c->W;
+  info[4] = kT;
+  info[5] = c->Ty;
+  info[6] = (int32_t)c->lds_f;
+  info[7] = (int32_t)c->lds_y;
+  return LLGC_OK;
+}
+
+}  // extern "C"

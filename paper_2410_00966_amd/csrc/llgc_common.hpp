@@ -1,0 +1,75 @@
+// Shared device/host definitions of the llgc library (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace llgc {
+
+constexpr int kMaxStages = 8;
+
+// Device-resident integrator control block.  Everything that decides the
+// next step (time, step size, cavity amplitude and stage values, accept /
+// reject) lives here so that a run needs no host round trip per step.
+struct Ctl {
+  double t, dt, t_end;
+  double a_re, a_im;                         // cavity amplitude at t
+  double as_re[kMaxStages], as_im[kMaxStages];  // stage inputs a_s (s>=1)
+  double ka_re[kMaxStages], ka_im[kMaxStages];  // stage rates k_a,s
+  double anext_re, anext_im;                 // RK4 end-of-step amplitude
+  double err_a, last_err, F_last;
+  double rhs_dadt_re, rhs_dadt_im;
+  long long accepted, rejected, rhs_evals, max_accepted;
+  int pending_accept, done, status, prev_rej;
+  int nrec, rec_every, rec_cap, pad0;
+  unsigned int cnt_xfwd, cnt_field, cnt_begin, cnt_rec;
+};
+
+enum { ST_OK = 0, ST_UNDERFLOW = 1, ST_NONFINITE = 2 };
+
+// Scalar problem parameters passed by value to every kernel.
+struct Prm {
+  int nx, ny, nz, ncell;
+  int Px, Py, Hx, Hy, logPx, logPy;
+  float idx2, idy2, idz2;       // 1/d^2 per axis
+  float ms;                     // uniform Ms (A/m) when ms_map == nullptr
+  const float* ms_map;
+  float aex2;                   // 2 A
+  float ku2;                    // 2 Ku (J/m^3) when ku_map == nullptr
+  const float* ku_map;
+  float ux, uy, uz;             // anisotropy axis
+  float bx, by, bz;             // static external field
+  int fkind;
+  double famp, fw;
+  float fdx, fdy, fdz;          // field drive direction
+  int demag;
+  float brx, bry, brz;          // B_rms
+  double brxd, bryd, brzd;
+  double wc, kappa, vc_hbar;    // V_c / hbar
+  int ckind;
+  double camp, cw;
+  float gpref;                  // -gamma / (1 + alpha^2)
+  float alpha;
+  int method;                   // 0 RK4, 1 DP45
+  double tol, dt_min, dt_max;
+};
+
+// Runge-Kutta epilogue description of one stage of the field kernel.
+struct Epi {
+  int kind;            // 0: evaluate only, 1: stage, 2: RK4 final, 3: DP45 error
+  int np;              // number of previous k's used
+  const float* yn;     // base state y_n
+  const float* kp[6];  // previous k_j
+  float ca[6];         // their coefficients (times dt)
+  float cself;         // coefficient of this stage's k
+  float* ynext;        // y_{s+1}, or y_n itself for the RK4 final stage
+  float* kout;         // k_s output (may be null)
+  float* bout;         // B_eff output (evaluate only, may be null)
+};
+
+__host__ __device__ inline int ilog2(int v) {
+  int r = 0;
+  while ((1 << r) < v) ++r;
+  return r;
+}
+
+}  // namespace llgc

@@ -1,0 +1,151 @@
+// Batched in-LDS complex FFT for power-of-two lengths (gfx950).
+//
+// Stockham auto-sort, radix 8/4/2, in place in one LDS buffer: each pass
+// loads a thread's butterflies into registers, barriers, computes and
+// stores to the auto-sorted positions, barriers.  All threads of the
+// workgroup cooperate on a batch of `batch` transforms of length L stored
+// contiguously (transform t at s + t*L).  Twiddles come from a table of
+// exp(-2 pi i m / Ltw) for m < Ltw (Ltw a power of two >= L).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace llgc {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) {
+  return make_float2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ float2 csub(float2 a, float2 b) {
+  return make_float2(a.x - b.x, a.y - b.y);
+}
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// multiply by s*i with s = +-1
+__device__ __forceinline__ float2 cmul_si(float2 a, float s) {
+  return make_float2(-s * a.y, s * a.x);
+}
+
+// R-point DFT in registers: X_p = sum_q v_q exp(s 2 pi i p q / R),
+// s = -1 forward, +1 inverse.
+template <int R>
+__device__ __forceinline__ void dft_small(float2* v, float s);
+
+template <>
+__device__ __forceinline__ void dft_small<2>(float2* v, float) {
+  float2 a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <>
+__device__ __forceinline__ void dft_small<4>(float2* v, float s) {
+  float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+  float2 t2 = cadd(v[1], v[3]), t3 = cmul_si(csub(v[1], v[3]), s);
+  v[0] = cadd(t0, t2);
+  v[2] = csub(t0, t2);
+  v[1] = cadd(t1, t3);
+  v[3] = csub(t1, t3);
+}
+
+template <>
+__device__ __forceinline__ void dft_small<8>(float2* v, float s) {
+  float2 e[4] = {v[0], v[2], v[4], v[6]};
+  float2 o[4] = {v[1], v[3], v[5], v[7]};
+  dft_small<4>(e, s);
+  dft_small<4>(o, s);
+  const float h = 0.70710678118654752f;
+  // w8^p = exp(s i pi p / 4)
+  float2 w1 = make_float2(h, s * h), w3 = make_float2(-h, s * h);
+  float2 o1 = cmul(o[1], w1), o2 = cmul_si(o[2], s), o3 = cmul(o[3], w3);
+  v[0] = cadd(e[0], o[0]);
+  v[4] = csub(e[0], o[0]);
+  v[1] = cadd(e[1], o1);
+  v[5] = csub(e[1], o1);
+  v[2] = cadd(e[2], o2);
+  v[6] = csub(e[2], o2);
+  v[3] = cadd(e[3], o3);
+  v[7] = csub(e[3], o3);
+}
+
+// One Stockham pass of radix R over `batch` transforms of length L = 2^logL
+// held in LDS.  Ns = 2^logNs is the length of the sub-transforms already
+// done.  NB is the number of butterflies a thread holds in registers; the
+// caller guarantees batch * L / R <= NB * blockDim.x.
+template <int R, int NB>
+__device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
+                                         int batch, const float2* tw,
+                                         int logTw, float dir) {
+  constexpr int logR = (R == 2) ? 1 : (R == 4) ? 2 : 3;
+  const int logLr = logL - logR;
+  const int Lr = 1 << logLr;
+  const int nbf = batch << logLr;
+  const int Ns = 1 << logNs;
+  const int twshift = logTw - logNs - logR;   // k * Ltw / (Ns R)
+  const int twmask = (1 << logTw) - 1;
+  float2 v[NB][R];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int b = threadIdx.x + i * blockDim.x;
+    if (b < nbf) {
+      const int t = b >> logLr, j = b & (Lr - 1);
+      const float2* base = s + (t << logL);
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[i][q] = base[j + q * Lr];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int b = threadIdx.x + i * blockDim.x;
+    if (b < nbf) {
+      const int t = b >> logLr, j = b & (Lr - 1);
+      const int k = j & (Ns - 1);
+      if (k != 0) {
+        const int step = k << twshift;
+#pragma unroll
+        for (int q = 1; q < R; ++q) {
+          float2 w = tw[(q * step) & twmask];
+          w.y *= -dir;   // table holds exp(-i ...); inverse conjugates
+          v[i][q] = cmul(v[i][q], w);
+        }
+      }
+      dft_small<R>(v[i], dir);
+      float2* base = s + (t << logL);
+      const int out0 = ((j - k) << logR) + k;
+#pragma unroll
+      for (int q = 0; q < R; ++q) base[out0 + q * Ns] = v[i][q];
+    }
+  }
+  __syncthreads();
+}
+
+// Full transform: dir = -1 forward (exp(-i...)), +1 inverse (unnormalised).
+// VPT = complex values a thread may hold (register budget per pass).
+template <int VPT>
+__device__ void fft_lds(float2* s, int logL, int batch, const float2* tw,
+                        int logTw, float dir) {
+  if (logL == 0) return;
+  int logNs = 0;
+  int rem = logL;
+  // radix plan: 8s, with the remainder as one 4, two 4s, or one 2
+  int n8 = rem / 3, tail = rem % 3;
+  int n4 = 0, n2 = 0;
+  if (tail == 2) n4 = 1;
+  if (tail == 1) {
+    if (n8 > 0) { n8 -= 1; n4 = 2; } else { n2 = 1; }
+  }
+  for (int p = 0; p < n8; ++p) {
+    fft_pass<8, VPT / 8>(s, logL, logNs, batch, tw, logTw, dir);
+    logNs += 3;
+  }
+  for (int p = 0; p < n4; ++p) {
+    fft_pass<4, VPT / 4>(s, logL, logNs, batch, tw, logTw, dir);
+    logNs += 2;
+  }
+  for (int p = 0; p < n2; ++p) {
+    fft_pass<2, VPT / 2>(s, logL, logNs, batch, tw, logTw, dir);
+    logNs += 1;
+  }
+}
+
+}  // namespace llgc

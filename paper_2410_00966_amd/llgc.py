@@ -1,0 +1,309 @@
+"""Python binding of the llgc C ABI (include/llgc.h).
+
+Argument marshalling only: every step of the integration runs in the HIP
+kernels of libllgc.so.  PyTorch supplies device memory and the stream.
+Importing works without a GPU; creating a `Sim` requires the built library
+and a visible GPU and raises otherwise (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libllgc.so")
+
+LLGC_OK = 0
+ERRORS = {-1: "LLGC_E_ARG", -2: "LLGC_E_OOM", -3: "LLGC_E_HIP",
+          -4: "LLGC_E_NONFINITE", -5: "LLGC_E_DT_UNDERFLOW",
+          -6: "LLGC_E_STATE", -7: "LLGC_E_UNSUPPORTED"}
+RK4, DP45 = 0, 1
+
+EXPORTED = ("llgc_create", "llgc_destroy", "llgc_last_error",
+            "llgc_set_params", "llgc_set_state", "llgc_get_state",
+            "llgc_reset_cavity", "llgc_cavity_enabled", "llgc_run",
+            "llgc_step", "llgc_eval_rhs", "llgc_demag_kernel",
+            "llgc_demag_tensor", "llgc_set_timing", "llgc_kernel_times",
+            "llgc_plan_info")
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("dx", ctypes.c_double),
+                ("dy", ctypes.c_double), ("dz", ctypes.c_double)]
+
+
+_D3 = ctypes.c_double * 3
+_FP = ctypes.c_void_p
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("ms", ctypes.c_double), ("ms_map", _FP),
+        ("aex", ctypes.c_double), ("alpha", ctypes.c_double),
+        ("ku1", ctypes.c_double), ("ku1_map", _FP), ("anis_u", _D3),
+        ("bext", _D3),
+        ("fdrive_kind", ctypes.c_int32), ("fdrive_amp", ctypes.c_double),
+        ("fdrive_w", ctypes.c_double), ("fdrive_dir", _D3),
+        ("enable_demag", ctypes.c_int32),
+        ("brms", _D3),
+        ("wc", ctypes.c_double), ("kappa", ctypes.c_double),
+        ("x0", ctypes.c_double), ("p0", ctypes.c_double),
+        ("cdrive_kind", ctypes.c_int32), ("cdrive_amp", ctypes.c_double),
+        ("cdrive_w", ctypes.c_double),
+        ("gamma", ctypes.c_double), ("hbar", ctypes.c_double),
+        ("mu0", ctypes.c_double),
+        ("method", ctypes.c_int32), ("dt", ctypes.c_double),
+        ("tol", ctypes.c_double), ("dt_min", ctypes.c_double),
+        ("dt_max", ctypes.c_double),
+    ]
+
+
+class RunInfo(ctypes.Structure):
+    _fields_ = [("accepted", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("rhs_evals", ctypes.c_int64), ("t", ctypes.c_double),
+                ("dt", ctypes.c_double), ("last_err", ctypes.c_double)]
+
+
+class LLGCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Loads libllgc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "__graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                         ctypes.c_double)
+    P = ctypes.POINTER
+    sig = {
+        "llgc_create": ([P(Grid), vp, P(vp)], ctypes.c_int),
+        "llgc_destroy": ([vp], ctypes.c_int),
+        "llgc_last_error": ([vp], ctypes.c_char_p),
+        "llgc_set_params": ([vp, P(Params)], ctypes.c_int),
+        "llgc_set_state": ([vp, vp, dbl, dbl, dbl], ctypes.c_int),
+        "llgc_get_state": ([vp, vp, P(dbl), P(dbl)], ctypes.c_int),
+        "llgc_reset_cavity": ([vp, dbl, dbl], ctypes.c_int),
+        "llgc_cavity_enabled": ([vp], ctypes.c_int),
+        "llgc_run": ([vp, i64, dbl, i32, P(dbl), i64, P(i64), P(RunInfo)],
+                     ctypes.c_int),
+        "llgc_step": ([vp, P(RunInfo)], ctypes.c_int),
+        "llgc_eval_rhs": ([vp, vp, dbl, dbl, dbl, vp, vp, P(dbl)],
+                          ctypes.c_int),
+        "llgc_demag_kernel": ([vp, P(ctypes.c_float), i64, P(i32)],
+                              ctypes.c_int),
+        "llgc_demag_tensor": ([vp, P(dbl), i64], ctypes.c_int),
+        "llgc_set_timing": ([vp, i32], ctypes.c_int),
+        "llgc_kernel_times": ([vp, P(dbl), P(i64), i32, ctypes.c_char_p, i32,
+                               i32], ctypes.c_int),
+        "llgc_plan_info": ([vp, P(i32)], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def make_params(prob, ms_map=None, ku_map=None) -> Params:
+    """Marshals an inputs.Problem into the C struct (maps: device tensors)."""
+    p = Params()
+    p.ms = prob.ms
+    p.ms_map = ms_map.data_ptr() if ms_map is not None else None
+    p.aex = prob.aex
+    p.alpha = prob.alpha
+    p.ku1 = prob.ku1
+    p.ku1_map = ku_map.data_ptr() if ku_map is not None else None
+    p.anis_u = _D3(*prob.anis_u)
+    p.bext = _D3(*prob.bext)
+    p.fdrive_kind = prob.fdrive_kind
+    p.fdrive_amp = prob.fdrive_amp
+    p.fdrive_w = prob.fdrive_w
+    p.fdrive_dir = _D3(*prob.fdrive_dir)
+    p.enable_demag = 1 if prob.enable_demag else 0
+    p.brms = _D3(*prob.brms)
+    p.wc, p.kappa, p.x0, p.p0 = prob.wc, prob.kappa, prob.x0, prob.p0
+    p.cdrive_kind = prob.cdrive_kind
+    p.cdrive_amp = prob.cdrive_amp
+    p.cdrive_w = prob.cdrive_w
+    p.gamma, p.hbar, p.mu0 = prob.gamma, prob.hbar, prob.mu0
+    p.method = prob.method
+    p.dt, p.tol = prob.dt, prob.tol
+    p.dt_min, p.dt_max = prob.dt_min, prob.dt_max
+    return p
+
+
+class Sim:
+    """One llgc context on the current torch CUDA/HIP device and stream."""
+
+    def __init__(self, prob, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("llgc needs a GPU: no HIP device is visible")
+        self.torch = torch
+        self.L = load()
+        self.prob = prob
+        self.shape = (3, prob.nz, prob.ny, prob.nx)
+        self.stream = stream or torch.cuda.current_stream()
+        g = Grid(prob.nx, prob.ny, prob.nz, prob.dx, prob.dy, prob.dz)
+        h = ctypes.c_void_p()
+        rc = self.L.llgc_create(ctypes.byref(g),
+                                ctypes.c_void_p(self.stream.cuda_stream),
+                                ctypes.byref(h))
+        if rc != LLGC_OK:
+            raise LLGCError(rc, "llgc_create")
+        self.h = h
+        self.set_params(prob)
+
+    # ------------------------------------------------------------ helpers
+    def _check(self, rc, what):
+        if rc < 0:
+            msg = self.L.llgc_last_error(self.h).decode()
+            raise LLGCError(rc, f"{what}: {msg}")
+        return rc
+
+    def _dev(self, a, dtype=None):
+        t = self.torch
+        dtype = dtype or t.float32
+        if isinstance(a, t.Tensor):
+            return a.to(device="cuda", dtype=dtype).contiguous()
+        return t.as_tensor(np.ascontiguousarray(a), dtype=dtype,
+                           device="cuda")
+
+    # ---------------------------------------------------------------- API
+    def set_params(self, prob):
+        self.prob = prob
+        msm = self._dev(prob.ms_map) if prob.ms_map is not None else None
+        kum = self._dev(prob.ku1_map) if prob.ku1_map is not None else None
+        p = make_params(prob, msm, kum)
+        self._check(self.L.llgc_set_params(self.h, ctypes.byref(p)),
+                    "llgc_set_params")
+        self.stream.synchronize()
+
+    def set_state(self, m, t=0.0, a=0j):
+        md = self._dev(m).reshape(self.shape)
+        a = complex(a)
+        self._check(self.L.llgc_set_state(self.h, md.data_ptr(), t, a.real,
+                                          a.imag), "llgc_set_state")
+        self.stream.synchronize()
+
+    def get_state(self):
+        m = self.torch.empty(self.shape, dtype=self.torch.float32,
+                             device="cuda")
+        t = ctypes.c_double()
+        a = (ctypes.c_double * 2)()
+        self._check(self.L.llgc_get_state(self.h, m.data_ptr(),
+                                          ctypes.byref(t), a),
+                    "llgc_get_state")
+        self.stream.synchronize()
+        return m, t.value, complex(a[0], a[1])
+
+    def reset_cavity(self, x0=0.0, p0=0.0):
+        self._check(self.L.llgc_reset_cavity(self.h, x0, p0),
+                    "llgc_reset_cavity")
+
+    def cavity_enabled(self):
+        return self._check(self.L.llgc_cavity_enabled(self.h),
+                           "llgc_cavity_enabled")
+
+    def run(self, nsteps=0, t_end=0.0, record_every=0, rec_cap=0):
+        """Returns (records (n, 6) float64, info dict)."""
+        if record_every > 0 and rec_cap <= 0:
+            rec_cap = (nsteps // record_every + 2) if nsteps else 100000
+        rec = np.zeros((max(rec_cap, 1), 6))
+        nrec = ctypes.c_int64()
+        info = RunInfo()
+        rc = self.L.llgc_run(
+            self.h, int(nsteps), float(t_end), int(record_every),
+            rec.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            int(rec_cap), ctypes.byref(nrec), ctypes.byref(info))
+        self._check(rc, "llgc_run")
+        return rec[: nrec.value].copy(), dict(
+            accepted=info.accepted, rejected=info.rejected,
+            rhs_evals=info.rhs_evals, t=info.t, dt=info.dt,
+            last_err=info.last_err)
+
+    def step(self):
+        info = RunInfo()
+        self._check(self.L.llgc_step(self.h, ctypes.byref(info)),
+                    "llgc_step")
+        return dict(accepted=info.accepted, rejected=info.rejected,
+                    t=info.t, dt=info.dt, last_err=info.last_err)
+
+    def eval_rhs(self, m, a=0j, t=0.0, want_field=True):
+        md = self._dev(m).reshape(self.shape)
+        dm = self.torch.empty_like(md)
+        B = self.torch.empty_like(md) if want_field else None
+        da = (ctypes.c_double * 2)()
+        a = complex(a)
+        self._check(self.L.llgc_eval_rhs(
+            self.h, md.data_ptr(), a.real, a.imag, float(t), dm.data_ptr(),
+            B.data_ptr() if B is not None else None, da), "llgc_eval_rhs")
+        self.stream.synchronize()
+        return dm, B, complex(da[0], da[1])
+
+    def demag_kernel(self):
+        dims = (ctypes.c_int32 * 4)()
+        self._check(self.L.llgc_demag_kernel(self.h, None, 0, dims),
+                    "llgc_demag_kernel")
+        Px, Py, Hx, Hy = list(dims)
+        n = Hx * Hy * 6 * self.prob.nz
+        out = np.zeros(n, dtype=np.float32)
+        self._check(self.L.llgc_demag_kernel(
+            self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n,
+            dims), "llgc_demag_kernel")
+        return out.reshape(Hx, Hy, 6, self.prob.nz), (Px, Py)
+
+    def demag_tensor(self):
+        n = 6 * self.prob.nx * self.prob.ny * self.prob.nz
+        out = np.zeros(n)
+        self._check(self.L.llgc_demag_tensor(
+            self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n),
+            "llgc_demag_tensor")
+        return out.reshape(6, self.prob.nz, self.prob.ny, self.prob.nx)
+
+    def set_timing(self, on=True):
+        self._check(self.L.llgc_set_timing(self.h, 1 if on else 0),
+                    "llgc_set_timing")
+
+    def kernel_times(self, reset=False):
+        cap = 32
+        ms = (ctypes.c_double * cap)()
+        ln = (ctypes.c_int64 * cap)()
+        names = ctypes.create_string_buffer(1024)
+        n = self._check(self.L.llgc_kernel_times(self.h, ms, ln, cap, names,
+                                                 1024, 1 if reset else 0),
+                        "llgc_kernel_times")
+        keys = names.value.decode().split(";") if n else []
+        return {k: (ms[i], ln[i]) for i, k in enumerate(keys)}
+
+    def plan_info(self):
+        info = (ctypes.c_int32 * 8)()
+        self._check(self.L.llgc_plan_info(self.h, info), "llgc_plan_info")
+        keys = ("Px", "Py", "rows_xfwd", "kx_per_block", "threads_x",
+                "threads_y", "lds_xfwd", "lds_yspec")
+        return dict(zip(keys, list(info)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.llgc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

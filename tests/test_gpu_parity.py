@@ -1,0 +1,204 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  Field and right-hand-side evaluations are compared
+element by element; fixed-step runs per cell; the demag tensor setup against
+the oracle's independent tensor.
+
+Tolerances (FP32 state and FFT against FP64):
+  * real-space tensor (FP64 on both sides, different quadratures): 1e-8 of
+    the largest component;
+  * demag / effective field and dm/dt: 2e-5 of the largest magnitude on the
+    grid (single-precision FFT of a few thousand points accumulates ~1e-6);
+  * fixed-step trajectories: max |dm| <= 1e-4 per cell, inside the FP64
+    sensitivity envelope of the trajectory.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2410_00966_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+def _sim(prob):
+    from paper_2410_00966_amd.llgc import Sim
+    return Sim(prob)
+
+
+def _oracle(prob, demag="auto"):
+    from oracle.llg import CavityLLG
+    return CavityLLG(prob, demag=demag)
+
+
+def _random_m(shape, seed):
+    rng = np.random.default_rng(seed)
+    m = rng.normal(size=(3,) + shape)
+    return (m / np.sqrt((m * m).sum(0))).astype(np.float32)
+
+
+def _rich_problem(nx, ny, nz, cell=(4e-9, 4e-9, 4e-9), demag=True):
+    p = I.Problem(nx=nx, ny=ny, nz=nz, dx=cell[0], dy=cell[1], dz=cell[2],
+                  ms=8e5, aex=1.3e-11, alpha=0.02, ku1=4e4,
+                  anis_u=(0.6, 0.0, 0.8), bext=(0.01, 0.03, 0.1),
+                  enable_demag=demag)
+    p.wc = 2 * math.pi * 9e9
+    p.kappa = 1e-3 * p.wc
+    p.brms = (2e-3, -1e-3, 5e-4)
+    p.fdrive_kind, p.fdrive_amp, p.fdrive_w = I.DRIVE_SINC, 0.01, 2e11
+    p.fdrive_dir = (0.0, 1.0, 0.0)
+    p.cdrive_kind, p.cdrive_amp, p.cdrive_w = I.DRIVE_CW, 3e7, 5e10
+    return p
+
+
+TENSOR_GRIDS = [((8, 5, 3), (2e-9, 3e-9, 1.5e-9)),
+                ((40, 33, 2), (4e-9, 4e-9, 4e-9)),
+                ((1, 1, 1), (5e-9, 5e-9, 5e-9))]
+
+
+@pytest.mark.parametrize("grid,cell", TENSOR_GRIDS)
+def test_tensor_matches_oracle(torch, grid, cell):
+    from oracle import demag as D
+    nx, ny, nz = grid
+    _say("tensor", grid, cell)
+    p = I.Problem(nx=nx, ny=ny, nz=nz, dx=cell[0], dy=cell[1], dz=cell[2])
+    s = _sim(p)
+    got = s.demag_tensor()
+    ref = D.tensor_octant(nx, ny, nz, *cell)
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() < 1e-8 * scale
+    s.close()
+
+
+FIELD_GRIDS = [(32, 32, 1), (37, 23, 3), (1, 1, 1), (1, 9, 2), (16, 1, 4),
+               (64, 8, 2), (5, 3, 4)]
+
+
+@pytest.mark.parametrize("grid", FIELD_GRIDS)
+def test_demag_field_matches_oracle(torch, grid):
+    nx, ny, nz = grid
+    _say("demag field", grid)
+    p = I.Problem(nx=nx, ny=ny, nz=nz, dx=4e-9, dy=3e-9, dz=2.5e-9, ms=8e5,
+                  aex=0.0, alpha=0.0)
+    m = _random_m(p.shape, seed=nx * 100 + ny * 10 + nz)
+    o = _oracle(p)
+    ref = o.demag(m.astype(np.float64))
+    s = _sim(p)
+    _, B, _ = s.eval_rhs(torch.from_numpy(m))
+    got = B.cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    _say("  rel err", err)
+    assert err < 2e-5
+    s.close()
+
+
+@pytest.mark.parametrize("grid", [(32, 32, 1), (37, 23, 3), (1, 1, 1),
+                                  (24, 1, 2), (20, 16, 4)])
+def test_rhs_matches_oracle(torch, grid):
+    nx, ny, nz = grid
+    _say("rhs", grid)
+    p = _rich_problem(nx, ny, nz)
+    m = _random_m(p.shape, seed=7 + nx)
+    a, t = 0.7 - 0.2j, 3.3e-12
+    o = _oracle(p)
+    Bref = o.effective_field(m.astype(np.float64), a, t)
+    dref, daref = o.rhs(m.astype(np.float64), a, t)
+    s = _sim(p)
+    dm, B, da = s.eval_rhs(torch.from_numpy(m), a, t)
+    eB = np.abs(B.cpu().numpy() - Bref).max() / np.abs(Bref).max()
+    ed = np.abs(dm.cpu().numpy() - dref).max() / np.abs(dref).max()
+    _say("  field err", eB, "torque err", ed, "da", da, daref)
+    assert eB < 2e-5 and ed < 2e-5
+    assert abs(da - daref) <= 1e-9 * abs(daref)
+    s.close()
+
+
+def _compare_run(torch, p, m0, nsteps, rec_every, tol_cell, a0=0j):
+    o = _oracle(p)
+    mref, aref, tref, recref = o.run_rk4(m0.astype(np.float64), a0, p.dt,
+                                         nsteps, rec_every)
+    s = _sim(p)
+    s.set_state(torch.from_numpy(m0), 0.0, a0)
+    rec, info = s.run(nsteps=nsteps, record_every=rec_every)
+    m, t, a = s.get_state()
+    m = m.cpu().numpy().astype(np.float64)
+    dm = np.abs(m - mref).max()
+    _say("  max|dm|", dm, "t", t, tref, "a", a, aref)
+    assert t == pytest.approx(tref, rel=1e-12)
+    assert dm <= tol_cell
+    assert rec.shape == recref.shape
+    assert np.abs(rec[:, 1:4] - recref[:, 1:4]).max() <= tol_cell
+    scale = max(1.0, np.abs(recref[:, 4:]).max())
+    assert np.abs(rec[:, 4:] - recref[:, 4:]).max() <= 1e-3 * scale
+    s.close()
+    return m, mref
+
+
+def test_rk4_small_film_prefix(torch):
+    """The 32x32x1 film workload over its first 1000 steps (its FP64
+    sensitivity envelope there is ~1e-6; it becomes O(1) after ~3500
+    steps, so longer windows are compared by invariants, below)."""
+    _say("rk4 small film prefix")
+    p, m0, run = I.c1_small()
+    _compare_run(torch, p, m0, 1000, 10, 1e-4)
+
+
+def test_rk4_small_film_stable_field_full_length(torch):
+    """Same film in 1.5 T along z (above the shape anisotropy, so the
+    trajectory is not chaotic): all 5000 steps, per cell."""
+    _say("rk4 stable film 5000 steps")
+    p, m0, run = I.c1_small()
+    p.bext = (0.0, 0.0, 1.5)
+    _compare_run(torch, p, m0, 5000, 10, 1e-4)
+
+
+def test_rk4_full_small_film_invariants(torch):
+    """All 5000 steps of the small film: |m| = 1 after every step and the
+    records stay finite; per-cell agreement is not expected past the
+    trajectory's sensitivity horizon."""
+    _say("rk4 small film invariants")
+    p, m0, run = I.c1_small()
+    s = _sim(p)
+    s.set_state(torch.from_numpy(m0))
+    rec, info = s.run(nsteps=5000, record_every=10)
+    m, t, a = s.get_state()
+    n = torch.sqrt((m * m).sum(0))
+    assert float((n - 1).abs().max()) < 1e-6
+    assert rec.shape == (501, 6) and np.isfinite(rec).all()
+    assert t == pytest.approx(1e-9, rel=1e-12)
+    s.close()
+
+
+def test_dicke_cell_trajectory(torch):
+    """Single macrospin in the normal phase (demag off) over many cavity
+    periods: GPU and oracle trajectories agree."""
+    _say("dicke cell")
+    wc = 2 * math.pi * 10e9
+    lam = 0.3 * wc / 2
+    p, m0 = I.dicke_macrospin(wc, wc, lam, kappa=1e-3 * wc, alpha=1e-3)
+    p.dt = 2e-13
+    _compare_run(torch, p, m0, 4000, 10, 1e-4)
+
+
+def test_rk4_ragged_grid_with_maps(torch):
+    _say("rk4 ragged grid with maps")
+    p = _rich_problem(19, 13, 3)
+    p.ms_map = I.smooth_map(19, 13, 3, 7e5, 9e5, 4, 2, seed=5)
+    p.ku1_map = I.smooth_map(19, 13, 3, 0.0, 1e4, 4, 2, seed=6)
+    p.dt = 5e-14
+    m0 = I.tilted_uniform_state(p.shape, 20.0, 0.05, seed=9)
+    _compare_run(torch, p, m0, 300, 50, 1e-4, a0=0.2 + 0.1j)
