@@ -166,6 +166,25 @@ int llgc_eval_rhs(llgc_ctx *ctx, const float *m_dev, double a_re,
                   double a_im, double t, float *dmdt_dev, float *beff_dev,
                   double *dadt);
 
+/* Gradient of a cavity observable by the discrete adjoint of the RK4 path.
+ * Runs `n_steps` RK4 steps of size `dt` from the current state (the state
+ * advances), with the loss
+ *     L = (1/(n1-n0+1)) sum_{n=n0..n1} |alpha_n|^2
+ * over step endpoints n (1-based, 1 <= n0 <= n1 <= n_steps), then sweeps
+ * the discrete adjoint backwards with checkpoints every `ckpt_stride` steps
+ * (0: ceil(sqrt(n_steps))), recomputing each segment once.  Outputs:
+ * `loss` (host), dL/dMs and dL/dKu per cell (device, N float32 each, may be
+ * NULL), dL/dB_rms (host, 3 float64, may be NULL) and dL/d(cavity drive
+ * amplitude) (host, may be NULL).  This is the gradient the paper's
+ * observables (photon number |alpha|^2, section "Introducing the effect of
+ * the cavity") admit with respect to the material maps and the coupling.
+ * Errors: LLGC_E_STATE (no params/state), LLGC_E_ARG (window),
+ * LLGC_E_UNSUPPORTED (padded x length < 64), LLGC_E_OOM, LLGC_E_HIP. */
+int llgc_adjoint(llgc_ctx *ctx, int64_t n_steps, double dt,
+                 int64_t ckpt_stride, int64_t n0, int64_t n1, double *loss,
+                 float *grad_ms, float *grad_ku, double *grad_brms,
+                 double *grad_cdrive_amp);
+
 /* Copies the demagnetising kernel the context built, for inspection: the
  * real coefficients K[kx][ky][comp][dz] (comp = xx, yy, zz, xy, xz, yz;
  * xz and yz are the coefficients of -i) already scaled by

@@ -17,6 +17,7 @@
 #include "llgc_common.hpp"
 #include "llgc_demag.hip"
 #include "llgc_kernels.hip"
+#include "llgc_adjoint.hip"
 
 using namespace llgc;
 
@@ -24,7 +25,7 @@ namespace {
 
 constexpr int kT = 256;               // x-pass / field / pointwise threads
 constexpr int kMaxLen = 2048;         // largest padded FFT length per axis
-constexpr size_t kLdsCap = 96 * 1024; // LDS per workgroup this plan uses
+constexpr size_t kLdsCap = 120 * 1024; // LDS per workgroup this plan uses
 
 struct TimerRec {
   double ms = 0.0;
@@ -40,6 +41,11 @@ struct llgc_ctx {
   double dx, dy, dz;
   int Px, Py, Hx, Hy, logPx, logPy, logTw;
   int Rf, Ri, W, Ty;
+  int Ww = 1;            // kx columns per wavefront-FFT spectral block
+  bool use_wy = false;   // register (wavefront) FFT along y
+  bool use_wx = false;   // register (wavefront) inverse FFT along x
+  int Rw = 2;            // rows per tile of the wavefront field kernel
+  int Rwf = 2;           // rows per tile of the wavefront forward x pass
   size_t lds_f, lds_i, lds_y;
   hipStream_t stream;
   // device buffers
@@ -122,8 +128,9 @@ int check_launch(llgc_ctx* c, const char* what) {
   return LLGC_OK;
 }
 
+// 1D tile grid: ceil(ny/R) y-tiles for each of the nz layers
 dim3 xgrid(const llgc_ctx* c, int R) {
-  return dim3((c->ny + R - 1) / R, c->nz, 1);
+  return dim3(((c->ny + R - 1) / R) * c->nz, 1, 1);
 }
 
 int n_pointwise_blocks(const llgc_ctx* c) {
@@ -131,24 +138,57 @@ int n_pointwise_blocks(const llgc_ctx* c) {
 }
 
 // ------------------------------------------------------------ stage launch
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+// rows per tile of whichever forward x pass runs
+int fwd_rows(const llgc_ctx* c) { return c->use_wx ? c->Rwf : c->Rf; }
+
 int launch_xfwd(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
                 int mode) {
   Timed tm(c, "k_xfwd");
-  hipLaunchKernelGGL(k_xfwd<kT>, xgrid(c, c->Rf), dim3(kT),
-                     c->P.demag ? c->lds_f : 0, c->stream, c->P, ys,
-                     c->spec, ctl, c->partials, stage, c->Rf, c->tw,
-                     c->logTw, mode);
+  if (c->use_wx) {
+    const int R = c->Rwf;
+    const size_t lds = c->P.demag ? sizeof(float2) * 3 * (R / 2) * c->Px : 0;
+    dim3 g = xgrid(c, R), b(64 * 3 * (R / 2));
+#define LLGC_FW_ARGS c->P, ys, c->spec, ctl, c->partials, stage, R, c->tw, \
+                     c->logTw, mode
+    switch (c->Px) {
+      case 64: hipLaunchKernelGGL((k_xfwd_w<1>), g, b, lds, c->stream, LLGC_FW_ARGS); break;
+      case 128: hipLaunchKernelGGL((k_xfwd_w<2>), g, b, lds, c->stream, LLGC_FW_ARGS); break;
+      case 256: hipLaunchKernelGGL((k_xfwd_w<4>), g, b, lds, c->stream, LLGC_FW_ARGS); break;
+      case 512: hipLaunchKernelGGL((k_xfwd_w<8>), g, b, lds, c->stream, LLGC_FW_ARGS); break;
+      case 1024: hipLaunchKernelGGL((k_xfwd_w<16>), g, b, lds, c->stream, LLGC_FW_ARGS); break;
+      default: hipLaunchKernelGGL((k_xfwd_w<32>), g, b, lds, c->stream, LLGC_FW_ARGS); break;
+    }
+#undef LLGC_FW_ARGS
+    return check_launch(c, "k_xfwd_w");
+  }
+  const bool v4 = (c->nx % 4 == 0) && aligned16(ys) &&
+                  (!c->ms_map || aligned16(c->ms_map));
+  const size_t lds = c->P.demag ? c->lds_f : 0;
+  if (v4)
+    hipLaunchKernelGGL((k_xfwd<kT, true>), xgrid(c, c->Rf), dim3(kT), lds,
+                       c->stream, c->P, ys, c->spec, ctl, c->partials, stage,
+                       c->Rf, c->tw, c->logTw, mode);
+  else
+    hipLaunchKernelGGL((k_xfwd<kT, false>), xgrid(c, c->Rf), dim3(kT), lds,
+                       c->stream, c->P, ys, c->spec, ctl, c->partials, stage,
+                       c->Rf, c->tw, c->logTw, mode);
   return check_launch(c, "k_xfwd");
 }
 
 template <int T>
-void yspec_nz(llgc_ctx* c, Ctl* ctl, dim3 g) {
+void yspec_nz(llgc_ctx* c, Ctl* ctl, dim3 g, int stage, int mode) {
+  const int nf = (int)xgrid(c, fwd_rows(c)).x;
+#define LLGC_YSPEC_ARGS c->P, c->spec, c->K, ctl, c->W, c->tw, c->logTw, \
+                        c->partials, nf, stage, mode
   switch (c->nz) {
-    case 1: hipLaunchKernelGGL((k_yspec<T, 1>), g, dim3(T), c->lds_y, c->stream, c->P, c->spec, c->K, ctl, c->W, c->tw, c->logTw); break;
-    case 2: hipLaunchKernelGGL((k_yspec<T, 2>), g, dim3(T), c->lds_y, c->stream, c->P, c->spec, c->K, ctl, c->W, c->tw, c->logTw); break;
-    case 3: hipLaunchKernelGGL((k_yspec<T, 3>), g, dim3(T), c->lds_y, c->stream, c->P, c->spec, c->K, ctl, c->W, c->tw, c->logTw); break;
-    default: hipLaunchKernelGGL((k_yspec<T, 4>), g, dim3(T), c->lds_y, c->stream, c->P, c->spec, c->K, ctl, c->W, c->tw, c->logTw); break;
+    case 1: hipLaunchKernelGGL((k_yspec<T, 1>), g, dim3(T), c->lds_y, c->stream, LLGC_YSPEC_ARGS); break;
+    case 2: hipLaunchKernelGGL((k_yspec<T, 2>), g, dim3(T), c->lds_y, c->stream, LLGC_YSPEC_ARGS); break;
+    case 3: hipLaunchKernelGGL((k_yspec<T, 3>), g, dim3(T), c->lds_y, c->stream, LLGC_YSPEC_ARGS); break;
+    default: hipLaunchKernelGGL((k_yspec<T, 4>), g, dim3(T), c->lds_y, c->stream, LLGC_YSPEC_ARGS); break;
   }
+#undef LLGC_YSPEC_ARGS
 }
 
 template <int T>
@@ -159,18 +199,74 @@ void yspec_attr(size_t lds) {
   hipFuncSetAttribute((const void*)k_yspec<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-int launch_yspec(llgc_ctx* c, Ctl* ctl) {
-  if (!c->P.demag) return LLGC_OK;
+// Spectral pass; its workgroup 0 also finishes the stage's coupling sum.
+// Without demag a one-workgroup kernel finishes the sum instead.
+template <int NZ>
+void yspec_w_nr(llgc_ctx* c, Ctl* ctl, dim3 g, dim3 b, size_t lds, int stage,
+                int mode) {
+  const int nf = (int)xgrid(c, fwd_rows(c)).x;
+#define LLGC_YW_ARGS c->P, c->spec, c->K, ctl, c->Ww, c->tw, c->logTw, \
+                     c->partials, nf, stage, mode
+  switch (c->Py) {
+    case 64: hipLaunchKernelGGL((k_yspec_w<NZ, 1>), g, b, lds, c->stream, LLGC_YW_ARGS); break;
+    case 128: hipLaunchKernelGGL((k_yspec_w<NZ, 2>), g, b, lds, c->stream, LLGC_YW_ARGS); break;
+    case 256: hipLaunchKernelGGL((k_yspec_w<NZ, 4>), g, b, lds, c->stream, LLGC_YW_ARGS); break;
+    case 512: hipLaunchKernelGGL((k_yspec_w<NZ, 8>), g, b, lds, c->stream, LLGC_YW_ARGS); break;
+    case 1024: hipLaunchKernelGGL((k_yspec_w<NZ, 16>), g, b, lds, c->stream, LLGC_YW_ARGS); break;
+    default: hipLaunchKernelGGL((k_yspec_w<NZ, 32>), g, b, lds, c->stream, LLGC_YW_ARGS); break;
+  }
+#undef LLGC_YW_ARGS
+}
+
+int launch_yspec(llgc_ctx* c, Ctl* ctl, int stage, int mode) {
+  if (c->P.demag && c->use_wy) {
+    Timed tm(c, "k_yspec");
+    const int nz3 = 3 * c->nz;
+    dim3 g((c->Hx + c->Ww - 1) / c->Ww), b(64 * c->Ww * nz3);
+    const int G = std::min(c->Py / 64, 8);
+    const size_t lds = sizeof(float2) * (size_t)c->Ww * nz3 * G * 64;
+    switch (c->nz) {
+      case 1: yspec_w_nr<1>(c, ctl, g, b, lds, stage, mode); break;
+      case 2: yspec_w_nr<2>(c, ctl, g, b, lds, stage, mode); break;
+      case 3: yspec_w_nr<3>(c, ctl, g, b, lds, stage, mode); break;
+      default: yspec_w_nr<4>(c, ctl, g, b, lds, stage, mode); break;
+    }
+    return check_launch(c, "k_yspec_w");
+  }
+  if (!c->P.demag) {
+    Timed tm(c, "k_finish_stage");
+    hipLaunchKernelGGL(k_finish_stage<kT>, dim3(1), dim3(kT), 0, c->stream,
+                       c->P, ctl, c->partials, (int)xgrid(c, fwd_rows(c)).x,
+                       stage, mode);
+    return check_launch(c, "k_finish_stage");
+  }
   Timed tm(c, "k_yspec");
   dim3 g((c->Hx + c->W - 1) / c->W);
-  if (c->Ty == 512) yspec_nz<512>(c, ctl, g);
-  else yspec_nz<256>(c, ctl, g);
+  if (c->Ty == 512) yspec_nz<512>(c, ctl, g, stage, mode);
+  else yspec_nz<256>(c, ctl, g, stage, mode);
   return check_launch(c, "k_yspec");
 }
 
 int launch_xfield(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
                   const Epi& E) {
   Timed tm(c, "k_xfield");
+  if (c->use_wx) {
+    const int R = c->Rw;
+    const size_t lds = c->P.demag ? sizeof(float) * 3 * R * c->nx : 0;
+    dim3 g = xgrid(c, R), b(64 * 3 * (R / 2));
+#define LLGC_XW_ARGS c->P, ys, c->spec, ctl, c->partials, c->rec, stage, R, \
+                     E, c->tw, c->logTw
+    switch (c->Px) {
+      case 64: hipLaunchKernelGGL((k_xfield_w<1>), g, b, lds, c->stream, LLGC_XW_ARGS); break;
+      case 128: hipLaunchKernelGGL((k_xfield_w<2>), g, b, lds, c->stream, LLGC_XW_ARGS); break;
+      case 256: hipLaunchKernelGGL((k_xfield_w<4>), g, b, lds, c->stream, LLGC_XW_ARGS); break;
+      case 512: hipLaunchKernelGGL((k_xfield_w<8>), g, b, lds, c->stream, LLGC_XW_ARGS); break;
+      case 1024: hipLaunchKernelGGL((k_xfield_w<16>), g, b, lds, c->stream, LLGC_XW_ARGS); break;
+      default: hipLaunchKernelGGL((k_xfield_w<32>), g, b, lds, c->stream, LLGC_XW_ARGS); break;
+    }
+#undef LLGC_XW_ARGS
+    return check_launch(c, "k_xfield_w");
+  }
   hipLaunchKernelGGL(k_xfield<kT>, xgrid(c, c->Ri), dim3(kT),
                      c->P.demag ? c->lds_i : 0, c->stream, c->P, ys, c->spec,
                      ctl, c->partials, c->rec, stage, c->Ri, E, c->tw,
@@ -178,12 +274,22 @@ int launch_xfield(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
   return check_launch(c, "k_xfield");
 }
 
+// rows per tile of whichever field kernel runs
+int field_rows(const llgc_ctx* c) { return c->use_wx ? c->Rw : c->Ri; }
+
 int rhs_stage(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
               const Epi& E, int mode) {
   int r;
   if ((r = launch_xfwd(c, ys, ctl, stage, mode))) return r;
-  if ((r = launch_yspec(c, ctl))) return r;
+  if ((r = launch_yspec(c, ctl, stage, mode))) return r;
   if ((r = launch_xfield(c, ys, ctl, stage, E))) return r;
+  if (E.kind == 2 || E.kind == 3) {
+    Timed tm(c, "k_finish_step");
+    hipLaunchKernelGGL(k_finish_step<kT>, dim3(1), dim3(kT), 0, c->stream,
+                       c->P, ctl, c->partials,
+                       (int)xgrid(c, field_rows(c)).x, E.kind, c->rec);
+    if ((r = check_launch(c, "k_finish_step"))) return r;
+  }
   return LLGC_OK;
 }
 
@@ -406,6 +512,7 @@ void fill_prm(llgc_ctx* c) {
   const llgc_params& p = c->prm;
   Prm& P = c->P;
   P.nx = c->nx; P.ny = c->ny; P.nz = c->nz; P.ncell = c->N;
+  P.nyp = c->ny + (c->ny & 1);
   P.Px = c->Px; P.Py = c->Py; P.Hx = c->Hx; P.Hy = c->Hy;
   P.logPx = c->logPx; P.logPy = c->logPy;
   P.idx2 = (float)(1.0 / (c->dx * c->dx));
@@ -490,28 +597,42 @@ int llgc_create(const llgc_grid* g, void* stream, llgc_ctx** out) {
     delete c;
     return LLGC_E_UNSUPPORTED;
   }
+  // rows per x-pass tile: even (rows are paired into complex transforms)
   auto pick_rows = [&](int npmax) {
     int R = 2 * npmax;
     while (R > 2 && ((c->ny + R - 1) / R) * c->nz < 512) R -= 2;
-    return std::min(R, std::max(1, c->ny + (c->ny & 1)));
+    return std::min(R, c->ny + (c->ny & 1));
   };
   c->Rf = pick_rows(npf);
   c->Ri = pick_rows(npi);
-  if (const char* s = getenv("LLGC_RF")) c->Rf = std::max(1, atoi(s));
-  if (const char* s = getenv("LLGC_RI")) c->Ri = std::max(1, atoi(s));
+  // tuning overrides (rounded up to even, capped by the register budget)
+  if (const char* s = getenv("LLGC_RF"))
+    c->Rf = std::min(2 * npf, std::max(2, (atoi(s) + 1) & ~1));
+  if (const char* s = getenv("LLGC_RI"))
+    c->Ri = std::min(2 * npi, std::max(2, (atoi(s) + 1) & ~1));
   const int col = 3 * c->nz * c->Py;
-  int W = std::max(1, std::min(16384 / col, (int)(kLdsCap / (8 * col))));
+  int W = std::max(1, std::min(16384 / col, (int)(kLdsCap / (9 * col))));
   while (W > 1 && (c->Hx + W - 1) / W < 256) --W;
-  if (const char* s = getenv("LLGC_W")) W = std::max(1, atoi(s));
+  if (const char* s = getenv("LLGC_W"))
+    W = std::max(1, std::min(atoi(s), 16384 / col));
   c->W = W;
   c->Ty = (W * col > VPT * 256) ? 512 : 256;
+  // columns of 64..2048 points: one wavefront per column, FFT in registers
+  c->use_wy = c->Py >= 64 && c->Py <= kMaxLen && !getenv("LLGC_LDS_YFFT") &&
+              (c->Py < 2048 || c->nz <= 2);  // 2048: 8 wavefronts at most
+  c->Ww = std::max(1, 6 / (3 * c->nz));
+  c->use_wx = c->Px >= 64 && c->Px <= kMaxLen && !getenv("LLGC_LDS_XFFT");
+  c->Rw = (((c->ny + 3) / 4) * c->nz >= 512) ? 4 : 2;
+  if (const char* s = getenv("LLGC_RW")) c->Rw = (atoi(s) >= 4) ? 4 : 2;
+  c->Rwf = 2;
+  if (const char* s = getenv("LLGC_RWF")) c->Rwf = (atoi(s) >= 4) ? 4 : 2;
   if (W * col > VPT * 512) {
     delete c;
     return LLGC_E_UNSUPPORTED;
   }
-  c->lds_f = sizeof(float2) * ((c->Rf + 1) / 2) * c->Px;
-  c->lds_i = sizeof(float2) * 3 * ((c->Ri + 1) / 2) * c->Px;
-  c->lds_y = sizeof(float2) * (size_t)W * col;
+  c->lds_f = sizeof(float2) * padded_len((size_t)(c->Rf / 2) * c->Px);
+  c->lds_i = sizeof(float2) * padded_len((size_t)3 * (c->Ri / 2) * c->Px);
+  c->lds_y = sizeof(float2) * padded_len((size_t)W * col);
   int dev = 0, maxlds = 65536;
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock,
@@ -522,7 +643,10 @@ int llgc_create(const llgc_grid* g, void* stream, llgc_ctx** out) {
     delete c;
     return LLGC_E_UNSUPPORTED;
   }
-  hipFuncSetAttribute((const void*)k_xfwd<kT>,
+  hipFuncSetAttribute((const void*)k_xfwd<kT, true>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)c->lds_f);
+  hipFuncSetAttribute((const void*)k_xfwd<kT, false>,
                       hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)c->lds_f);
   hipFuncSetAttribute((const void*)k_xfield<kT>,
@@ -537,7 +661,7 @@ int llgc_create(const llgc_grid* g, void* stream, llgc_ctx** out) {
             hipMalloc(&c->yb[1], n3 * 4) == hipSuccess;
   for (int j = 0; j < 7 && ok; ++j)
     ok = hipMalloc(&c->kb[j], n3 * 4) == hipSuccess;
-  const size_t nspec = (size_t)c->Hx * c->nz * 3 * c->ny;
+  const size_t nspec = (size_t)c->Hx * c->nz * 3 * (c->ny + (c->ny & 1));
   const size_t nK = (size_t)c->Hx * c->Hy * 6 * c->nz;
   ok = ok && hipMalloc(&c->spec, nspec * sizeof(float2)) == hipSuccess &&
        hipMalloc(&c->K, nK * sizeof(float)) == hipSuccess &&
@@ -545,9 +669,10 @@ int llgc_create(const llgc_grid* g, void* stream, llgc_ctx** out) {
        hipMalloc(&c->ctl_eval, sizeof(Ctl)) == hipSuccess;
   const int Ltw = 1 << c->logTw;
   ok = ok && hipMalloc(&c->tw, sizeof(float2) * Ltw) == hipSuccess;
-  size_t nb = std::max<size_t>(
-      {(size_t)xgrid(c, c->Rf).x * c->nz, (size_t)xgrid(c, c->Ri).x * c->nz,
-       (size_t)n_pointwise_blocks(c)});
+  size_t nb = std::max<size_t>({(size_t)xgrid(c, c->Rf).x,
+                                 (size_t)xgrid(c, c->Ri).x,
+                                 (size_t)xgrid(c, 2).x,
+                                 (size_t)n_pointwise_blocks(c)});
   c->npartials = 4 * nb + 16;
   ok = ok && hipMalloc(&c->partials, sizeof(double) * c->npartials) ==
                  hipSuccess;
@@ -940,3 +1065,243 @@ int llgc_plan_info(const llgc_ctx* c, int32_t* info) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- adjoint
+namespace {
+
+struct AdjBuf {
+  std::vector<void*> owned;
+  template <class T>
+  int alloc(llgc_ctx* c, T** p, size_t n) {
+    if (hipMalloc(p, sizeof(T) * std::max<size_t>(n, 1)) != hipSuccess)
+      return fail(c, LLGC_E_OOM, "adjoint buffer of %zu bytes", sizeof(T) * n);
+    owned.push_back(*p);
+    return LLGC_OK;
+  }
+  ~AdjBuf() {
+    for (void* p : owned) hipFree(p);
+  }
+};
+
+__global__ void k_d2f(const double* __restrict__ a, float* __restrict__ b,
+                      int n) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
+    b[i] = (float)a[i];
+}
+
+// One RK4 step of the forward map whose stage inputs, stage fields and
+// pre-normalisation norms are stored for the reverse sweep.
+int rk4_step_stored(llgc_ctx* c, float* Yk /*4 x 3N*/, float* Bk /*4 x 3N*/,
+                    float* nk /*N*/) {
+  const size_t n3 = (size_t)3 * c->N;
+  int r = 0;
+  HIPCHK(c, hipMemcpyAsync(Yk, c->yn, n3 * 4, hipMemcpyDeviceToDevice,
+                           c->stream));
+  for (int s = 1; s <= 4 && !r; ++s) {
+    Epi E = epi_rk4(c, s);
+    E.bout = Bk + (size_t)(s - 1) * n3;
+    if (s < 4) E.ynext = Yk + (size_t)s * n3;
+    else E.nout = nk;
+    r = rhs_stage(c, Yk + (size_t)(s - 1) * n3, c->ctl, s, E, 0);
+  }
+  return r;
+}
+
+}  // namespace
+
+extern "C" int llgc_adjoint(llgc_ctx* c, int64_t n_steps, double dt,
+                            int64_t stride, int64_t n0, int64_t n1,
+                            double* loss, float* grad_ms, float* grad_ku,
+                            double* grad_brms, double* grad_eps) {
+  if (!c) return LLGC_E_ARG;
+  if (!c->have_params || !c->have_state)
+    return fail(c, LLGC_E_STATE, "set params and state before llgc_adjoint");
+  if (n_steps < 1 || n0 < 1 || n1 < n0 || n1 > n_steps || !(dt > 0))
+    return fail(c, LLGC_E_ARG, "bad step count, window or dt");
+  if (!c->use_wx)
+    return fail(c, LLGC_E_UNSUPPORTED, "adjoint needs padded nx >= 64");
+  if (stride <= 0) stride = (int64_t)std::ceil(std::sqrt((double)n_steps));
+  const int64_t S = stride;
+  const int64_t nseg = (n_steps + S - 1) / S;
+  const size_t N = c->N, n3 = 3 * N;
+  // the adjoint runs the RK4 path with the given dt
+  const llgc_params saved = c->prm;
+  const Prm savedP = c->P;
+  c->prm.method = LLGC_RK4;
+  c->prm.dt = dt;
+  fill_prm(c);
+  struct Restore {
+    llgc_ctx* c; llgc_params p; Prm P;
+    ~Restore() { c->prm = p; c->P = P; }
+  } restore{c, saved, savedP};
+  AdjBuf B;
+  float *ck = nullptr, *SY = nullptr, *SB = nullptr, *SN = nullptr;
+  float *lam = nullptr, *hat = nullptr, *acc = nullptr, *lamK = nullptr,
+        *lamB = nullptr, *lamM = nullptr;
+  double *gms = nullptr, *gku = nullptr, *hist = nullptr, *part = nullptr;
+  AdjCtl* A = nullptr;
+  const int nlb = std::max(1, std::min(1024, (int)((N + 255) / 256)));
+  int r;
+  if ((r = B.alloc(c, &ck, n3 * nseg)) || (r = B.alloc(c, &SY, n3 * 4 * S + n3)) ||
+      (r = B.alloc(c, &SB, n3 * 4 * S)) || (r = B.alloc(c, &SN, N * S)) ||
+      (r = B.alloc(c, &lam, n3)) || (r = B.alloc(c, &hat, n3)) ||
+      (r = B.alloc(c, &acc, n3)) || (r = B.alloc(c, &lamK, n3)) ||
+      (r = B.alloc(c, &lamB, n3)) || (r = B.alloc(c, &lamM, n3)) ||
+      (r = B.alloc(c, &gms, N)) || (r = B.alloc(c, &gku, N)) ||
+      (r = B.alloc(c, &hist, (size_t)10 * S)) ||
+      (r = B.alloc(c, &part, (size_t)7 * nlb)) || (r = B.alloc(c, &A, 1)))
+    return r;
+  // ---- forward with checkpoints and the windowed loss
+  std::vector<double> cks(3 * nseg);
+  Ctl h{};
+  if ((r = ctl_read(c, &h, c->ctl))) return r;
+  h.dt = dt;
+  h.accepted = 0;
+  h.loss_n0 = n0;
+  h.loss_n1 = n1;
+  h.loss_acc = 0.0;
+  h.ahist = nullptr;
+  h.done = 0;
+  h.status = 0;
+  h.rec_every = 0;
+  h.as_re[1] = h.a_re;
+  h.as_im[1] = h.a_im;
+  h.t_end = 1e300;
+  if ((r = ctl_write(c, c->ctl, &h))) return r;
+  for (int64_t j = 0; j < nseg; ++j) {
+    Ctl q{};
+    if ((r = ctl_read(c, &q, c->ctl))) return r;
+    cks[3 * j] = q.t;
+    cks[3 * j + 1] = q.a_re;
+    cks[3 * j + 2] = q.a_im;
+    HIPCHK(c, hipMemcpyAsync(ck + n3 * j, c->yn, n3 * 4,
+                             hipMemcpyDeviceToDevice, c->stream));
+    const int64_t Sj = std::min(S, n_steps - j * S);
+    for (int64_t k = 0; k < Sj && !r; ++k)
+      for (int s = 1; s <= 4 && !r; ++s)
+        r = rhs_stage(c, s == 1 ? c->yn : c->yb[(s + 1) % 2], c->ctl, s,
+                      epi_rk4(c, s), 0);
+    if (r) return r;
+  }
+  Ctl fin{};
+  if ((r = ctl_read(c, &fin, c->ctl))) return r;
+  if (fin.status) return fail(c, LLGC_E_NONFINITE, "non-finite forward state");
+  const double Lval = fin.loss_acc / (double)(n1 - n0 + 1);
+  // final state saved to restore after the sweep
+  float* mfin = nullptr;
+  if ((r = B.alloc(c, &mfin, n3))) return r;
+  HIPCHK(c, hipMemcpyAsync(mfin, c->yn, n3 * 4, hipMemcpyDeviceToDevice,
+                           c->stream));
+  // ---- reverse sweep
+  HIPCHK(c, hipMemsetAsync(lam, 0, n3 * 4, c->stream));
+  HIPCHK(c, hipMemsetAsync(gms, 0, N * 8, c->stream));
+  HIPCHK(c, hipMemsetAsync(gku, 0, N * 8, c->stream));
+  AdjCtl a0{};
+  a0.loss_scale = 1.0 / (double)(n1 - n0 + 1);
+  HIPCHK(c, hipMemcpyAsync(A, &a0, sizeof(AdjCtl), hipMemcpyHostToDevice,
+                           c->stream));
+  // unit-weight parameters for the demag pipeline applied to lamB
+  Prm Pu = c->P;
+  Pu.ms = 1.f;
+  Pu.ms_map = nullptr;
+  Pu.brx = Pu.bry = Pu.brz = 0.f;
+  Pu.brxd = Pu.bryd = Pu.brzd = 0.0;
+  Ctl he{};
+  he.t_end = 1e300;
+  if ((r = ctl_write(c, c->ctl_eval, &he))) return r;
+  const int R = c->Rw;
+  const dim3 fg = xgrid(c, R), fb(64 * 3 * (R / 2));
+  const size_t flds = c->P.demag ? sizeof(float) * 3 * R * c->nx : 0;
+  const double cs[5] = {0.0, 0.0, 0.5, 0.5, 1.0};
+  for (int64_t j = nseg - 1; j >= 0 && !r; --j) {
+    const int64_t Sj = std::min(S, n_steps - j * S);
+    // restore the checkpoint and recompute the segment with storage
+    HIPCHK(c, hipMemcpyAsync(c->yn, ck + n3 * j, n3 * 4,
+                             hipMemcpyDeviceToDevice, c->stream));
+    Ctl q{};
+    if ((r = ctl_read(c, &q, c->ctl))) return r;
+    q.t = cks[3 * j];
+    q.a_re = cks[3 * j + 1];
+    q.a_im = cks[3 * j + 2];
+    q.as_re[1] = q.a_re;
+    q.as_im[1] = q.a_im;
+    q.accepted = 0;
+    q.loss_n0 = q.loss_n1 = 0;
+    q.ahist = hist;
+    q.dt = dt;
+    if ((r = ctl_write(c, c->ctl, &q))) return r;
+    for (int64_t k = 0; k < Sj && !r; ++k)
+      r = rk4_step_stored(c, SY + n3 * 4 * k, SB + n3 * 4 * k, SN + N * k);
+    if (r) return r;
+    HIPCHK(c, hipMemcpyAsync(SY + n3 * 4 * Sj, c->yn, n3 * 4,
+                             hipMemcpyDeviceToDevice, c->stream));
+    for (int64_t k = Sj - 1; k >= 0 && !r; --k) {
+      const int64_t n = j * S + k + 1;
+      const double tn = cks[3 * j] + (double)k * dt;
+      const float* m_end = SY + n3 * 4 * (k + 1);
+      hipLaunchKernelGGL(k_adj_begin, dim3(nlb), dim3(256), 0, c->stream,
+                         (int)N, m_end, SN + N * k, lam, hat, acc, lamK,
+                         (float)(dt / 6.0));
+      hipLaunchKernelGGL(k_adj_begin_scalar, dim3(1), dim3(64), 0, c->stream,
+                         A, hist + 10 * k + 8, (n >= n0 && n <= n1) ? 1 : 0,
+                         dt / 6.0);
+      for (int s = 4; s >= 1 && !r; --s) {
+        const float* Y = SY + n3 * (4 * k + (s - 1));
+        const float* Bs = SB + n3 * (4 * k + (s - 1));
+        const double cK = (s == 4 || s == 3) ? dt / 3.0 : (s == 2 ? dt / 6.0 : 0.0);
+        const double cY = s == 4 ? dt : (s > 1 ? 0.5 * dt : 0.0);
+        hipLaunchKernelGGL(k_vjp_local, dim3(nlb), dim3(256), 0, c->stream,
+                           c->P, Y, Bs, lamK, A, lamB, lamM, gms, gku, part);
+        if (c->P.demag) {
+          Prm keep = c->P;
+          c->P = Pu;
+          r = launch_xfwd(c, lamB, c->ctl_eval, 1, 1);
+          if (!r) r = launch_yspec(c, c->ctl_eval, 1, 1);
+          c->P = keep;
+          if (r) break;
+        }
+#define LLGC_VF_ARGS c->P, Y, c->spec, lamB, lamM, gms, acc, hat, lamK, \
+                     (float)cK, (float)cY, R, c->tw, c->logTw
+        switch (c->Px) {
+          case 64: hipLaunchKernelGGL((k_vjp_field_w<1>), fg, fb, flds, c->stream, LLGC_VF_ARGS); break;
+          case 128: hipLaunchKernelGGL((k_vjp_field_w<2>), fg, fb, flds, c->stream, LLGC_VF_ARGS); break;
+          case 256: hipLaunchKernelGGL((k_vjp_field_w<4>), fg, fb, flds, c->stream, LLGC_VF_ARGS); break;
+          case 512: hipLaunchKernelGGL((k_vjp_field_w<8>), fg, fb, flds, c->stream, LLGC_VF_ARGS); break;
+          case 1024: hipLaunchKernelGGL((k_vjp_field_w<16>), fg, fb, flds, c->stream, LLGC_VF_ARGS); break;
+          default: hipLaunchKernelGGL((k_vjp_field_w<32>), fg, fb, flds, c->stream, LLGC_VF_ARGS); break;
+        }
+#undef LLGC_VF_ARGS
+        hipLaunchKernelGGL(k_vjp_scalar, dim3(1), dim3(256), 0, c->stream,
+                           c->P, A, part, nlb, hist + 10 * k + 2 * (s - 1),
+                           tn + cs[s] * dt, cK, cY);
+        r = check_launch(c, "adjoint stage");
+      }
+      std::swap(lam, acc);
+      hipLaunchKernelGGL(k_adj_end_scalar, dim3(1), dim3(64), 0, c->stream, A);
+    }
+  }
+  if (r) return r;
+  // outputs; the state is left at the end of the forward run
+  HIPCHK(c, hipMemcpyAsync(c->yn, mfin, n3 * 4, hipMemcpyDeviceToDevice,
+                           c->stream));
+  fin.ahist = nullptr;
+  fin.loss_n0 = fin.loss_n1 = 0;
+  fin.accepted = 0;
+  if ((r = ctl_write(c, c->ctl, &fin))) return r;
+  if (grad_ms)
+    hipLaunchKernelGGL(k_d2f, dim3(nlb), dim3(256), 0, c->stream, gms,
+                       grad_ms, (int)N);
+  if (grad_ku)
+    hipLaunchKernelGGL(k_d2f, dim3(nlb), dim3(256), 0, c->stream, gku,
+                       grad_ku, (int)N);
+  AdjCtl af{};
+  HIPCHK(c, hipMemcpyAsync(&af, A, sizeof(AdjCtl), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (loss) *loss = Lval;
+  if (grad_brms)
+    for (int k = 0; k < 3; ++k) grad_brms[k] = af.g_brms[k];
+  if (grad_eps) *grad_eps = af.g_eps0;
+  c->need_init = true;
+  return check_launch(c, "llgc_adjoint");
+}

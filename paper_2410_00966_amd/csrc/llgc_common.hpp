@@ -22,6 +22,12 @@ struct Ctl {
   int pending_accept, done, status, prev_rej;
   int nrec, rec_every, rec_cap, pad0;
   unsigned int cnt_xfwd, cnt_field, cnt_begin, cnt_rec;
+  // optional: per-step cavity history (stage amplitudes a_1..a_4 and the
+  // end-of-step amplitude, 5 complex per step) and the windowed loss
+  // sum_{n0 <= n <= n1} |alpha_n|^2 over accepted RK4 steps n (1-based)
+  double* ahist;
+  long long loss_n0, loss_n1;
+  double loss_acc;
 };
 
 enum { ST_OK = 0, ST_UNDERFLOW = 1, ST_NONFINITE = 2 };
@@ -29,6 +35,7 @@ enum { ST_OK = 0, ST_UNDERFLOW = 1, ST_NONFINITE = 2 };
 // Scalar problem parameters passed by value to every kernel.
 struct Prm {
   int nx, ny, nz, ncell;
+  int nyp;                      // spectrum row length (ny rounded up to even)
   int Px, Py, Hx, Hy, logPx, logPy;
   float idx2, idy2, idz2;       // 1/d^2 per axis
   float ms;                     // uniform Ms (A/m) when ms_map == nullptr
@@ -63,7 +70,8 @@ struct Epi {
   float cself;         // coefficient of this stage's k
   float* ynext;        // y_{s+1}, or y_n itself for the RK4 final stage
   float* kout;         // k_s output (may be null)
-  float* bout;         // B_eff output (evaluate only, may be null)
+  float* bout;         // B_eff output (may be null)
+  float* nout;         // RK4 final: |m_hat| before renormalisation (or null)
 };
 
 __host__ __device__ inline int ilog2(int v) {

@@ -4,12 +4,20 @@
 // loads a thread's butterflies into registers, barriers, computes and
 // stores to the auto-sorted positions, barriers.  All threads of the
 // workgroup cooperate on a batch of `batch` transforms of length L stored
-// contiguously (transform t at s + t*L).  Twiddles come from a table of
+// contiguously (transform t at logical s + t*L, stored at pidx()).  Twiddles come from a table of
 // exp(-2 pi i m / Ltw) for m < Ltw (Ltw a power of two >= L).
 #pragma once
 #include <hip/hip_runtime.h>
 
 namespace llgc {
+
+// LDS index with 2 padding slots every 16 complex values: spreads the
+// strided Stockham stores over the banks and keeps even indices 16-byte
+// aligned (pairs 2i, 2i+1 never straddle a gap).
+__host__ __device__ __forceinline__ int pidx(int i) { return i + ((i >> 4) << 1); }
+__host__ __device__ __forceinline__ size_t padded_len(size_t n) {
+  return n + ((n >> 4) << 1) + 2;
+}
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) {
   return make_float2(a.x + b.x, a.y + b.y);
@@ -83,14 +91,21 @@ __device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
   const int twshift = logTw - logNs - logR;   // k * Ltw / (Ns R)
   const int twmask = (1 << logTw) - 1;
   float2 v[NB][R];
+  float2 w1[NB];
+  // Loads of the butterfly inputs and of its base twiddle w = exp(-/+ i 2 pi
+  // k / (Ns R)) are issued before the barrier so their latency overlaps;
+  // the powers w^q are formed in registers afterwards.
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     const int b = threadIdx.x + i * blockDim.x;
+    w1[i] = make_float2(1.f, 0.f);
     if (b < nbf) {
       const int t = b >> logLr, j = b & (Lr - 1);
-      const float2* base = s + (t << logL);
+      const int base = t << logL;
 #pragma unroll
-      for (int q = 0; q < R; ++q) v[i][q] = base[j + q * Lr];
+      for (int q = 0; q < R; ++q) v[i][q] = s[pidx(base + j + q * Lr)];
+      const int k = j & (Ns - 1);
+      if (k != 0) w1[i] = tw[(k << twshift) & twmask];
     }
   }
   __syncthreads();
@@ -101,19 +116,19 @@ __device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
       const int t = b >> logLr, j = b & (Lr - 1);
       const int k = j & (Ns - 1);
       if (k != 0) {
-        const int step = k << twshift;
+        float2 w = w1[i];
+        w.y *= -dir;   // table holds exp(-i ...); inverse conjugates
+        float2 wq = w;
 #pragma unroll
         for (int q = 1; q < R; ++q) {
-          float2 w = tw[(q * step) & twmask];
-          w.y *= -dir;   // table holds exp(-i ...); inverse conjugates
-          v[i][q] = cmul(v[i][q], w);
+          v[i][q] = cmul(v[i][q], wq);
+          if (q + 1 < R) wq = cmul(wq, w);
         }
       }
       dft_small<R>(v[i], dir);
-      float2* base = s + (t << logL);
-      const int out0 = ((j - k) << logR) + k;
+      const int out0 = (t << logL) + ((j - k) << logR) + k;
 #pragma unroll
-      for (int q = 0; q < R; ++q) base[out0 + q * Ns] = v[i][q];
+      for (int q = 0; q < R; ++q) s[pidx(out0 + q * Ns)] = v[i][q];
     }
   }
   __syncthreads();

@@ -25,6 +25,7 @@
 
 #include "llgc_common.hpp"
 #include "llgc_fft.hpp"
+#include "llgc_wfft.hpp"
 
 namespace llgc {
 
@@ -126,11 +127,62 @@ __device__ inline bool last_block(unsigned int* counter, unsigned int nblk,
   return last;
 }
 
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Remap the launch index so that consecutive tiles run on the same
+// XCD: neighbouring tiles share spectrum cache lines and exchange halos.
+__device__ inline int xcd_tile(int bid, int nblk) {
+  const int per = nblk >> 3, rem = nblk & 7;
+  const int x = bid & 7, k = bid >> 3;
+  return (x < rem) ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
+}
+
+// Deterministic block-wide sum of NV interleaved partials p[b*NV + k],
+// b < n (fixed assignment of partials to threads and fixed tree order).
+template <int NV>
+__device__ inline void sum_partials(const double* p, unsigned int n,
+                                    double (&out)[NV], double* red) {
+  double v[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = 0.0;
+  for (unsigned int b = threadIdx.x; b < n; b += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] += p[(size_t)b * NV + k];
+  block_sum<NV>(v, red);
+#pragma unroll
+  for (int k = 0; k < NV; ++k) out[k] = v[k];
+}
+
+__device__ inline double max_partials(const double* p, unsigned int n,
+                                      double* red) {
+  double v = 0.0;
+  bool bad = false;
+  for (unsigned int b = threadIdx.x; b < n; b += blockDim.x) {
+    const double q = p[b];
+    if (!(q == q) || isinf(q)) bad = true;
+    v = fmax(v, q);
+  }
+  if (bad) v = INFINITY;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = red[0];
+    for (int i = 1; i < nw; ++i) a = fmax(a, red[i]);
+    v = a;
+  }
+  return v;
+}
+
 // ------------------------------------------------------------ cavity stage
 // Cavity rate at stage s and the amplitude for stage s+1 (or the end of the
 // step / the embedded error).  d alpha/dt = -(i wc + kappa) alpha
 // + i (V_c/hbar) F - i eps(t).
-__device__ void cavity_stage(const Prm& P, Ctl* c, int s, double F) {
+__device__ __forceinline__ void cavity_stage(const Prm& P, Ctl* c, int s,
+                                             double F) {
   const double dt = c->dt;
   const double ts = c->t + stage_c(P, s) * dt;
   const double eps = P.camp * drive_shape(P.ckind, P.cw, ts);
@@ -174,119 +226,296 @@ __device__ void cavity_stage(const Prm& P, Ctl* c, int s, double F) {
 }
 
 // ================================================================== k_xfwd
-// grid (ceil(ny/R), nz); LDS: (R/2) * Px complex.  mode 0: integrate
-// (cavity stage in the last block), mode 1: evaluate (store rate only).
-template <int T>
+// 1D grid of ceil(ny/R)*nz tiles (R even, XCD-remapped; the nz layers of one
+// y range are consecutive tiles).  LDS: (R/2) * Px complex.
+// mode 0: integrate (cavity stage in the last block); mode 1: evaluate.
+// V4: nx % 4 == 0 and 16-byte aligned planes (vector loads).
+template <int T, bool V4>
 __global__ __launch_bounds__(T) void k_xfwd(
     Prm P, const float* __restrict__ ys, float2* __restrict__ spec,
     Ctl* __restrict__ ctl, double* __restrict__ partials, int stage, int R,
     const float2* __restrict__ tw, int logTw, int mode) {
   extern __shared__ float2 lds[];
-  __shared__ double red[16 * 1];
-  __shared__ bool amlast;
+  __shared__ double red[16];
   if (ctl->done) return;
-  const int z = blockIdx.y;
-  const int y0 = blockIdx.x * R;
-  const int np = (R + 1) >> 1;
-  const int Px = P.Px, nx = P.nx, ny = P.ny, N = P.ncell;
+  const int nblk = gridDim.x;
+  const int tile = xcd_tile(blockIdx.x, nblk);
+  const int nz = P.nz;
+  const int z = tile % nz;
+  const int y0 = (tile / nz) * R;
+  const int np = R >> 1;
+  const int Px = P.Px, nx = P.nx, ny = P.ny, nyp = P.nyp, N = P.ncell;
   const int plane = nx * ny;
   const double br[3] = {P.brxd, P.bryd, P.brzd};
   double facc[1] = {0.0};
+  const float* msz = P.ms_map ? P.ms_map + (size_t)z * plane : nullptr;
   for (int c = 0; c < 3; ++c) {
     const float* yc = ys + (size_t)c * N + (size_t)z * plane;
-    // load pairs (row y0+2p as real part, y0+2p+1 as imaginary part);
-    // the coupling sum takes the exact FP64 products Ms_i m_i B_rms
-    const int tot = np * Px;
     double fc = 0.0;
-    for (int e = threadIdx.x; e < tot; e += T) {
-      const int p = e / Px, x = e - p * Px;
-      float2 v = make_float2(0.f, 0.f);
-      if (x < nx) {
-        const int ya = y0 + 2 * p, yb = ya + 1;
-        if (ya < ny && 2 * p < R) {
-          const int i = ya * nx + x;
-          const float msv = P.ms_map ? P.ms_map[z * plane + i] : P.ms;
-          const float mv = yc[i];
-          v.x = msv * mv;
-          fc += (double)msv * (double)mv;
+    if (V4) {
+      // quads of 4 consecutive x; row pair p: rows y0+2p (re), y0+2p+1 (im)
+      const int qpr = Px >> 2;               // quads per padded row
+      const int nq = np * qpr;
+      constexpr int U = 4;
+      for (int q0 = threadIdx.x; q0 < nq; q0 += T * U) {
+        float4 va[U], vb[U], sa[U], sb[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int q = q0 + u * T;
+          const int p = q / qpr, x = (q - p * qpr) << 2;
+          const int ya = y0 + 2 * p;
+          va[u] = vb[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+          sa[u] = sb[u] = make_float4(P.ms, P.ms, P.ms, P.ms);
+          if (q < nq && x < nx) {
+            if (ya < ny) {
+              va[u] = *(const float4*)(yc + ya * nx + x);
+              if (msz) sa[u] = *(const float4*)(msz + ya * nx + x);
+            }
+            if (ya + 1 < ny) {
+              vb[u] = *(const float4*)(yc + (ya + 1) * nx + x);
+              if (msz) sb[u] = *(const float4*)(msz + (ya + 1) * nx + x);
+            }
+          }
         }
-        if (yb < ny && 2 * p + 1 < R) {
-          const int i = yb * nx + x;
-          const float msv = P.ms_map ? P.ms_map[z * plane + i] : P.ms;
-          const float mv = yc[i];
-          v.y = msv * mv;
-          fc += (double)msv * (double)mv;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int q = q0 + u * T;
+          if (q >= nq) continue;
+          const int p = q / qpr, x = (q - p * qpr) << 2;
+          fc += (double)sa[u].x * va[u].x + (double)sa[u].y * va[u].y +
+                (double)sa[u].z * va[u].z + (double)sa[u].w * va[u].w +
+                (double)sb[u].x * vb[u].x + (double)sb[u].y * vb[u].y +
+                (double)sb[u].z * vb[u].z + (double)sb[u].w * vb[u].w;
+          if (P.demag) {
+            const int li = p * Px + x;
+            *(float4*)(lds + pidx(li)) =
+                make_float4(sa[u].x * va[u].x, sb[u].x * vb[u].x,
+                            sa[u].y * va[u].y, sb[u].y * vb[u].y);
+            *(float4*)(lds + pidx(li + 2)) =
+                make_float4(sa[u].z * va[u].z, sb[u].z * vb[u].z,
+                            sa[u].w * va[u].w, sb[u].w * vb[u].w);
+          }
         }
       }
-      if (P.demag) lds[e] = v;
+    } else {
+      const int tot = np * Px;
+      for (int e = threadIdx.x; e < tot; e += T) {
+        const int p = e / Px, x = e - p * Px;
+        float2 v = make_float2(0.f, 0.f);
+        if (x < nx) {
+          const int ya = y0 + 2 * p;
+          if (ya < ny) {
+            const float msv = msz ? msz[ya * nx + x] : P.ms;
+            const float mv = yc[ya * nx + x];
+            v.x = msv * mv;
+            fc += (double)msv * (double)mv;
+          }
+          if (ya + 1 < ny) {
+            const float msv = msz ? msz[(ya + 1) * nx + x] : P.ms;
+            const float mv = yc[(ya + 1) * nx + x];
+            v.y = msv * mv;
+            fc += (double)msv * (double)mv;
+          }
+        }
+        if (P.demag) lds[pidx(e)] = v;
+      }
     }
     facc[0] += fc * br[c];
     if (!P.demag) continue;
     __syncthreads();
     fft_lds<VPT>(lds, P.logPx, np, tw, logTw, -1.f);
-    // split the two real transforms and write the half spectrum
+    // split the two real transforms and write the half spectrum: rows
+    // (y0+2p, y0+2p+1) are adjacent -> one 16-byte store per (kx, p)
     const int H = P.Hx;
     const int totw = np * H;
     for (int e = threadIdx.x; e < totw; e += T) {
       const int k = e / np, p = e - k * np;
-      const float2 z1 = lds[p * Px + k];
-      const float2 z2 = lds[p * Px + ((Px - k) & (Px - 1))];
+      const float2 z1 = lds[pidx(p * Px + k)];
+      const float2 z2 = lds[pidx(p * Px + ((Px - k) & (Px - 1)))];
       // A = (Z[k] + conj Z[-k]) / 2 ; B = (Z[k] - conj Z[-k]) / (2i)
-      const float2 A = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y));
-      const float2 B = make_float2(0.5f * (z1.y + z2.y), -0.5f * (z1.x - z2.x));
+      const float4 AB = make_float4(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y),
+                                    0.5f * (z1.y + z2.y), -0.5f * (z1.x - z2.x));
       const int ya = y0 + 2 * p;
-      float2* row = spec + ((size_t)(k * P.nz + z) * 3 + c) * ny;
-      if (ya < ny && 2 * p < R) row[ya] = A;
-      if (ya + 1 < ny && 2 * p + 1 < R) row[ya + 1] = B;
+      if (ya < ny) {
+        float4 v = AB;
+        if (ya + 1 >= ny) { v.z = 0.f; v.w = 0.f; }   // keep the pad zero
+        float2* row = spec + ((size_t)(k * nz + z) * 3 + c) * nyp;
+        *(float4*)(row + ya) = v;
+      }
     }
     __syncthreads();
   }
   block_sum<1>(facc, red);
-  const unsigned int nblk = gridDim.x * gridDim.y;
-  const unsigned int bid = blockIdx.y * gridDim.x + blockIdx.x;
-  if (threadIdx.x == 0) partials[bid] = facc[0];
-  if (last_block(&ctl->cnt_xfwd, nblk, &amlast)) {
-    if (threadIdx.x == 0) {
-      double F = 0.0;
-      for (unsigned int i = 0; i < nblk; ++i) F += partials[i];
-      if (mode == 0) {
-        cavity_stage(P, ctl, stage, F);
-      } else {
-        // evaluate: rate at (a_s, F, t) with s = 1
-        const double ts = ctl->t;
-        const double eps = P.camp * drive_shape(P.ckind, P.cw, ts);
-        const double ar = ctl->as_re[1], ai = ctl->as_im[1];
-        ctl->rhs_dadt_re = -P.kappa * ar + P.wc * ai;
-        ctl->rhs_dadt_im = -P.wc * ar - P.kappa * ai + P.vc_hbar * F - eps;
-        ctl->F_last = F;
+  if (threadIdx.x == 0) partials[blockIdx.x] = facc[0];
+}
+
+// ================================================================ k_xfwd_w
+// Forward x pass with the FFT in registers (Px = 64 * NR): one wavefront per
+// (component, row pair) of an R-row tile.  Lane l, register r loads x =
+// l + 64 r of both rows (coalesced), the wavefront FFT leaves the spectrum in
+// its bit-reversed order, a per-wavefront LDS region (Px complex) puts it
+// back in natural order for the two-for-one split, and each lane writes the
+// (A, B) row pair of its kx values as one 16-byte store.  Same contract and
+// partial sums as k_xfwd.
+template <int NR>
+__global__ __launch_bounds__(NR >= 32 ? 512 : 1024) void k_xfwd_w(
+    Prm P, const float* __restrict__ ys, float2* __restrict__ spec,
+    Ctl* __restrict__ ctl, double* __restrict__ partials, int stage, int R,
+    const float2* __restrict__ tw, int logTw, int mode) {
+  extern __shared__ float2 zl[];
+  __shared__ double red[16];
+  if (ctl->done) return;
+  constexpr int LNR = Log2<NR>::v;
+  const int nblk = gridDim.x;
+  const int tile = xcd_tile(blockIdx.x, nblk);
+  const int nz = P.nz;
+  const int z = tile % nz;
+  const int y0 = (tile / nz) * R;
+  const int np = R >> 1;
+  const int Px = P.Px, nx = P.nx, ny = P.ny, nyp = P.nyp, N = P.ncell;
+  const int plane = nx * ny;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double fc = 0.0;
+  const bool active = wv < 3 * np;
+  const int c = active ? wv / np : 0, p = active ? wv - c * np : 0;
+  const int ya = y0 + 2 * p;
+  const bool fft = active && P.demag && ya < ny;
+  float2* zw = zl + (size_t)wv * Px;
+  if (active) {
+    const double br = c == 0 ? P.brxd : (c == 1 ? P.bryd : P.brzd);
+    const float* yc = ys + (size_t)c * N + (size_t)z * plane;
+    const float* msz = P.ms_map ? P.ms_map + (size_t)z * plane : nullptr;
+    float2 v[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int x = lane + 64 * r;
+      float a = 0.f, b = 0.f;
+      if (x < nx) {
+        if (ya < ny) {
+          const float ms = msz ? msz[ya * nx + x] : P.ms;
+          const float mv = yc[ya * nx + x];
+          a = ms * mv;
+          fc += (double)ms * (double)mv;
+        }
+        if (ya + 1 < ny) {
+          const float ms = msz ? msz[(ya + 1) * nx + x] : P.ms;
+          const float mv = yc[(ya + 1) * nx + x];
+          b = ms * mv;
+          fc += (double)ms * (double)mv;
+        }
       }
-      ctl->cnt_xfwd = 0;
+      v[r] = make_float2(a, b);
+    }
+    fc *= br;
+    if (fft) {
+      wfft_fwd<NR>(v, lane, tw, logTw);
+      const int b2 = NR * brev_bits(lane, 6);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) zw[brev_bits(r, LNR) + b2] = v[r];
     }
   }
+  __syncthreads();   // natural-order spectrum of each wavefront in LDS
+  if (fft) {
+    const int H = P.Hx;
+    for (int k = lane; k < H; k += 64) {
+      const float2 z1 = zw[k];
+      const float2 z2 = zw[(Px - k) & (Px - 1)];
+      // A = (Z[k] + conj Z[-k]) / 2 ; B = (Z[k] - conj Z[-k]) / (2i)
+      float4 AB = make_float4(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y),
+                              0.5f * (z1.y + z2.y), -0.5f * (z1.x - z2.x));
+      if (ya + 1 >= ny) { AB.z = 0.f; AB.w = 0.f; }   // keep the pad zero
+      *(float4*)(spec + ((size_t)(k * nz + z) * 3 + c) * nyp + ya) = AB;
+    }
+  }
+  double facc[1] = {fc};
+  block_sum<1>(facc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = facc[0];
+}
+
+// Finishes the FP64 coupling sum of a stage from the k_xfwd partials (the
+// kernel boundary makes them visible) and advances the cavity: mode 0
+// integrate, mode 1 evaluate (rate at a_1, t).  Runs in one workgroup.
+__device__ __forceinline__ void finish_cavity(const Prm& P, Ctl* ctl,
+                                              const double* partials,
+                              int nblk, int stage, int mode, double* red) {
+  double F[1];
+  sum_partials<1>(partials, nblk, F, red);
+  if (threadIdx.x != 0) return;
+  if (mode == 0) {
+    if (ctl->ahist && P.method == 0) {
+      double* h = ctl->ahist + 2 * (5 * ctl->accepted + (stage - 1));
+      h[0] = ctl->as_re[stage];
+      h[1] = ctl->as_im[stage];
+    }
+    cavity_stage(P, ctl, stage, F[0]);
+  } else {
+    const double ts = ctl->t;
+    const double eps = P.camp * drive_shape(P.ckind, P.cw, ts);
+    const double ar = ctl->as_re[1], ai = ctl->as_im[1];
+    ctl->rhs_dadt_re = -P.kappa * ar + P.wc * ai;
+    ctl->rhs_dadt_im = -P.wc * ar - P.kappa * ai + P.vc_hbar * F[0] - eps;
+    ctl->F_last = F[0];
+  }
+}
+
+// Stand-alone stage finish (used when there is no spectral pass).
+template <int T>
+__global__ __launch_bounds__(T) void k_finish_stage(
+    Prm P, Ctl* __restrict__ ctl, const double* __restrict__ partials,
+    int nblk, int stage, int mode) {
+  __shared__ double red[16];
+  if (ctl->done) return;
+  finish_cavity(P, ctl, partials, nblk, stage, mode, red);
 }
 
 // ================================================================= k_yspec
 // grid ceil(Hx/W); LDS: W * nz * 3 * Py complex.  Kernel layout
 // K[kx][ky][comp][dz] (comp: xx yy zz xy xz yz; xz, yz coefficients of -i),
-// ky in [0, Py/2]; scaled by -mu0/(Px Py).
+// ky in [0, Py/2]; scaled by -mu0/(Px Py).  Spectrum rows have nyp (even)
+// entries; entries at y >= ny are zero and stay zero.
 template <int T, int NZ>
 __global__ __launch_bounds__(T) void k_yspec(
     Prm P, float2* __restrict__ spec, const float* __restrict__ K,
-    const Ctl* __restrict__ ctl, int W, const float2* __restrict__ tw,
-    int logTw) {
+    Ctl* __restrict__ ctl, int W, const float2* __restrict__ tw,
+    int logTw, const double* __restrict__ partials, int nblk_f, int stage,
+    int mode) {
   extern __shared__ float2 lds[];
+  __shared__ double red[16];
   if (ctl->done) return;
+  // workgroup 0 also finishes the coupling sum of this stage
+  if (blockIdx.x == 0) {
+    finish_cavity(P, ctl, partials, nblk_f, stage, mode, red);
+    __syncthreads();
+  }
   const int kx0 = blockIdx.x * W;
   const int Wb = min(W, P.Hx - kx0);
-  const int ny = P.ny, Py = P.Py;
+  const int ny = P.ny, nyp = P.nyp, Py = P.Py;
   constexpr int nz = NZ;
   const int ncol = Wb * nz * 3;
-  // load physical rows, zero the padding
-  const int tot = ncol * Py;
-  const float2* src = spec + (size_t)kx0 * nz * 3 * ny;
-  for (int e = threadIdx.x; e < tot; e += T) {
-    const int col = e >> P.logPy, y = e & (Py - 1);
-    lds[e] = (y < ny) ? src[(size_t)col * ny + y] : make_float2(0.f, 0.f);
+  const float2* src = spec + (size_t)kx0 * nz * 3 * nyp;
+  if (Py >= 2) {
+    // pairs of rows (y, y+1) per 16-byte load
+    const int hp = Py >> 1;
+    const int tot = ncol * hp;
+    constexpr int U = 8;
+    for (int e0 = threadIdx.x; e0 < tot; e0 += T * U) {
+      float4 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * T;
+        const int col = e / hp, y = (e - col * hp) << 1;
+        v[u] = (e < tot && y < ny)
+                   ? *(const float4*)(src + (size_t)col * nyp + y)
+                   : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * T;
+        if (e < tot) *(float4*)(lds + pidx(2 * e)) = v[u];
+      }
+    }
+  } else {
+    for (int e = threadIdx.x; e < ncol; e += T) lds[pidx(e)] = src[(size_t)e * nyp];
   }
   __syncthreads();
   fft_lds<VPT>(lds, P.logPy, ncol, tw, logTw, -1.f);
@@ -300,10 +529,13 @@ __global__ __launch_bounds__(T) void k_yspec(
     const int kyi = lo ? ky : Py - ky;
     const float sy = lo ? 1.f : -1.f;   // odd-in-ky components flip
     const float* Kp = K + ((size_t)kx * Hy + kyi) * 6 * nz;
+    float kk[6 * NZ];
+#pragma unroll
+    for (int q = 0; q < 6 * NZ; ++q) kk[q] = Kp[q];
     float2 M[nz3], Hf[nz3];
 #pragma unroll
     for (int q = 0; q < nz3; ++q) {
-      M[q] = lds[(size_t)(w * nz3 + q) * Py + ky];
+      M[q] = lds[pidx((w * nz3 + q) * Py + ky)];
       Hf[q] = make_float2(0.f, 0.f);
     }
 #pragma unroll
@@ -313,10 +545,10 @@ __global__ __launch_bounds__(T) void k_yspec(
         const int d = zt - zs;
         const int ad = d < 0 ? -d : d;
         const float sz = d < 0 ? -1.f : 1.f;   // xz, yz odd in dz
-        const float kxx = Kp[0 * nz + ad], kyy = Kp[1 * nz + ad];
-        const float kzz = Kp[2 * nz + ad], kxy = sy * Kp[3 * nz + ad];
-        const float qxz = sz * Kp[4 * nz + ad];          // K_xz = -i qxz
-        const float qyz = sz * sy * Kp[5 * nz + ad];     // K_yz = -i qyz
+        const float kxx = kk[0 * nz + ad], kyy = kk[1 * nz + ad];
+        const float kzz = kk[2 * nz + ad], kxy = sy * kk[3 * nz + ad];
+        const float qxz = sz * kk[4 * nz + ad];          // K_xz = -i qxz
+        const float qyz = sz * sy * kk[5 * nz + ad];     // K_yz = -i qyz
         const float2 mx = M[zs * 3 + 0], my = M[zs * 3 + 1],
                      mz = M[zs * 3 + 2];
         // -i q * v = (q v.y, -q v.x)
@@ -332,59 +564,160 @@ __global__ __launch_bounds__(T) void k_yspec(
       }
     }
 #pragma unroll
-    for (int q = 0; q < nz3; ++q) lds[(size_t)(w * nz3 + q) * Py + ky] = Hf[q];
+    for (int q = 0; q < nz3; ++q) lds[pidx((w * nz3 + q) * Py + ky)] = Hf[q];
   }
   __syncthreads();
   fft_lds<VPT>(lds, P.logPy, ncol, tw, logTw, 1.f);
-  float2* dst = spec + (size_t)kx0 * nz * 3 * ny;
-  const int totw = ncol * ny;
-  for (int e = threadIdx.x; e < totw; e += T) {
-    const int col = e / ny, y = e - col * ny;
-    dst[e] = lds[(size_t)col * Py + y];
+  float2* dst = spec + (size_t)kx0 * nz * 3 * nyp;
+  if (Py >= 2) {
+    const int hq = nyp >> 1;          // row pairs actually stored
+    const int tot = ncol * hq;
+    for (int e = threadIdx.x; e < tot; e += T) {
+      const int col = e / hq, y = (e - col * hq) << 1;
+      float4 v = *(const float4*)(lds + pidx(col * Py + y));
+      if (y + 1 >= ny) { v.z = 0.f; v.w = 0.f; }   // keep the pad zero
+      *(float4*)(dst + (size_t)col * nyp + y) = v;
+    }
+  } else {
+    for (int e = threadIdx.x; e < ncol; e += T) dst[(size_t)e * nyp] = lds[pidx(e)];
   }
 }
 
-// ================================================================ k_xfield
-// grid (ceil(ny/R), nz); LDS: 3 * (R/2) * Px complex.
-template <int T>
-__global__ __launch_bounds__(T) void k_xfield(
-    Prm P, const float* __restrict__ ys, const float2* __restrict__ spec,
-    Ctl* __restrict__ ctl, double* __restrict__ partials,
-    double* __restrict__ rec, int stage, int R, Epi E,
-    const float2* __restrict__ tw, int logTw) {
+
+// ============================================================== k_yspec_w
+// Kernel product of one chunk of G registers (all columns of the workgroup
+// at the same ky), staged through LDS.  The chunk start G0 is a template
+// parameter so that the register array is only ever indexed statically.
+template <int NZ, int NR, int G, int G0>
+__device__ __forceinline__ void yprod_chunks(
+    float2 (&v)[NR], float2* lds, int Py, int Hy, const float* __restrict__ K,
+    int kx0, int Wb, int wv, int lane, bool active) {
+  constexpr int nz3 = 3 * NZ;
+  constexpr int LNR = Log2<NR>::v;
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int rr = 0; rr < G; ++rr) lds[(wv * G + rr) * 64 + lane] = v[G0 + rr];
+  }
+  __syncthreads();
+  const int nslot = Wb * G * 64;
+  for (int s = threadIdx.x; s < nslot; s += blockDim.x) {
+    const int w = s / (G * 64);
+    const int rem = s - w * (G * 64);
+    const int rr = rem >> 6, ln = rem & 63;
+    const int ky = brev_bits(G0 + rr, LNR) + NR * brev_bits(ln, 6);
+    const int kx = kx0 + w;
+    const bool lo = ky <= (Py >> 1);
+    const int kyi = lo ? ky : Py - ky;
+    const float sy = lo ? 1.f : -1.f;
+    const float* Kp = K + ((size_t)kx * Hy + kyi) * 6 * NZ;
+    float kk[6 * NZ];
+#pragma unroll
+    for (int q = 0; q < 6 * NZ; ++q) kk[q] = Kp[q];
+    float2 M[nz3], Hf[nz3];
+#pragma unroll
+    for (int q = 0; q < nz3; ++q) {
+      M[q] = lds[((w * nz3 + q) * G + rr) * 64 + ln];
+      Hf[q] = make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int zt = 0; zt < NZ; ++zt) {
+#pragma unroll
+      for (int zs = 0; zs < NZ; ++zs) {
+        const int d = zt - zs;
+        const int ad = d < 0 ? -d : d;
+        const float sz = d < 0 ? -1.f : 1.f;
+        const float kxx = kk[0 * NZ + ad], kyy = kk[1 * NZ + ad];
+        const float kzz = kk[2 * NZ + ad], kxy = sy * kk[3 * NZ + ad];
+        const float qxz = sz * kk[4 * NZ + ad];          // K_xz = -i qxz
+        const float qyz = sz * sy * kk[5 * NZ + ad];     // K_yz = -i qyz
+        const float2 mx = M[zs * 3 + 0], my = M[zs * 3 + 1],
+                     mz = M[zs * 3 + 2];
+        float2& hx = Hf[zt * 3 + 0];
+        float2& hy = Hf[zt * 3 + 1];
+        float2& hz = Hf[zt * 3 + 2];
+        hx.x += kxx * mx.x + kxy * my.x + qxz * mz.y;
+        hx.y += kxx * mx.y + kxy * my.y - qxz * mz.x;
+        hy.x += kxy * mx.x + kyy * my.x + qyz * mz.y;
+        hy.y += kxy * mx.y + kyy * my.y - qyz * mz.x;
+        hz.x += qxz * mx.y + qyz * my.y + kzz * mz.x;
+        hz.y += -qxz * mx.x - qyz * my.x + kzz * mz.y;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < nz3; ++q) lds[((w * nz3 + q) * G + rr) * 64 + ln] = Hf[q];
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int rr = 0; rr < G; ++rr) v[G0 + rr] = lds[(wv * G + rr) * 64 + lane];
+  }
+  if constexpr (G0 + G < NR)
+    yprod_chunks<NZ, NR, G, G0 + G>(v, lds, Py, Hy, K, kx0, Wb, wv, lane,
+                                    active);
+}
+
+// Spectral pass with one wavefront per column (kx, z, c) and the y FFT held
+// in registers (Py = 64 * NR): the 3*nz columns of W consecutive kx form a
+// workgroup; only the kernel product goes through LDS, G registers at a
+// time (the product needs all columns at one ky).  Same contract as k_yspec.
+template <int NZ, int NR>
+__global__ __launch_bounds__(NR >= 32 ? 512 : 1024) void k_yspec_w(
+    Prm P, float2* __restrict__ spec, const float* __restrict__ K,
+    Ctl* __restrict__ ctl, int W, const float2* __restrict__ tw,
+    int logTw, const double* __restrict__ partials, int nblk_f, int stage,
+    int mode) {
   extern __shared__ float2 lds[];
+  __shared__ double red[16];
+  if (ctl->done) return;
+  if (blockIdx.x == 0) {
+    finish_cavity(P, ctl, partials, nblk_f, stage, mode, red);
+    __syncthreads();
+  }
+  constexpr int nz3 = 3 * NZ;
+  constexpr int G = NR < 8 ? NR : 8;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int kx0 = blockIdx.x * W;
+  const int Wb = min(W, P.Hx - kx0);
+  const bool active = wv < Wb * nz3;
+  const int ny = P.ny, nyp = P.nyp;
+  float2* col = spec + ((size_t)kx0 * nz3 + wv) * nyp;
+  float2 v[NR];
+  if (active) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int y = lane + 64 * r;
+      v[r] = (y < ny) ? col[y] : make_float2(0.f, 0.f);
+    }
+    wfft_fwd<NR>(v, lane, tw, logTw);
+  }
+  yprod_chunks<NZ, NR, G, 0>(v, lds, P.Py, P.Hy, K, kx0, Wb, wv, lane, active);
+  if (active) {
+    wfft_inv<NR>(v, lane, tw, logTw);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int y = lane + 64 * r;
+      if (y < ny) col[y] = v[r];
+      else if (y < nyp) col[y] = make_float2(0.f, 0.f);   // pad stays zero
+    }
+  }
+}
+
+// Local fields, LL torque and Runge-Kutta epilogue for the R rows of one
+// tile (cells (x, y0 + r, z)), given B_demag through `bd(r, x)`; writes the
+// stage outputs and the workgroup's partial sums (RK4 final: <m> sums,
+// DP45 error stage: max error).  Any block size.
+template <class BD>
+__device__ __forceinline__ void field_cells(const Prm& P,
+                                            const float* __restrict__ ys,
+                                            const Ctl* __restrict__ ctl,
+                                            double* __restrict__ partials,
+                                            int stage, int R, const Epi& E,
+                                            int z, int y0, BD bd) {
   __shared__ double red[16 * 3];
   __shared__ float redf[16];
-  __shared__ bool amlast;
-  if (ctl->done) return;
-  const int z = blockIdx.y;
-  const int y0 = blockIdx.x * R;
-  const int np = (R + 1) >> 1;
-  const int Px = P.Px, nx = P.nx, ny = P.ny, nz = P.nz, N = P.ncell;
+  const int nx = P.nx, ny = P.ny, nz = P.nz, N = P.ncell;
   const int plane = nx * ny;
-  if (P.demag) {
-    // rebuild the two-for-one spectra: Z[k] = A[k] + i B[k],
-    // Z[Px-k] = conj(A[k]) + i conj(B[k])
-    const int H = P.Hx;
-    const int tot = 3 * np * H;
-    for (int e = threadIdx.x; e < tot; e += T) {
-      const int k = e / (3 * np);
-      const int r = e - k * 3 * np;
-      const int c = r / np, p = r - c * np;
-      const int ya = y0 + 2 * p;
-      const float2* row = spec + ((size_t)(k * nz + z) * 3 + c) * ny;
-      float2 A = make_float2(0.f, 0.f), B = make_float2(0.f, 0.f);
-      if (ya < ny && 2 * p < R) A = row[ya];
-      if (ya + 1 < ny && 2 * p + 1 < R) B = row[ya + 1];
-      if (k == 0 || 2 * k == Px) { A.y = 0.f; B.y = 0.f; }
-      float2* s = lds + (size_t)(c * np + p) * Px;
-      s[k] = make_float2(A.x - B.y, A.y + B.x);
-      if (k != 0 && 2 * k != Px)
-        s[Px - k] = make_float2(A.x + B.y, -A.y + B.x);
-    }
-    __syncthreads();
-    fft_lds<VPT>(lds, P.logPx, 3 * np, tw, logTw, 1.f);
-  }
   const double dtd = ctl->dt;
   const float dt = (float)dtd;
   const double ts = ctl->t + stage_c(P, stage) * dtd;
@@ -396,7 +729,7 @@ __global__ __launch_bounds__(T) void k_xfield(
   double acc[3] = {0.0, 0.0, 0.0};
   float emax = 0.f;
   const int ncellb = R * nx;
-  for (int e = threadIdx.x; e < ncellb; e += T) {
+  for (int e = threadIdx.x; e < ncellb; e += blockDim.x) {
     const int r = e / nx, x = e - r * nx;
     const int y = y0 + r;
     if (y >= ny) continue;
@@ -405,14 +738,10 @@ __global__ __launch_bounds__(T) void k_xfield(
     const float msv = P.ms_map ? P.ms_map[i] : P.ms;
     float Bx = bex + bcx, By = bey + bcy, Bz = bez + bcz;
     if (P.demag) {
-      const int p = r >> 1;
-      const bool hi = r & 1;
-      const float2 vx = lds[(size_t)(0 * np + p) * Px + x];
-      const float2 vy = lds[(size_t)(1 * np + p) * Px + x];
-      const float2 vz = lds[(size_t)(2 * np + p) * Px + x];
-      Bx += hi ? vx.y : vx.x;
-      By += hi ? vy.y : vy.x;
-      Bz += hi ? vz.y : vz.x;
+      const float3 b = bd(r, x);
+      Bx += b.x;
+      By += b.y;
+      Bz += b.z;
     }
     if (msv > 0.f) {
       // exchange: (2A/Ms) sum over existing neighbours (m_j - m_i)/d^2
@@ -441,10 +770,8 @@ __global__ __launch_bounds__(T) void k_xfield(
     const float ky = P.gpref * (py + P.alpha * qy);
     const float kz = P.gpref * (pz + P.alpha * qz);
     if (E.kout) { E.kout[i] = kx; E.kout[N + i] = ky; E.kout[2 * N + i] = kz; }
-    if (E.kind == 0) {
-      if (E.bout) { E.bout[i] = Bx; E.bout[N + i] = By; E.bout[2 * N + i] = Bz; }
-      continue;
-    }
+    if (E.bout) { E.bout[i] = Bx; E.bout[N + i] = By; E.bout[2 * N + i] = Bz; }
+    if (E.kind == 0) continue;
     float sx = E.cself * kx, sy = E.cself * ky, sz = E.cself * kz;
     for (int j = 0; j < E.np; ++j) {
       const float cj = E.ca[j];
@@ -454,49 +781,198 @@ __global__ __launch_bounds__(T) void k_xfield(
     }
     if (E.kind == 3) {
       const float ex = dt * sx, ey = dt * sy, ez = dt * sz;
-      emax = fmaxf(emax, sqrtf(ex * ex + ey * ey + ez * ez));
+      const float en = sqrtf(ex * ex + ey * ey + ez * ez);
+      emax = (en == en) ? fmaxf(emax, en) : INFINITY;   // NaN -> reject
       continue;
     }
     float nxv = E.yn[i] + dt * sx, nyv = E.yn[N + i] + dt * sy,
           nzv = E.yn[2 * N + i] + dt * sz;
     if (E.kind == 2) {
-      const float inv = 1.f / sqrtf(nxv * nxv + nyv * nyv + nzv * nzv);
+      const float nrm = sqrtf(nxv * nxv + nyv * nyv + nzv * nzv);
+      if (E.nout) E.nout[i] = nrm;
+      const float inv = 1.f / nrm;
       nxv *= inv; nyv *= inv; nzv *= inv;
       acc[0] += nxv; acc[1] += nyv; acc[2] += nzv;
     }
     E.ynext[i] = nxv; E.ynext[N + i] = nyv; E.ynext[2 * N + i] = nzv;
   }
   if (E.kind != 2 && E.kind != 3) return;
-  const unsigned int nblk = gridDim.x * gridDim.y;
-  const unsigned int bid = blockIdx.y * gridDim.x + blockIdx.x;
   if (E.kind == 2) {
     block_sum<3>(acc, red);
     if (threadIdx.x == 0) {
-      partials[3 * bid + 0] = acc[0];
-      partials[3 * bid + 1] = acc[1];
-      partials[3 * bid + 2] = acc[2];
+      partials[3 * blockIdx.x + 0] = acc[0];
+      partials[3 * blockIdx.x + 1] = acc[1];
+      partials[3 * blockIdx.x + 2] = acc[2];
     }
   } else {
     emax = block_max(emax, redf);
-    if (threadIdx.x == 0) partials[bid] = (double)emax;
+    if (threadIdx.x == 0) partials[blockIdx.x] = (double)emax;
   }
-  if (!last_block(&ctl->cnt_field, nblk, &amlast)) return;
+}
+
+
+// ================================================================ k_xfield
+// 1D grid of ceil(ny/R)*nz tiles (as k_xfwd); LDS: 3 * (R/2) * Px complex.
+template <int T>
+__global__ __launch_bounds__(T) void k_xfield(
+    Prm P, const float* __restrict__ ys, const float2* __restrict__ spec,
+    Ctl* __restrict__ ctl, double* __restrict__ partials,
+    double* __restrict__ rec, int stage, int R, Epi E,
+    const float2* __restrict__ tw, int logTw) {
+  extern __shared__ float2 lds[];
+  if (ctl->done) return;
+  const int nblk = gridDim.x;
+  const int nz = P.nz;
+  const int tile = xcd_tile(blockIdx.x, nblk);
+  const int z = tile % nz;
+  const int y0 = (tile / nz) * R;
+  const int np = R >> 1;
+  const int Px = P.Px, ny = P.ny, nyp = P.nyp;
+  if (P.demag) {
+    // rebuild the two-for-one spectra: Z[k] = A[k] + i B[k],
+    // Z[Px-k] = conj(A[k]) + i conj(B[k]); (A, B) adjacent rows -> 16 B
+    const int H = P.Hx;
+    const int per = 3 * np;
+    const int tot = per * H;
+    constexpr int U = 4;
+    for (int e0 = threadIdx.x; e0 < tot; e0 += T * U) {
+      float4 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * T;
+        const int k = e / per;
+        const int r = e - k * per;
+        const int c = r / np, p = r - c * np;
+        const int ya = y0 + 2 * p;
+        v[u] = (e < tot && ya < ny)
+                   ? *(const float4*)(spec +
+                                      ((size_t)(k * nz + z) * 3 + c) * nyp + ya)
+                   : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * T;
+        if (e >= tot) continue;
+        const int k = e / per;
+        const int r = e - k * per;
+        const int c = r / np, p = r - c * np;
+        float2 A = make_float2(v[u].x, v[u].y), B = make_float2(v[u].z, v[u].w);
+        if (k == 0 || 2 * k == Px) { A.y = 0.f; B.y = 0.f; }
+        const int sp = (c * np + p) * Px;
+        lds[pidx(sp + k)] = make_float2(A.x - B.y, A.y + B.x);
+        if (k != 0 && 2 * k != Px)
+          lds[pidx(sp + Px - k)] = make_float2(A.x + B.y, -A.y + B.x);
+      }
+    }
+    __syncthreads();
+    fft_lds<VPT>(lds, P.logPx, 3 * np, tw, logTw, 1.f);
+  }
+  field_cells(P, ys, ctl, partials, stage, R, E, z, y0,
+              [&](int r, int x) {
+                const int p = r >> 1;
+                const bool hi = r & 1;
+                const float2 vx = lds[pidx((0 * np + p) * Px + x)];
+                const float2 vy = lds[pidx((1 * np + p) * Px + x)];
+                const float2 vz = lds[pidx((2 * np + p) * Px + x)];
+                return hi ? make_float3(vx.y, vy.y, vz.y)
+                          : make_float3(vx.x, vy.x, vz.x);
+              });
+}
+
+// ============================================================== k_xfield_w
+// Field kernel with the x inverse FFT in registers (Px = 64 * NR): one
+// wavefront per (component, row pair) of an R-row tile gathers its
+// two-for-one spectrum straight from the half spectrum in the wavefront-FFT
+// input order, transforms, and leaves B_demag of its two rows in LDS
+// (3 * R * nx floats); then all threads run the cell loop.
+template <int NR>
+__global__ __launch_bounds__(NR >= 32 ? 512 : 1024) void k_xfield_w(
+    Prm P, const float* __restrict__ ys, const float2* __restrict__ spec,
+    Ctl* __restrict__ ctl, double* __restrict__ partials,
+    double* __restrict__ rec, int stage, int R, Epi E,
+    const float2* __restrict__ tw, int logTw) {
+  extern __shared__ float bdl[];
+  if (ctl->done) return;
+  constexpr int LNR = Log2<NR>::v;
+  const int nblk = gridDim.x;
+  const int nz = P.nz;
+  const int tile = xcd_tile(blockIdx.x, nblk);
+  const int z = tile % nz;
+  const int y0 = (tile / nz) * R;
+  const int np = R >> 1;
+  const int Px = P.Px, nx = P.nx, ny = P.ny, nyp = P.nyp;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (P.demag && wv < 3 * np) {
+    const int c = wv / np, p = wv - c * np;
+    const int ya = y0 + 2 * p;
+    float2 v[NR];
+    if (ya < ny) {
+      const int b2 = NR * brev_bits(lane, 6);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int k = brev_bits(r, LNR) + b2;
+        const bool lo = 2 * k <= Px;
+        const int kk = lo ? k : Px - k;
+        const float4 ab = *(const float4*)(spec +
+                                           ((size_t)(kk * nz + z) * 3 + c) * nyp + ya);
+        float2 A = make_float2(ab.x, ab.y), B = make_float2(ab.z, ab.w);
+        if (kk == 0 || 2 * kk == Px) { A.y = 0.f; B.y = 0.f; }
+        v[r] = lo ? make_float2(A.x - B.y, A.y + B.x)
+                  : make_float2(A.x + B.y, -A.y + B.x);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) v[r] = make_float2(0.f, 0.f);
+    }
+    wfft_inv<NR>(v, lane, tw, logTw);
+    float* b0 = bdl + (size_t)(c * R + 2 * p) * nx;
+    float* b1 = b0 + nx;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int x = lane + 64 * r;
+      if (x < nx) { b0[x] = v[r].x; b1[x] = v[r].y; }
+    }
+  }
+  __syncthreads();
+  field_cells(P, ys, ctl, partials, stage, R, E, z, y0,
+              [&](int r, int x) {
+                return make_float3(bdl[(0 * R + r) * nx + x],
+                                   bdl[(1 * R + r) * nx + x],
+                                   bdl[(2 * R + r) * nx + x]);
+              });
+}
+
+// End of a step, one workgroup: RK4 commit and record (kind 2) or the
+// Dormand-Prince step controller (kind 3), from the k_xfield partials.
+template <int T>
+__global__ __launch_bounds__(T) void k_finish_step(
+    Prm P, Ctl* __restrict__ ctl, const double* __restrict__ partials,
+    int nblk, int kind, double* __restrict__ rec) {
+  __shared__ double red[16 * 3];
+  if (ctl->done) return;
+  const int N = P.ncell;
+  double S[3] = {0.0, 0.0, 0.0};
+  double errm = 0.0;
+  if (kind == 2) sum_partials<3>(partials, nblk, S, red);
+  else errm = max_partials(partials, nblk, red);
   if (threadIdx.x != 0) return;
   Ctl* c = ctl;
-  if (E.kind == 2) {
+  if (kind == 2) {
     // RK4 commit and record
     c->t = c->t + c->dt;
     c->a_re = c->anext_re;
     c->a_im = c->anext_im;
     c->as_re[1] = c->a_re;
     c->as_im[1] = c->a_im;
-    c->accepted += 1;
-    double s0 = 0, s1 = 0, s2 = 0;
-    for (unsigned int b = 0; b < nblk; ++b) {
-      s0 += partials[3 * b];
-      s1 += partials[3 * b + 1];
-      s2 += partials[3 * b + 2];
+    if (c->ahist) {
+      double* h = c->ahist + 2 * (5 * c->accepted + 4);
+      h[0] = c->a_re;
+      h[1] = c->a_im;
     }
+    c->accepted += 1;
+    if (c->accepted >= c->loss_n0 && c->accepted <= c->loss_n1)
+      c->loss_acc += c->a_re * c->a_re + c->a_im * c->a_im;
+    const double s0 = S[0], s1 = S[1], s2 = S[2];
     if (!(isfinite(s0) && isfinite(s1) && isfinite(s2))) {
       c->status = ST_NONFINITE;
       c->done = 1;
@@ -514,12 +990,8 @@ __global__ __launch_bounds__(T) void k_xfield(
     }
   } else {
     // Dormand-Prince step controller
-    double errm = 0.0;
-    for (unsigned int b = 0; b < nblk; ++b) errm = fmax(errm, partials[b]);
     double err = fmax(errm, c->err_a);
-    bool bad = !isfinite(err) || !isfinite(errm);
-    for (unsigned int b = 0; b < nblk && !bad; ++b)
-      if (!isfinite(partials[b])) bad = true;
+    const bool bad = !isfinite(err);
     const double h = c->dt;
     double fac;
     if (!bad && err <= P.tol) {
@@ -556,12 +1028,12 @@ __global__ __launch_bounds__(T) void k_xfield(
     c->as_re[2] = c->a_re + dtn * c_dp_a[2][0] * c->ka_re[1];
     c->as_im[2] = c->a_im + dtn * c_dp_a[2][0] * c->ka_im[1];
   }
-  c->cnt_field = 0;
 }
 
 // ================================================================= k_begin
 // Start of a Dormand-Prince attempt: commit an accepted step (renormalise
 // y7 into y_n, FSAL k7 -> k1, record), form y2 = y_n + dt a21 k1.
+// Requires N % 4 == 0 for the vector path (scalar tail otherwise).
 template <int T>
 __global__ __launch_bounds__(T) void k_begin(
     Prm P, float* __restrict__ yn, float* __restrict__ k1,
@@ -571,11 +1043,56 @@ __global__ __launch_bounds__(T) void k_begin(
   __shared__ double red[16 * 3];
   __shared__ bool amlast;
   const int pend = ctl->pending_accept;
-  if (ctl->done && !pend) return;
+  const int done = ctl->done;
+  if (done && !pend) return;
+  // the average is reduced only when this accepted step is recorded
+  const bool rec_due = pend && ctl->rec_every > 0 && ctl->nrec < ctl->rec_cap &&
+                       (ctl->accepted % ctl->rec_every) == 0;
   const int N = P.ncell;
   const float c21 = (float)(ctl->dt * c_dp_a[2][0]);
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int i = blockIdx.x * T + threadIdx.x; i < N; i += gridDim.x * T) {
+  const int n4 = N >> 2;
+  const int stride = gridDim.x * T;
+  // component planes as float4 (N % 4 == 0 checked by the host; the
+  // remainder loop below covers the rest)
+  const int nvec = (N % 4 == 0) ? n4 : 0;
+  for (int q = blockIdx.x * T + threadIdx.x; q < nvec; q += stride) {
+    float4 m[3], k[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (pend) {
+        m[c] = ((const float4*)(y7 + (size_t)c * N))[q];
+        k[c] = ((const float4*)(k7 + (size_t)c * N))[q];
+      } else {
+        m[c] = ((const float4*)(yn + (size_t)c * N))[q];
+        k[c] = ((const float4*)(k1 + (size_t)c * N))[q];
+      }
+    }
+    if (pend) {
+      float* mx = &m[0].x; float* my = &m[1].x; float* mz = &m[2].x;
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        const float inv = 1.f / sqrtf(mx[l] * mx[l] + my[l] * my[l] + mz[l] * mz[l]);
+        mx[l] *= inv; my[l] *= inv; mz[l] *= inv;
+        acc[0] += mx[l]; acc[1] += my[l]; acc[2] += mz[l];
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        ((float4*)(yn + (size_t)c * N))[q] = m[c];
+        ((float4*)(k1 + (size_t)c * N))[q] = k[c];
+      }
+    }
+    if (!done) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float4 o;
+        o.x = m[c].x + c21 * k[c].x; o.y = m[c].y + c21 * k[c].y;
+        o.z = m[c].z + c21 * k[c].z; o.w = m[c].w + c21 * k[c].w;
+        ((float4*)(y2 + (size_t)c * N))[q] = o;
+      }
+    }
+  }
+  for (int i = 4 * nvec + blockIdx.x * T + threadIdx.x; i < N; i += stride) {
     float mx, my, mz, kx, ky, kz;
     if (pend) {
       mx = y7[i]; my = y7[N + i]; mz = y7[2 * N + i];
@@ -589,12 +1106,23 @@ __global__ __launch_bounds__(T) void k_begin(
       mx = yn[i]; my = yn[N + i]; mz = yn[2 * N + i];
       kx = k1[i]; ky = k1[N + i]; kz = k1[2 * N + i];
     }
-    if (!ctl->done) {
+    if (!done) {
       y2[i] = mx + c21 * kx; y2[N + i] = my + c21 * ky;
       y2[2 * N + i] = mz + c21 * kz;
     }
   }
   if (!pend) return;
+  if (!rec_due) {
+    // every block saw pend = 1; clear it from the last one to arrive
+    if (threadIdx.x == 0) {
+      const unsigned int prev = atomicAdd(&ctl->cnt_begin, 1u);
+      if (prev == gridDim.x - 1) {
+        ctl->pending_accept = 0;
+        ctl->cnt_begin = 0;
+      }
+    }
+    return;
+  }
   block_sum<3>(acc, red);
   if (threadIdx.x == 0) {
     partials[3 * blockIdx.x + 0] = acc[0];
@@ -602,20 +1130,15 @@ __global__ __launch_bounds__(T) void k_begin(
     partials[3 * blockIdx.x + 2] = acc[2];
   }
   if (!last_block(&ctl->cnt_begin, gridDim.x, &amlast)) return;
+  double S[3];
+  sum_partials<3>(partials, gridDim.x, S, red);
   if (threadIdx.x != 0) return;
-  double s0 = 0, s1 = 0, s2 = 0;
-  for (unsigned int b = 0; b < gridDim.x; ++b) {
-    s0 += partials[3 * b];
-    s1 += partials[3 * b + 1];
-    s2 += partials[3 * b + 2];
-  }
-  if (ctl->rec_every > 0 && (ctl->accepted % ctl->rec_every) == 0 &&
-      ctl->nrec < ctl->rec_cap) {
+  {
     double* row = rec + 6 * (size_t)ctl->nrec;
     row[0] = ctl->t;
-    row[1] = s0 / N;
-    row[2] = s1 / N;
-    row[3] = s2 / N;
+    row[1] = S[0] / N;
+    row[2] = S[1] / N;
+    row[3] = S[2] / N;
     row[4] = ctl->a_re;
     row[5] = ctl->a_im;
     ctl->nrec += 1;
@@ -646,19 +1169,15 @@ __global__ __launch_bounds__(T) void k_record(
     partials[3 * blockIdx.x + 2] = acc[2];
   }
   if (!last_block(&ctl->cnt_rec, gridDim.x, &amlast)) return;
+  double S[3];
+  sum_partials<3>(partials, gridDim.x, S, red);
   if (threadIdx.x != 0) return;
-  double s0 = 0, s1 = 0, s2 = 0;
-  for (unsigned int b = 0; b < gridDim.x; ++b) {
-    s0 += partials[3 * b];
-    s1 += partials[3 * b + 1];
-    s2 += partials[3 * b + 2];
-  }
   if (ctl->nrec < ctl->rec_cap) {
     double* row = rec + 6 * (size_t)ctl->nrec;
     row[0] = ctl->t;
-    row[1] = s0 / N;
-    row[2] = s1 / N;
-    row[3] = s2 / N;
+    row[1] = S[0] / N;
+    row[2] = S[1] / N;
+    row[3] = S[2] / N;
     row[4] = ctl->a_re;
     row[5] = ctl->a_im;
     ctl->nrec += 1;

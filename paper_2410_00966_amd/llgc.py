@@ -24,7 +24,7 @@ RK4, DP45 = 0, 1
 EXPORTED = ("llgc_create", "llgc_destroy", "llgc_last_error",
             "llgc_set_params", "llgc_set_state", "llgc_get_state",
             "llgc_reset_cavity", "llgc_cavity_enabled", "llgc_run",
-            "llgc_step", "llgc_eval_rhs", "llgc_demag_kernel",
+            "llgc_step", "llgc_eval_rhs", "llgc_adjoint", "llgc_demag_kernel",
             "llgc_demag_tensor", "llgc_set_timing", "llgc_kernel_times",
             "llgc_plan_info")
 
@@ -102,6 +102,8 @@ def load():
         "llgc_step": ([vp, P(RunInfo)], ctypes.c_int),
         "llgc_eval_rhs": ([vp, vp, dbl, dbl, dbl, vp, vp, P(dbl)],
                           ctypes.c_int),
+        "llgc_adjoint": ([vp, i64, dbl, i64, i64, i64, P(dbl), vp, vp,
+                          P(dbl), P(dbl)], ctypes.c_int),
         "llgc_demag_kernel": ([vp, P(ctypes.c_float), i64, P(i32)],
                               ctypes.c_int),
         "llgc_demag_tensor": ([vp, P(dbl), i64], ctypes.c_int),
@@ -254,6 +256,26 @@ class Sim:
             B.data_ptr() if B is not None else None, da), "llgc_eval_rhs")
         self.stream.synchronize()
         return dm, B, complex(da[0], da[1])
+
+    def adjoint(self, n_steps, dt, n0, n1, stride=0):
+        """Discrete-adjoint gradient of L = mean_{n0<=n<=n1} |alpha_n|^2
+        after n_steps RK4 steps from the current state.  Returns dict(loss,
+        g_ms, g_ku (device tensors shaped like one component plane),
+        g_brms (3,), g_eps0)."""
+        shape = self.shape[1:]
+        gms = self.torch.empty(shape, dtype=self.torch.float32,
+                               device="cuda")
+        gku = self.torch.empty_like(gms)
+        loss = ctypes.c_double()
+        gb = (ctypes.c_double * 3)()
+        ge = ctypes.c_double()
+        self._check(self.L.llgc_adjoint(
+            self.h, int(n_steps), float(dt), int(stride), int(n0), int(n1),
+            ctypes.byref(loss), gms.data_ptr(), gku.data_ptr(), gb,
+            ctypes.byref(ge)), "llgc_adjoint")
+        self.stream.synchronize()
+        return dict(loss=loss.value, g_ms=gms, g_ku=gku,
+                    g_brms=np.array(list(gb)), g_eps0=ge.value)
 
     def demag_kernel(self):
         dims = (ctypes.c_int32 * 4)()
