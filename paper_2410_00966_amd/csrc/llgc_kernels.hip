@@ -358,16 +358,12 @@ __global__ __launch_bounds__(T) void k_xfwd(
 // (A, B) row pair of its kx values as one 16-byte store.  Same contract and
 // partial sums as k_xfwd.
 template <int NR>
-__global__ __launch_bounds__(NR >= 32 ? 512 : 1024) void k_xfwd_w(
-    Prm P, const float* __restrict__ ys, float2* __restrict__ spec,
-    Ctl* __restrict__ ctl, double* __restrict__ partials, int stage, int R,
-    const float2* __restrict__ tw, int logTw, int mode) {
-  extern __shared__ float2 zl[];
+__device__ __forceinline__ void xfwd_w_body(
+    const Prm& P, const float* __restrict__ ys, float2* __restrict__ spec,
+    double* __restrict__ partials, int R, const float2* __restrict__ tw,
+    int logTw, int tile, int slot, float2* zl) {
   __shared__ double red[16];
-  if (ctl->done) return;
   constexpr int LNR = Log2<NR>::v;
-  const int nblk = gridDim.x;
-  const int tile = xcd_tile(blockIdx.x, nblk);
   const int nz = P.nz;
   const int z = tile % nz;
   const int y0 = (tile / nz) * R;
@@ -429,7 +425,18 @@ __global__ __launch_bounds__(NR >= 32 ? 512 : 1024) void k_xfwd_w(
   }
   double facc[1] = {fc};
   block_sum<1>(facc, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = facc[0];
+  if (threadIdx.x == 0) partials[slot] = facc[0];
+}
+
+template <int NR>
+__global__ __launch_bounds__(NR >= 32 ? 512 : 1024) void k_xfwd_w(
+    Prm P, const float* __restrict__ ys, float2* __restrict__ spec,
+    Ctl* __restrict__ ctl, double* __restrict__ partials, int stage, int R,
+    const float2* __restrict__ tw, int logTw, int mode) {
+  extern __shared__ float2 zl[];
+  if (ctl->done) return;
+  xfwd_w_body<NR>(P, ys, spec, partials, R, tw, logTw,
+                  xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, zl);
 }
 
 // Finishes the FP64 coupling sum of a stage from the k_xfwd partials (the
@@ -662,22 +669,20 @@ __device__ __forceinline__ void yprod_chunks(
 // workgroup; only the kernel product goes through LDS, G registers at a
 // time (the product needs all columns at one ky).  Same contract as k_yspec.
 template <int NZ, int NR>
-__global__ __launch_bounds__(NR >= 32 ? 512 : 1024) void k_yspec_w(
-    Prm P, float2* __restrict__ spec, const float* __restrict__ K,
+__device__ __forceinline__ void yspec_w_body(
+    const Prm& P, float2* __restrict__ spec, const float* __restrict__ K,
     Ctl* __restrict__ ctl, int W, const float2* __restrict__ tw,
     int logTw, const double* __restrict__ partials, int nblk_f, int stage,
-    int mode) {
-  extern __shared__ float2 lds[];
+    int mode, int blk, float2* lds) {
   __shared__ double red[16];
-  if (ctl->done) return;
-  if (blockIdx.x == 0) {
+  if (blk == 0) {
     finish_cavity(P, ctl, partials, nblk_f, stage, mode, red);
     __syncthreads();
   }
   constexpr int nz3 = 3 * NZ;
   constexpr int G = NR < 8 ? NR : 8;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int kx0 = blockIdx.x * W;
+  const int kx0 = blk * W;
   const int Wb = min(W, P.Hx - kx0);
   const bool active = wv < Wb * nz3;
   const int ny = P.ny, nyp = P.nyp;
@@ -703,6 +708,18 @@ __global__ __launch_bounds__(NR >= 32 ? 512 : 1024) void k_yspec_w(
   }
 }
 
+template <int NZ, int NR>
+__global__ __launch_bounds__(NR >= 32 ? 512 : 1024) void k_yspec_w(
+    Prm P, float2* __restrict__ spec, const float* __restrict__ K,
+    Ctl* __restrict__ ctl, int W, const float2* __restrict__ tw,
+    int logTw, const double* __restrict__ partials, int nblk_f, int stage,
+    int mode) {
+  extern __shared__ float2 lds[];
+  if (ctl->done) return;
+  yspec_w_body<NZ, NR>(P, spec, K, ctl, W, tw, logTw, partials, nblk_f, stage,
+                       mode, blockIdx.x, lds);
+}
+
 // Local fields, LL torque and Runge-Kutta epilogue for the R rows of one
 // tile (cells (x, y0 + r, z)), given B_demag through `bd(r, x)`; writes the
 // stage outputs and the workgroup's partial sums (RK4 final: <m> sums,
@@ -713,7 +730,8 @@ __device__ __forceinline__ void field_cells(const Prm& P,
                                             const Ctl* __restrict__ ctl,
                                             double* __restrict__ partials,
                                             int stage, int R, const Epi& E,
-                                            int z, int y0, BD bd) {
+                                            int z, int y0, BD bd,
+                                            int slot) {
   __shared__ double red[16 * 3];
   __shared__ float redf[16];
   const int nx = P.nx, ny = P.ny, nz = P.nz, N = P.ncell;
@@ -800,13 +818,13 @@ __device__ __forceinline__ void field_cells(const Prm& P,
   if (E.kind == 2) {
     block_sum<3>(acc, red);
     if (threadIdx.x == 0) {
-      partials[3 * blockIdx.x + 0] = acc[0];
-      partials[3 * blockIdx.x + 1] = acc[1];
-      partials[3 * blockIdx.x + 2] = acc[2];
+      partials[3 * slot + 0] = acc[0];
+      partials[3 * slot + 1] = acc[1];
+      partials[3 * slot + 2] = acc[2];
     }
   } else {
     emax = block_max(emax, redf);
-    if (threadIdx.x == 0) partials[blockIdx.x] = (double)emax;
+    if (threadIdx.x == 0) partials[slot] = (double)emax;
   }
 }
 
@@ -876,7 +894,7 @@ __global__ __launch_bounds__(T) void k_xfield(
                 const float2 vz = lds[pidx((2 * np + p) * Px + x)];
                 return hi ? make_float3(vx.y, vy.y, vz.y)
                           : make_float3(vx.x, vy.x, vz.x);
-              });
+              }, blockIdx.x);
 }
 
 // ============================================================== k_xfield_w
@@ -886,17 +904,14 @@ __global__ __launch_bounds__(T) void k_xfield(
 // input order, transforms, and leaves B_demag of its two rows in LDS
 // (3 * R * nx floats); then all threads run the cell loop.
 template <int NR>
-__global__ __launch_bounds__(NR >= 32 ? 512 : 1024) void k_xfield_w(
-    Prm P, const float* __restrict__ ys, const float2* __restrict__ spec,
-    Ctl* __restrict__ ctl, double* __restrict__ partials,
-    double* __restrict__ rec, int stage, int R, Epi E,
-    const float2* __restrict__ tw, int logTw) {
-  extern __shared__ float bdl[];
-  if (ctl->done) return;
+__device__ __forceinline__ void xfield_w_body(
+    const Prm& P, const float* __restrict__ ys,
+    const float2* __restrict__ spec, const Ctl* __restrict__ ctl,
+    double* __restrict__ partials, int stage, int R, const Epi& E,
+    const float2* __restrict__ tw, int logTw, int tile, int slot,
+    float* bdl) {
   constexpr int LNR = Log2<NR>::v;
-  const int nblk = gridDim.x;
   const int nz = P.nz;
-  const int tile = xcd_tile(blockIdx.x, nblk);
   const int z = tile % nz;
   const int y0 = (tile / nz) * R;
   const int np = R >> 1;
@@ -939,7 +954,19 @@ __global__ __launch_bounds__(NR >= 32 ? 512 : 1024) void k_xfield_w(
                 return make_float3(bdl[(0 * R + r) * nx + x],
                                    bdl[(1 * R + r) * nx + x],
                                    bdl[(2 * R + r) * nx + x]);
-              });
+              }, slot);
+}
+
+template <int NR>
+__global__ __launch_bounds__(NR >= 32 ? 512 : 1024) void k_xfield_w(
+    Prm P, const float* __restrict__ ys, const float2* __restrict__ spec,
+    Ctl* __restrict__ ctl, double* __restrict__ partials,
+    double* __restrict__ rec, int stage, int R, Epi E,
+    const float2* __restrict__ tw, int logTw) {
+  extern __shared__ float bdl[];
+  if (ctl->done) return;
+  xfield_w_body<NR>(P, ys, spec, ctl, partials, stage, R, E, tw, logTw,
+                    xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, bdl);
 }
 
 // End of a step, one workgroup: RK4 commit and record (kind 2) or the
