@@ -107,6 +107,19 @@ typedef struct {
  * or padded sizes beyond the on-chip FFT limits), LLGC_E_OOM, LLGC_E_HIP. */
 int llgc_create(const llgc_grid *grid, void *hip_stream, llgc_ctx **out);
 
+/* Plan flags of llgc_create_ex. */
+enum { LLGC_PLAN_BATCH = 1 };
+
+/* As llgc_create, with plan flags.  LLGC_PLAN_BATCH selects the fixed plan
+ * that every instance of a batch (llgc_batch_create) uses: register FFTs
+ * on padded lengths of at least 64 points, 4-row x tiles.  A context
+ * created with it performs bit for bit the same arithmetic as the same
+ * problem run inside a batch.  It needs 2 <= nx, ny <= 128.
+ * Errors: as llgc_create; LLGC_E_ARG for unknown flags;
+ * LLGC_E_UNSUPPORTED outside the batched size range. */
+int llgc_create_ex(const llgc_grid *grid, void *hip_stream, int32_t flags,
+                   llgc_ctx **out);
+
 /* Frees every buffer of the context.  NULL is accepted. */
 int llgc_destroy(llgc_ctx *ctx);
 
@@ -207,6 +220,52 @@ int llgc_set_timing(llgc_ctx *ctx, int32_t enable);
 int llgc_kernel_times(llgc_ctx *ctx, double *ms, int64_t *launches,
                       int32_t cap, char *names, int32_t names_cap,
                       int32_t reset);
+
+/* ---------------------------------------------------------------------
+ * Batched engine: many independent problems of different grid sizes
+ * advanced together, one launch per kernel and stage for all of them.
+ * This is the shape of the paper's parameter studies (the Dicke-model
+ * validation repeated over the whole range of omega_c, omega_z and lambda,
+ * section "Benchmark"; material and size scans of section "Ferromagnetic
+ * materials in a cavity"), where each run alone is too small to fill the
+ * GPU.  Each instance is an ordinary context with the LLGC_PLAN_BATCH plan
+ * owned by the batch; it is configured with llgc_set_params /
+ * llgc_set_state and read with llgc_get_state as usual.  Every instance
+ * keeps its own time, step size, step controller and cavity; instances
+ * that finish drop out of the launches. */
+typedef struct llgc_batch llgc_batch;
+
+/* Creates `n_inst` instances, instance k on grids[k] (host array).  All
+ * instances share `hip_stream`.  Grid limits as LLGC_PLAN_BATCH.
+ * Errors: LLGC_E_ARG (n_inst < 1, NULL pointers), LLGC_E_UNSUPPORTED,
+ * LLGC_E_OOM, LLGC_E_HIP. */
+int llgc_batch_create(const llgc_grid *grids, int32_t n_inst,
+                      void *hip_stream, llgc_batch **out);
+
+/* Frees the batch and all its instances.  NULL is accepted. */
+int llgc_batch_destroy(llgc_batch *b);
+
+/* Message of the last failed batch call (owned by b).  Never NULL. */
+const char *llgc_batch_last_error(const llgc_batch *b);
+
+/* Instance k (0 <= k < n_inst), owned by the batch (do not destroy), or
+ * NULL for an invalid index. */
+llgc_ctx *llgc_batch_instance(llgc_batch *b, int32_t k);
+
+/* Runs every instance as llgc_run would run it alone, with the same
+ * `nsteps`, `t_end` and `record_every` for all instances (t_end is an
+ * absolute time on each instance's own clock).  All instances must use
+ * the same method.  Records: host buffer of n_inst * rec_cap rows of 6
+ * float64, instance k's rows starting at row k * rec_cap; `n_rec`
+ * (n_inst int64), `info` (n_inst entries) and `status` (n_inst int32,
+ * each instance's llgc_run status) may be NULL.  Returns LLGC_OK when every
+ * instance succeeded, else the first failing instance's status (its
+ * message in llgc_batch_last_error).
+ * Errors: LLGC_E_STATE (an instance without params/state), LLGC_E_ARG
+ * (mixed methods, records without a buffer), LLGC_E_HIP. */
+int llgc_batch_run(llgc_batch *b, int64_t nsteps, double t_end,
+                   int32_t record_every, double *rec, int64_t rec_cap,
+                   int64_t *n_rec, llgc_run_info *info, int32_t *status);
 
 /* Plan facts (host ints, 8 entries): Px, Py, rows per x-pass block,
  * kx columns per spectral block, x-pass threads, spectral threads,

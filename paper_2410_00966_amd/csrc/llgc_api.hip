@@ -18,6 +18,7 @@
 #include "llgc_demag.hip"
 #include "llgc_kernels.hip"
 #include "llgc_adjoint.hip"
+#include "llgc_batch.hip"
 
 using namespace llgc;
 
@@ -26,6 +27,9 @@ namespace {
 constexpr int kT = 256;               // x-pass / field / pointwise threads
 constexpr int kMaxLen = 2048;         // largest padded FFT length per axis
 constexpr size_t kLdsCap = 120 * 1024; // LDS per workgroup this plan uses
+constexpr int kBatchMaxLen = 256;     // batched plan: padded length per axis
+constexpr int kBatchRows = 4;         // batched plan: rows per x-pass tile
+constexpr int kBatchYWaves = 12;      // batched plan: wavefronts per y block
 
 struct TimerRec {
   double ms = 0.0;
@@ -44,6 +48,7 @@ struct llgc_ctx {
   int Ww = 1;            // kx columns per wavefront-FFT spectral block
   bool use_wy = false;   // register (wavefront) FFT along y
   bool use_wx = false;   // register (wavefront) inverse FFT along x
+  bool batch_plan = false;  // fixed plan shared with the batched engine
   int Rw = 2;            // rows per tile of the wavefront field kernel
   int Rwf = 2;           // rows per tile of the wavefront forward x pass
   size_t lds_f, lds_i, lds_y;
@@ -570,20 +575,35 @@ int timers_collect(llgc_ctx* c) {
 extern "C" {
 
 int llgc_create(const llgc_grid* g, void* stream, llgc_ctx** out) {
+  return llgc_create_ex(g, stream, 0, out);
+}
+
+int llgc_create_ex(const llgc_grid* g, void* stream, int flags,
+                   llgc_ctx** out) {
   if (!g || !out) return LLGC_E_ARG;
   *out = nullptr;
   if (g->nx < 1 || g->ny < 1 || g->nz < 1 || !(g->dx > 0) || !(g->dy > 0) ||
-      !(g->dz > 0))
+      !(g->dz > 0) || (flags & ~LLGC_PLAN_BATCH))
     return LLGC_E_ARG;
   if (g->nz > 4 || g->nx > kMaxLen / 2 || g->ny > kMaxLen / 2)
+    return LLGC_E_UNSUPPORTED;
+  const bool bplan = (flags & LLGC_PLAN_BATCH) != 0;
+  if (bplan && (g->nx < 2 || g->ny < 2 || g->nx > kBatchMaxLen / 2 ||
+                g->ny > kBatchMaxLen / 2))
     return LLGC_E_UNSUPPORTED;
   llgc_ctx* c = new llgc_ctx();
   c->nx = g->nx; c->ny = g->ny; c->nz = g->nz;
   c->N = g->nx * g->ny * g->nz;
   c->dx = g->dx; c->dy = g->dy; c->dz = g->dz;
   c->stream = (hipStream_t)stream;
+  c->batch_plan = bplan;
   c->Px = g->nx == 1 ? 1 : pow2_ceil(2 * g->nx);
   c->Py = g->ny == 1 ? 1 : pow2_ceil(2 * g->ny);
+  if (bplan) {
+    // the batched kernels hold every transform in registers: >= 64 points
+    c->Px = std::max(c->Px, 64);
+    c->Py = std::max(c->Py, 64);
+  }
   c->Hx = c->Px / 2 + 1;
   c->Hy = c->Py / 2 + 1;
   c->logPx = ilog2(c->Px);
@@ -626,6 +646,12 @@ int llgc_create(const llgc_grid* g, void* stream, llgc_ctx** out) {
   if (const char* s = getenv("LLGC_RW")) c->Rw = (atoi(s) >= 4) ? 4 : 2;
   c->Rwf = 2;
   if (const char* s = getenv("LLGC_RWF")) c->Rwf = (atoi(s) >= 4) ? 4 : 2;
+  if (bplan) {
+    // the fixed plan of every batched instance (no tuning overrides)
+    c->use_wx = c->use_wy = true;
+    c->Rw = c->Rwf = kBatchRows;
+    c->Ww = std::max(1, kBatchYWaves / (3 * c->nz));
+  }
   if (W * col > VPT * 512) {
     delete c;
     return LLGC_E_UNSUPPORTED;
@@ -847,35 +873,49 @@ int llgc_cavity_enabled(const llgc_ctx* c) {
   return (b[0] != 0.0 || b[1] != 0.0 || b[2] != 0.0) ? 1 : 0;
 }
 
-int llgc_run(llgc_ctx* c, int64_t nsteps, double t_end, int32_t rec_every,
-             double* rec, int64_t rec_cap, int64_t* n_rec,
-             llgc_run_info* info) {
-  if (!c) return LLGC_E_ARG;
+}  // extern "C" (reopened below)
+
+namespace {
+
+// Run set-up shared by llgc_run and the batched engine: control block,
+// initial record, and for Dormand-Prince the first stage and the first
+// attempt's start (k_begin), so that what follows is whole attempts.
+struct RunPrep {
+  long long acc0 = 0, rej0 = 0;
+  int64_t nsteps = 0, cap = 0, evals = 0;
+  bool rk4 = false, done = false;
+};
+
+int run_prepare(llgc_ctx* c, int64_t nsteps, double t_end, int32_t rec_every,
+                double* rec, int64_t rec_cap, RunPrep* rp) {
   if (!c->have_params || !c->have_state)
     return fail(c, LLGC_E_STATE, "set params and state before running");
   if (rec_every > 0 && (!rec || rec_cap < 1))
     return fail(c, LLGC_E_ARG, "records requested without a buffer");
-  if (n_rec) *n_rec = 0;
-  int64_t cap = rec_every > 0 ? rec_cap : 0;
-  if (int r = ensure_rec(c, std::max<int64_t>(cap, 1))) return r;
+  rp->cap = rec_every > 0 ? rec_cap : 0;
+  if (int r = ensure_rec(c, std::max<int64_t>(rp->cap, 1))) return r;
   Ctl h{};
   if (int r = ctl_read(c, &h, c->ctl)) return r;
-  const long long acc0 = h.accepted, rej0 = h.rejected;
+  rp->acc0 = h.accepted;
+  rp->rej0 = h.rejected;
   h.rec_every = rec_every > 0 ? rec_every : 0;
-  h.rec_cap = (int)cap;
+  h.rec_cap = (int)rp->cap;
   h.nrec = 0;
   h.status = 0;
   h.done = 0;
   h.accepted = 0;
   h.rejected = 0;
   h.cnt_xfwd = h.cnt_field = h.cnt_begin = h.cnt_rec = 0;
-  int64_t evals = 0;
-  const bool rk4 = c->prm.method == LLGC_RK4;
-  if (rk4) {
+  rp->rk4 = c->prm.method == LLGC_RK4;
+  rp->evals = 0;
+  if (rp->rk4) {
     h.dt = c->prm.dt;
     if (nsteps <= 0) nsteps = (int64_t)std::llround((t_end - h.t) / h.dt);
+    rp->nsteps = std::max<int64_t>(nsteps, 0);
     h.t_end = 1e300;
-    h.max_accepted = (long long)1 << 62;
+    // the commit of step `nsteps` marks the run done
+    h.max_accepted = rp->nsteps;
+    h.done = rp->nsteps == 0 ? 1 : 0;
   } else {
     h.t_end = t_end;
     h.max_accepted = nsteps > 0 ? nsteps : ((long long)1 << 62);
@@ -883,31 +923,84 @@ int llgc_run(llgc_ctx* c, int64_t nsteps, double t_end, int32_t rec_every,
     h.dt = std::min(h.dt, t_end - h.t);
     h.done = (h.t >= t_end) ? 1 : 0;
     h.pending_accept = 0;
-  }
-  if (int r = ctl_write(c, c->ctl, &h)) return r;
-  if (cap > 0) {
-    if (int r = launch_record(c)) return r;
-  }
-  int r = LLGC_OK;
-  if (rk4) {
-    for (int64_t n = 0; n < nsteps && !r; ++n) {
-      for (int s = 1; s <= 4 && !r; ++s) {
-        const float* ys = (s == 1) ? c->yn : c->yb[(s + 1) % 2];
-        r = rhs_stage(c, ys, c->ctl, s, epi_rk4(c, s), 0);
-        evals++;
-      }
-    }
-  } else if (!h.done) {
-    if (c->need_init) {
-      r = rhs_stage(c, c->yn, c->ctl, 1, epi_eval(c->kb[0], nullptr), 0);
-      evals++;
-    } else {
+    if (!h.done && !c->need_init) {
       // current dt may differ from the one y2 was formed with
       h.as_re[2] = h.a_re + h.dt * 0.2 * h.ka_re[1];
       h.as_im[2] = h.a_im + h.dt * 0.2 * h.ka_im[1];
-      r = ctl_write(c, c->ctl, &h);
     }
-    if (!r) r = launch_begin(c);
+  }
+  rp->done = h.done != 0;
+  if (int r = ctl_write(c, c->ctl, &h)) return r;
+  if (rp->cap > 0) {
+    if (int r = launch_record(c)) return r;
+  }
+  if (!rp->rk4 && !rp->done) {
+    if (c->need_init) {
+      if (int r = rhs_stage(c, c->yn, c->ctl, 1, epi_eval(c->kb[0], nullptr),
+                            0))
+        return r;
+      rp->evals = 1;
+    }
+    if (int r = launch_begin(c)) return r;
+  }
+  return LLGC_OK;
+}
+
+// Reads the outcome of a run back: records, info, totals, status.
+int run_conclude(llgc_ctx* c, const RunPrep& rp, double* rec,
+                 int64_t* n_rec, llgc_run_info* info) {
+  c->need_init = false;
+  Ctl e{};
+  if (int q = ctl_read(c, &e, c->ctl)) return q;
+  const int64_t evals = rp.rk4 ? 4 * e.accepted
+                               : 6 * (e.accepted + e.rejected) + rp.evals;
+  if (rp.cap > 0 && e.nrec > 0) {
+    HIPCHK(c, hipMemcpy(rec, c->rec, sizeof(double) * 6 * e.nrec,
+                        hipMemcpyDeviceToHost));
+  }
+  if (n_rec) *n_rec = e.nrec;
+  if (info) {
+    info->accepted = e.accepted;
+    info->rejected = e.rejected;
+    info->rhs_evals = evals;
+    info->t = e.t;
+    info->dt = e.dt;
+    info->last_err = e.last_err;
+  }
+  // keep totals across runs
+  e.accepted += rp.acc0;
+  e.rejected += rp.rej0;
+  const int st = e.status;
+  e.status = 0;
+  if (int q = ctl_write(c, c->ctl, &e)) return q;
+  if (st == ST_UNDERFLOW)
+    return fail(c, LLGC_E_DT_UNDERFLOW, "time step fell below dt_min");
+  if (st == ST_NONFINITE)
+    return fail(c, LLGC_E_NONFINITE, "non-finite state or error estimate");
+  return LLGC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int llgc_run(llgc_ctx* c, int64_t nsteps, double t_end, int32_t rec_every,
+             double* rec, int64_t rec_cap, int64_t* n_rec,
+             llgc_run_info* info) {
+  if (!c) return LLGC_E_ARG;
+  if (n_rec) *n_rec = 0;
+  RunPrep rp;
+  if (int r = run_prepare(c, nsteps, t_end, rec_every, rec, rec_cap, &rp))
+    return r;
+  int r = LLGC_OK;
+  if (rp.rk4) {
+    for (int64_t n = 0; n < rp.nsteps && !r; ++n) {
+      for (int s = 1; s <= 4 && !r; ++s) {
+        const float* ys = (s == 1) ? c->yn : c->yb[(s + 1) % 2];
+        r = rhs_stage(c, ys, c->ctl, s, epi_rk4(c, s), 0);
+      }
+    }
+  } else if (!rp.done) {
     const int64_t max_attempts = 50000000;
     int64_t attempts = 0;
     while (!r) {
@@ -932,34 +1025,7 @@ int llgc_run(llgc_ctx* c, int64_t nsteps, double t_end, int32_t rec_every,
     }
   }
   if (r) return r;
-  c->need_init = false;
-  Ctl e{};
-  if (int q = ctl_read(c, &e, c->ctl)) return q;
-  if (!rk4) evals = 6 * (e.accepted + e.rejected) + (evals ? 1 : 0);
-  if (cap > 0 && e.nrec > 0) {
-    HIPCHK(c, hipMemcpy(rec, c->rec, sizeof(double) * 6 * e.nrec,
-                        hipMemcpyDeviceToHost));
-  }
-  if (n_rec) *n_rec = e.nrec;
-  if (info) {
-    info->accepted = e.accepted;
-    info->rejected = e.rejected;
-    info->rhs_evals = evals;
-    info->t = e.t;
-    info->dt = e.dt;
-    info->last_err = e.last_err;
-  }
-  // keep totals across runs
-  e.accepted += acc0;
-  e.rejected += rej0;
-  const int st = e.status;
-  e.status = 0;
-  if (int q = ctl_write(c, c->ctl, &e)) return q;
-  if (st == ST_UNDERFLOW)
-    return fail(c, LLGC_E_DT_UNDERFLOW, "time step fell below dt_min");
-  if (st == ST_NONFINITE)
-    return fail(c, LLGC_E_NONFINITE, "non-finite state or error estimate");
-  return LLGC_OK;
+  return run_conclude(c, rp, rec, n_rec, info);
 }
 
 int llgc_step(llgc_ctx* c, llgc_run_info* info) {
@@ -1157,6 +1223,7 @@ extern "C" int llgc_adjoint(llgc_ctx* c, int64_t n_steps, double dt,
   if ((r = ctl_read(c, &h, c->ctl))) return r;
   h.dt = dt;
   h.accepted = 0;
+  h.max_accepted = 0;
   h.loss_n0 = n0;
   h.loss_n1 = n1;
   h.loss_acc = 0.0;
@@ -1305,3 +1372,5 @@ extern "C" int llgc_adjoint(llgc_ctx* c, int64_t n_steps, double dt,
   c->need_init = true;
   return check_launch(c, "llgc_adjoint");
 }
+
+#include "llgc_batch_api.hip"

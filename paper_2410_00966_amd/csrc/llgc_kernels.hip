@@ -435,8 +435,8 @@ __global__ __launch_bounds__(NR >= 32 ? 512 : 1024) void k_xfwd_w(
     const float2* __restrict__ tw, int logTw, int mode) {
   extern __shared__ float2 zl[];
   if (ctl->done) return;
-  xfwd_w_body<NR>(P, ys, spec, partials, R, tw, logTw,
-                  xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, zl);
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  xfwd_w_body<NR>(P, ys, spec, partials, R, tw, logTw, tile, tile, zl);
 }
 
 // Finishes the FP64 coupling sum of a stage from the k_xfwd partials (the
@@ -445,8 +445,13 @@ __global__ __launch_bounds__(NR >= 32 ? 512 : 1024) void k_xfwd_w(
 __device__ __forceinline__ void finish_cavity(const Prm& P, Ctl* ctl,
                                               const double* partials,
                               int nblk, int stage, int mode, double* red) {
-  double F[1];
-  sum_partials<1>(partials, nblk, F, red);
+  (void)red;
+  // first wavefront only, lane l owns partials l, l+64, ...: the summation
+  // order does not depend on the workgroup size
+  if (threadIdx.x >= 64) return;
+  double F[1] = {0.0};
+  for (int b = threadIdx.x; b < nblk; b += 64) F[0] += partials[b];
+  for (int o = 32; o > 0; o >>= 1) F[0] += __shfl_xor(F[0], o, 64);
   if (threadIdx.x != 0) return;
   if (mode == 0) {
     if (ctl->ahist && P.method == 0) {
@@ -965,18 +970,18 @@ __global__ __launch_bounds__(NR >= 32 ? 512 : 1024) void k_xfield_w(
     const float2* __restrict__ tw, int logTw) {
   extern __shared__ float bdl[];
   if (ctl->done) return;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
   xfield_w_body<NR>(P, ys, spec, ctl, partials, stage, R, E, tw, logTw,
-                    xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, bdl);
+                    tile, tile, bdl);
 }
 
 // End of a step, one workgroup: RK4 commit and record (kind 2) or the
 // Dormand-Prince step controller (kind 3), from the k_xfield partials.
-template <int T>
-__global__ __launch_bounds__(T) void k_finish_step(
-    Prm P, Ctl* __restrict__ ctl, const double* __restrict__ partials,
-    int nblk, int kind, double* __restrict__ rec) {
+// `ndone` (optional) counts the runs this call finishes.
+__device__ __forceinline__ void finish_step_body(
+    const Prm& P, Ctl* __restrict__ ctl, const double* __restrict__ partials,
+    int nblk, int kind, double* __restrict__ rec, int* __restrict__ ndone) {
   __shared__ double red[16 * 3];
-  if (ctl->done) return;
   const int N = P.ncell;
   double S[3] = {0.0, 0.0, 0.0};
   double errm = 0.0;
@@ -999,6 +1004,7 @@ __global__ __launch_bounds__(T) void k_finish_step(
     c->accepted += 1;
     if (c->accepted >= c->loss_n0 && c->accepted <= c->loss_n1)
       c->loss_acc += c->a_re * c->a_re + c->a_im * c->a_im;
+    if (c->max_accepted > 0 && c->accepted >= c->max_accepted) c->done = 1;
     const double s0 = S[0], s1 = S[1], s2 = S[2];
     if (!(isfinite(s0) && isfinite(s1) && isfinite(s2))) {
       c->status = ST_NONFINITE;
@@ -1055,18 +1061,29 @@ __global__ __launch_bounds__(T) void k_finish_step(
     c->as_re[2] = c->a_re + dtn * c_dp_a[2][0] * c->ka_re[1];
     c->as_im[2] = c->a_im + dtn * c_dp_a[2][0] * c->ka_im[1];
   }
+  if (ndone && c->done) atomicAdd(ndone, 1);
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void k_finish_step(
+    Prm P, Ctl* __restrict__ ctl, const double* __restrict__ partials,
+    int nblk, int kind, double* __restrict__ rec) {
+  if (ctl->done) return;
+  finish_step_body(P, ctl, partials, nblk, kind, rec, nullptr);
 }
 
 // ================================================================= k_begin
 // Start of a Dormand-Prince attempt: commit an accepted step (renormalise
 // y7 into y_n, FSAL k7 -> k1, record), form y2 = y_n + dt a21 k1.
 // Requires N % 4 == 0 for the vector path (scalar tail otherwise).
+// Workgroup `blk` of `nblk` (grid-stride over the cells of one run).
 template <int T>
-__global__ __launch_bounds__(T) void k_begin(
-    Prm P, float* __restrict__ yn, float* __restrict__ k1,
+__device__ __forceinline__ void begin_body(
+    const Prm& P, float* __restrict__ yn, float* __restrict__ k1,
     const float* __restrict__ y7, const float* __restrict__ k7,
     float* __restrict__ y2, Ctl* __restrict__ ctl,
-    double* __restrict__ partials, double* __restrict__ rec) {
+    double* __restrict__ partials, double* __restrict__ rec, int blk,
+    int nblk) {
   __shared__ double red[16 * 3];
   __shared__ bool amlast;
   const int pend = ctl->pending_accept;
@@ -1079,11 +1096,11 @@ __global__ __launch_bounds__(T) void k_begin(
   const float c21 = (float)(ctl->dt * c_dp_a[2][0]);
   double acc[3] = {0.0, 0.0, 0.0};
   const int n4 = N >> 2;
-  const int stride = gridDim.x * T;
+  const int stride = nblk * T;
   // component planes as float4 (N % 4 == 0 checked by the host; the
   // remainder loop below covers the rest)
   const int nvec = (N % 4 == 0) ? n4 : 0;
-  for (int q = blockIdx.x * T + threadIdx.x; q < nvec; q += stride) {
+  for (int q = blk * T + threadIdx.x; q < nvec; q += stride) {
     float4 m[3], k[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -1119,7 +1136,7 @@ __global__ __launch_bounds__(T) void k_begin(
       }
     }
   }
-  for (int i = 4 * nvec + blockIdx.x * T + threadIdx.x; i < N; i += stride) {
+  for (int i = 4 * nvec + blk * T + threadIdx.x; i < N; i += stride) {
     float mx, my, mz, kx, ky, kz;
     if (pend) {
       mx = y7[i]; my = y7[N + i]; mz = y7[2 * N + i];
@@ -1143,7 +1160,7 @@ __global__ __launch_bounds__(T) void k_begin(
     // every block saw pend = 1; clear it from the last one to arrive
     if (threadIdx.x == 0) {
       const unsigned int prev = atomicAdd(&ctl->cnt_begin, 1u);
-      if (prev == gridDim.x - 1) {
+      if (prev == nblk - 1) {
         ctl->pending_accept = 0;
         ctl->cnt_begin = 0;
       }
@@ -1152,13 +1169,13 @@ __global__ __launch_bounds__(T) void k_begin(
   }
   block_sum<3>(acc, red);
   if (threadIdx.x == 0) {
-    partials[3 * blockIdx.x + 0] = acc[0];
-    partials[3 * blockIdx.x + 1] = acc[1];
-    partials[3 * blockIdx.x + 2] = acc[2];
+    partials[3 * blk + 0] = acc[0];
+    partials[3 * blk + 1] = acc[1];
+    partials[3 * blk + 2] = acc[2];
   }
-  if (!last_block(&ctl->cnt_begin, gridDim.x, &amlast)) return;
+  if (!last_block(&ctl->cnt_begin, nblk, &amlast)) return;
   double S[3];
-  sum_partials<3>(partials, gridDim.x, S, red);
+  sum_partials<3>(partials, nblk, S, red);
   if (threadIdx.x != 0) return;
   {
     double* row = rec + 6 * (size_t)ctl->nrec;
@@ -1172,6 +1189,16 @@ __global__ __launch_bounds__(T) void k_begin(
   }
   ctl->pending_accept = 0;
   ctl->cnt_begin = 0;
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void k_begin(
+    Prm P, float* __restrict__ yn, float* __restrict__ k1,
+    const float* __restrict__ y7, const float* __restrict__ k7,
+    float* __restrict__ y2, Ctl* __restrict__ ctl,
+    double* __restrict__ partials, double* __restrict__ rec) {
+  begin_body<T>(P, yn, k1, y7, k7, y2, ctl, partials, rec, blockIdx.x,
+                gridDim.x);
 }
 
 // ================================================================ k_record

@@ -26,7 +26,10 @@ EXPORTED = ("llgc_create", "llgc_destroy", "llgc_last_error",
             "llgc_reset_cavity", "llgc_cavity_enabled", "llgc_run",
             "llgc_step", "llgc_eval_rhs", "llgc_adjoint", "llgc_demag_kernel",
             "llgc_demag_tensor", "llgc_set_timing", "llgc_kernel_times",
-            "llgc_plan_info")
+            "llgc_plan_info", "llgc_create_ex", "llgc_batch_create",
+            "llgc_batch_destroy", "llgc_batch_last_error",
+            "llgc_batch_instance", "llgc_batch_run")
+PLAN_BATCH = 1
 
 
 class Grid(ctypes.Structure):
@@ -111,6 +114,13 @@ def load():
         "llgc_kernel_times": ([vp, P(dbl), P(i64), i32, ctypes.c_char_p, i32,
                                i32], ctypes.c_int),
         "llgc_plan_info": ([vp, P(i32)], ctypes.c_int),
+        "llgc_create_ex": ([P(Grid), vp, i32, P(vp)], ctypes.c_int),
+        "llgc_batch_create": ([P(Grid), i32, vp, P(vp)], ctypes.c_int),
+        "llgc_batch_destroy": ([vp], ctypes.c_int),
+        "llgc_batch_last_error": ([vp], ctypes.c_char_p),
+        "llgc_batch_instance": ([vp, i32], vp),
+        "llgc_batch_run": ([vp, i64, dbl, i32, P(dbl), i64, P(i64),
+                            P(RunInfo), P(i32)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -118,6 +128,10 @@ def load():
         f.restype = res
     _lib = L
     return L
+
+
+def grid_of(prob) -> Grid:
+    return Grid(prob.nx, prob.ny, prob.nz, prob.dx, prob.dy, prob.dz)
 
 
 def make_params(prob, ms_map=None, ku_map=None) -> Params:
@@ -151,7 +165,10 @@ def make_params(prob, ms_map=None, ku_map=None) -> Params:
 class Sim:
     """One llgc context on the current torch CUDA/HIP device and stream."""
 
-    def __init__(self, prob, stream=None):
+    def __init__(self, prob, stream=None, batch_plan=False, _handle=None,
+                 _owner=None):
+        """`batch_plan`: use the fixed plan of batched instances (the same
+        arithmetic as this problem inside a `Batch`)."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("llgc needs a GPU: no HIP device is visible")
@@ -160,14 +177,18 @@ class Sim:
         self.prob = prob
         self.shape = (3, prob.nz, prob.ny, prob.nx)
         self.stream = stream or torch.cuda.current_stream()
-        g = Grid(prob.nx, prob.ny, prob.nz, prob.dx, prob.dy, prob.dz)
-        h = ctypes.c_void_p()
-        rc = self.L.llgc_create(ctypes.byref(g),
-                                ctypes.c_void_p(self.stream.cuda_stream),
-                                ctypes.byref(h))
-        if rc != LLGC_OK:
-            raise LLGCError(rc, "llgc_create")
-        self.h = h
+        self._owner = _owner
+        if _handle is None:
+            g = grid_of(prob)
+            h = ctypes.c_void_p()
+            rc = self.L.llgc_create_ex(
+                ctypes.byref(g), ctypes.c_void_p(self.stream.cuda_stream),
+                PLAN_BATCH if batch_plan else 0, ctypes.byref(h))
+            if rc != LLGC_OK:
+                raise LLGCError(rc, "llgc_create_ex")
+            self.h = h
+        else:
+            self.h = ctypes.c_void_p(_handle)
         self.set_params(prob)
 
     # ------------------------------------------------------------ helpers
@@ -321,7 +342,73 @@ class Sim:
 
     def close(self):
         if getattr(self, "h", None):
-            self.L.llgc_destroy(self.h)
+            if self._owner is None:        # batch instances belong to it
+                self.L.llgc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many problems of different sizes advanced together (llgc_batch_*).
+    `sims[k]` is instance k, a `Sim` owned by the batch (set_state,
+    get_state, set_params work on it as on a standalone context)."""
+
+    def __init__(self, probs, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("llgc needs a GPU: no HIP device is visible")
+        self.L = load()
+        self.n = len(probs)
+        self.stream = stream or torch.cuda.current_stream()
+        grids = (Grid * self.n)(*[grid_of(p) for p in probs])
+        h = ctypes.c_void_p()
+        rc = self.L.llgc_batch_create(
+            grids, self.n, ctypes.c_void_p(self.stream.cuda_stream),
+            ctypes.byref(h))
+        if rc != LLGC_OK:
+            raise LLGCError(rc, "llgc_batch_create")
+        self.h = h
+        self.sims = []
+        for k, p in enumerate(probs):
+            hk = self.L.llgc_batch_instance(self.h, k)
+            self.sims.append(Sim(p, self.stream, _handle=hk, _owner=self))
+
+    def run(self, nsteps=0, t_end=0.0, record_every=0, rec_cap=0,
+            check=True):
+        """Runs every instance as `Sim.run` would.  Returns (records: list
+        of (n_k, 6) arrays, infos: list of dicts, status: int32 array)."""
+        if record_every > 0 and rec_cap <= 0:
+            rec_cap = (nsteps // record_every + 2) if nsteps else 100000
+        rec = np.zeros((self.n, max(rec_cap, 1), 6))
+        nrec = (ctypes.c_int64 * self.n)()
+        info = (RunInfo * self.n)()
+        st = (ctypes.c_int32 * self.n)()
+        rc = self.L.llgc_batch_run(
+            self.h, int(nsteps), float(t_end), int(record_every),
+            rec.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            int(rec_cap), nrec, info, st)
+        if check and rc < 0:
+            msg = self.L.llgc_batch_last_error(self.h).decode()
+            raise LLGCError(rc, f"llgc_batch_run: {msg}")
+        recs = [rec[k, : nrec[k]].copy() for k in range(self.n)]
+        infos = [dict(accepted=i.accepted, rejected=i.rejected,
+                      rhs_evals=i.rhs_evals, t=i.t, dt=i.dt,
+                      last_err=i.last_err) for i in info]
+        return recs, infos, np.array(list(st), dtype=np.int32)
+
+    def last_error(self):
+        return self.L.llgc_batch_last_error(self.h).decode()
+
+    def close(self):
+        if getattr(self, "h", None):
+            for s in self.sims:
+                s.h = None
+            self.L.llgc_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -89,3 +89,24 @@ def test_sim_fails_loudly_without_gpu():
     p, _, _ = I.c1_small()
     with pytest.raises(RuntimeError):
         Sim(p)
+
+
+def test_batch_and_plan_entry_points_reject_bad_arguments():
+    llgc, L = _lib()
+    h = ctypes.c_void_p()
+    g = llgc.Grid(16, 16, 1, 1e-9, 1e-9, 1e-9)
+    # unknown plan flag; batch plan outside its size range
+    assert L.llgc_create_ex(ctypes.byref(g), None, 2, ctypes.byref(h)) == -1
+    big = llgc.Grid(200, 16, 1, 1e-9, 1e-9, 1e-9)
+    assert L.llgc_create_ex(ctypes.byref(big), None, llgc.PLAN_BATCH,
+                            ctypes.byref(h)) == -7
+    one = llgc.Grid(1, 16, 1, 1e-9, 1e-9, 1e-9)
+    assert L.llgc_create_ex(ctypes.byref(one), None, llgc.PLAN_BATCH,
+                            ctypes.byref(h)) == -7
+    assert L.llgc_batch_create(None, 1, None, ctypes.byref(h)) == -1
+    grids = (llgc.Grid * 1)(g)
+    assert L.llgc_batch_create(grids, 0, None, ctypes.byref(h)) == -1
+    assert L.llgc_batch_destroy(None) == 0
+    assert L.llgc_batch_last_error(None) == b"null batch"
+    assert L.llgc_batch_instance(None, 0) is None
+    assert L.llgc_batch_run(None, 0, 0.0, 0, None, 0, None, None, None) == -1
