@@ -63,6 +63,28 @@ def kernel_bytes(plan, prob, method, kernel):
     return 0
 
 
+def counted_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the library sources as they are now;
+    otherwise None (the kernel changed since the counters were taken)."""
+    import glob
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "film_1024x1024x2_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2410_00966_amd",
+                                           "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    for line in open(path):
+        w = line.split()
+        if (len(w) == 5 and w[0] == "traffic_bytes_per_launch"
+                and w[1] == kernel and w[3] == "sources"):
+            return float(w[2]) if w[4] == h.hexdigest()[:16] else None
+    return None
+
+
 def cpu_baseline(prob, m0):
     """The oracle on the same workload and state: one right-hand-side
     evaluation timed (tensor and FFT-kernel setup excluded), scaled to the
@@ -82,6 +104,95 @@ def cpu_baseline(prob, m0):
                         "step"))
 
 
+def bench_batched(torch, t_end, n_plain):
+    """The 512-instance size/coupling sweep (grids U{16..128}^2 x U{1..4} of
+    5 nm cells, Dormand-Prince tol 1e-6) as one batch, against a sample of
+    the same instances solved one after another with standalone contexts.
+    Set-up (contexts, demag kernels) is outside both timed regions."""
+    from paper_2410_00966_amd import inputs as I
+    from paper_2410_00966_amd.llgc import Batch, Sim
+    inst = I.c4_instances()
+    probs = [p for p, _, _ in inst]
+    m0s = [m0 for _, m0, _ in inst]
+    t_set = time.perf_counter()
+    b = Batch(probs)
+    for s, m0 in zip(b.sims, m0s):
+        s.set_state(torch.from_numpy(m0))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_set
+    t0 = time.perf_counter()
+    _, infos, st = b.run(t_end=t_end)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assert (st == 0).all(), st
+    cs = sum(p.ncells * i["accepted"] for p, i in zip(probs, infos))
+    b.close()
+    idx = np.linspace(0, len(probs) - 1, n_plain).round().astype(int)
+    wall_p, cs_p = 0.0, 0
+    for k in idx:
+        s = Sim(probs[k])
+        s.set_state(torch.from_numpy(m0s[k]))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, info = s.run(t_end=t_end)
+        torch.cuda.synchronize()
+        wall_p += time.perf_counter() - t1
+        cs_p += probs[k].ncells * info["accepted"]
+        s.close()
+    rate_b, rate_p = cs / wall, cs_p / wall_p
+    return {
+        "workload": ("512 ragged instances, grids U{16..128}^2 x U{1..4} of "
+                     "5 nm, g/wc log-uniform 1e-3..1e-1, Bz U(0,0.3) T, "
+                     f"wc/2pi 5..15 GHz, Dormand-Prince tol 1e-6 to "
+                     f"{t_end * 1e12:g} ps"),
+        "value": rate_b, "unit": "cell-steps/s",
+        "cells": int(sum(p.ncells for p in probs)),
+        "accepted_total": int(sum(i["accepted"] for i in infos)),
+        "wall_s": wall, "setup_s": round(setup_s, 2),
+        "plain": {"value": rate_p, "unit": "cell-steps/s",
+                  "sample": (f"{len(idx)} evenly spaced instances solved one "
+                             "after another, standalone contexts"),
+                  "wall_s": wall_p},
+        "speedup_vs_plain": rate_b / rate_p,
+    }
+
+
+def bench_adjoint(torch, nsteps):
+    """256x256x2 film with Ms and Ku maps, RK4 dt 1e-13 s: forward alone and
+    forward with checkpoints + discrete adjoint of the loss
+    mean |alpha_n|^2 over the last fifth of the steps."""
+    from paper_2410_00966_amd import inputs as I
+    from paper_2410_00966_amd.llgc import Sim
+    p, m0, _ = I.c5_adjoint()
+    s = Sim(p)
+    s.set_state(torch.from_numpy(m0))
+    s.run(nsteps=20)                                   # warm-up
+    s.set_state(torch.from_numpy(m0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.run(nsteps=nsteps)
+    torch.cuda.synchronize()
+    w_f = time.perf_counter() - t0
+    s.set_state(torch.from_numpy(m0))
+    n0 = nsteps - nsteps // 5 + 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = s.adjoint(nsteps, p.dt, n0, nsteps)
+    torch.cuda.synchronize()
+    w_a = time.perf_counter() - t0
+    s.close()
+    assert np.isfinite(g["loss"]) and np.isfinite(g["g_brms"]).all()
+    return {
+        "workload": ("256x256x2 cells of 4 nm, seeded Ms/Ku maps, cavity "
+                     f"9.31 GHz, RK4 dt 1e-13 s, {nsteps} steps, loss over "
+                     f"steps {n0}..{nsteps}"),
+        "fwd_value": p.ncells * nsteps / w_f,
+        "fwd_adjoint_value": p.ncells * nsteps / w_a,
+        "unit": "cell-steps/s", "steps": nsteps,
+        "fwd_s": w_f, "fwd_adjoint_s": w_a,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +202,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
                     help="skip per-kernel events (for profiler runs)")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-t-end", type=float, default=10e-12)
+    ap.add_argument("--batch-plain", type=int, default=32)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=5000)
+    ap.add_argument("--only", choices=("film", "adjoint", "batched"),
+                    help="run one leg alone (for profiler runs)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 256 MiB device to device 5 times (the "
+                         "reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not "
@@ -103,6 +224,31 @@ def main():
     from paper_2410_00966_amd.llgc import Sim
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe:
+        # 512 MiB copies; before each, 1 GiB of unrelated writes evicts the
+        # source from the 256 MB last-level (Infinity) cache so the copy's
+        # reads come from HBM
+        x = torch.ones(128 * 2 ** 20, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        flush = torch.empty(256 * 2 ** 20, dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            flush.fill_(2.0)
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": x.numel() * 4,
+                          "copy_probe_bytes_written": y.numel() * 4,
+                          "launches": 3}))
+        return
+    if args.only == "adjoint":
+        print(json.dumps({"adjoint": bench_adjoint(torch,
+                                                   args.adjoint_steps)}))
+        return
+    if args.only == "batched":
+        print(json.dumps({"batched": bench_batched(
+            torch, args.batch_t_end, args.batch_plain)}))
+        return
+    if args.only == "film":
+        args.no_adjoint = args.no_batched = args.no_cpu_baseline = True
     prob, m0, cfg = I.c3_film()
     brms = prob.brms
     # --- relaxation (untimed): alpha 0.5, no cavity coupling
@@ -172,7 +318,8 @@ def main():
         out["roofline"] = {
             "bound": "hbm", "kernel": dom,
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": counted_traffic(dom),
             "bytes_per_launch": byts, "avg_launch_us": per_launch_s * 1e6,
         }
         counts = {k: v[1] / info["accepted"] for k, v in kt.items()}
@@ -183,10 +330,15 @@ def main():
                           for k, v in kt.items()}
         out["model_bytes_per_step"] = sb
         out["effective_GBs"] = sb * args.steps / wall / 1e9
+    sim.close()
+    if not args.no_adjoint:
+        out["adjoint"] = bench_adjoint(torch, args.adjoint_steps)
+    if not args.no_batched:
+        out["batched"] = bench_batched(torch, args.batch_t_end,
+                                       args.batch_plain)
     if not args.no_cpu_baseline:
         m_host = m_relaxed.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(prob, m_host)
-    sim.close()
     print(json.dumps(out))
 
 

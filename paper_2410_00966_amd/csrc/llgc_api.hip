@@ -24,7 +24,15 @@ using namespace llgc;
 
 namespace {
 
-constexpr int kT = 256;               // x-pass / field / pointwise threads
+constexpr int kT = 256;               // pointwise / reduction threads
+#ifndef LLGC_TX
+#define LLGC_TX 512
+#endif
+#ifndef LLGC_TYMAX
+#define LLGC_TYMAX 1024
+#endif
+constexpr int kTX = LLGC_TX;          // threads of the LDS x-pass kernels
+constexpr int kTyMax = LLGC_TYMAX;    // largest LDS spectral workgroup
 constexpr int kMaxLen = 2048;         // largest padded FFT length per axis
 constexpr size_t kLdsCap = 120 * 1024; // LDS per workgroup this plan uses
 constexpr int kBatchMaxLen = 256;     // batched plan: padded length per axis
@@ -47,7 +55,8 @@ struct llgc_ctx {
   int Rf, Ri, W, Ty;
   int Ww = 1;            // kx columns per wavefront-FFT spectral block
   bool use_wy = false;   // register (wavefront) FFT along y
-  bool use_wx = false;   // register (wavefront) inverse FFT along x
+  bool use_wxf = false;  // register (wavefront) FFT in the forward x pass
+  bool use_wxi = false;  // register (wavefront) inverse FFT in the field pass
   bool batch_plan = false;  // fixed plan shared with the batched engine
   int Rw = 2;            // rows per tile of the wavefront field kernel
   int Rwf = 2;           // rows per tile of the wavefront forward x pass
@@ -146,12 +155,12 @@ int n_pointwise_blocks(const llgc_ctx* c) {
 bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 // rows per tile of whichever forward x pass runs
-int fwd_rows(const llgc_ctx* c) { return c->use_wx ? c->Rwf : c->Rf; }
+int fwd_rows(const llgc_ctx* c) { return c->use_wxf ? c->Rwf : c->Rf; }
 
 int launch_xfwd(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
                 int mode) {
   Timed tm(c, "k_xfwd");
-  if (c->use_wx) {
+  if (c->use_wxf) {
     const int R = c->Rwf;
     const size_t lds = c->P.demag ? sizeof(float2) * 3 * (R / 2) * c->Px : 0;
     dim3 g = xgrid(c, R), b(64 * 3 * (R / 2));
@@ -172,11 +181,11 @@ int launch_xfwd(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
                   (!c->ms_map || aligned16(c->ms_map));
   const size_t lds = c->P.demag ? c->lds_f : 0;
   if (v4)
-    hipLaunchKernelGGL((k_xfwd<kT, true>), xgrid(c, c->Rf), dim3(kT), lds,
+    hipLaunchKernelGGL((k_xfwd<kTX, true>), xgrid(c, c->Rf), dim3(kTX), lds,
                        c->stream, c->P, ys, c->spec, ctl, c->partials, stage,
                        c->Rf, c->tw, c->logTw, mode);
   else
-    hipLaunchKernelGGL((k_xfwd<kT, false>), xgrid(c, c->Rf), dim3(kT), lds,
+    hipLaunchKernelGGL((k_xfwd<kTX, false>), xgrid(c, c->Rf), dim3(kTX), lds,
                        c->stream, c->P, ys, c->spec, ctl, c->partials, stage,
                        c->Rf, c->tw, c->logTw, mode);
   return check_launch(c, "k_xfwd");
@@ -247,15 +256,18 @@ int launch_yspec(llgc_ctx* c, Ctl* ctl, int stage, int mode) {
   }
   Timed tm(c, "k_yspec");
   dim3 g((c->Hx + c->W - 1) / c->W);
+  if constexpr (kTyMax >= 1024) {
+    if (c->Ty == 1024) yspec_nz<1024>(c, ctl, g, stage, mode);
+  }
   if (c->Ty == 512) yspec_nz<512>(c, ctl, g, stage, mode);
-  else yspec_nz<256>(c, ctl, g, stage, mode);
+  else if (c->Ty == 256) yspec_nz<256>(c, ctl, g, stage, mode);
   return check_launch(c, "k_yspec");
 }
 
 int launch_xfield(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
                   const Epi& E) {
   Timed tm(c, "k_xfield");
-  if (c->use_wx) {
+  if (c->use_wxi) {
     const int R = c->Rw;
     const size_t lds = c->P.demag ? sizeof(float) * 3 * R * c->nx : 0;
     dim3 g = xgrid(c, R), b(64 * 3 * (R / 2));
@@ -272,7 +284,7 @@ int launch_xfield(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
 #undef LLGC_XW_ARGS
     return check_launch(c, "k_xfield_w");
   }
-  hipLaunchKernelGGL(k_xfield<kT>, xgrid(c, c->Ri), dim3(kT),
+  hipLaunchKernelGGL(k_xfield<kTX>, xgrid(c, c->Ri), dim3(kTX),
                      c->P.demag ? c->lds_i : 0, c->stream, c->P, ys, c->spec,
                      ctl, c->partials, c->rec, stage, c->Ri, E, c->tw,
                      c->logTw);
@@ -280,7 +292,7 @@ int launch_xfield(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
 }
 
 // rows per tile of whichever field kernel runs
-int field_rows(const llgc_ctx* c) { return c->use_wx ? c->Rw : c->Ri; }
+int field_rows(const llgc_ctx* c) { return c->use_wxi ? c->Rw : c->Ri; }
 
 int rhs_stage(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
               const Epi& E, int mode) {
@@ -610,7 +622,7 @@ int llgc_create_ex(const llgc_grid* g, void* stream, int flags,
   c->logPy = ilog2(c->Py);
   c->logTw = ilog2(std::max(c->Px, c->Py));
   // --- plan: rows per x-pass block, kx columns per spectral block
-  const int VPTT = VPT * kT;
+  const int VPTT = VPT * kTX;
   int npf = std::max(1, std::min(8, VPTT / c->Px));
   int npi = std::max(1, std::min(8, VPTT / (3 * c->Px)));
   if (npf * c->Px > VPTT || 3 * npi * c->Px > VPTT) {
@@ -631,28 +643,38 @@ int llgc_create_ex(const llgc_grid* g, void* stream, int flags,
   if (const char* s = getenv("LLGC_RI"))
     c->Ri = std::min(2 * npi, std::max(2, (atoi(s) + 1) & ~1));
   const int col = 3 * c->nz * c->Py;
-  int W = std::max(1, std::min(16384 / col, (int)(kLdsCap / (9 * col))));
+  const int ycap = VPTY * kTyMax;       // complex values one workgroup holds
+  int W = std::max(1, std::min(ycap / col, (int)(kLdsCap / (9 * col))));
   while (W > 1 && (c->Hx + W - 1) / W < 256) --W;
   if (const char* s = getenv("LLGC_W"))
-    W = std::max(1, std::min(atoi(s), 16384 / col));
+    W = std::max(1, std::min(atoi(s), ycap / col));
   c->W = W;
-  c->Ty = (W * col > VPT * 256) ? 512 : 256;
-  // columns of 64..2048 points: one wavefront per column, FFT in registers
-  c->use_wy = c->Py >= 64 && c->Py <= kMaxLen && !getenv("LLGC_LDS_YFFT") &&
-              (c->Py < 2048 || c->nz <= 2);  // 2048: 8 wavefronts at most
+  c->Ty = 256;
+  while (c->Ty < kTyMax && W * col > VPTY * c->Ty) c->Ty *= 2;
+  // One wavefront per transform with the FFT in registers where that was
+  // measured faster than the LDS Stockham kernels (gfx950, DP45 steps of
+  // 64^2 x 4 ... 1024^2 x 2 grids): y columns of 128..512 points, forward
+  // x rows of 64..512, field-pass x rows of 64..128.  Longer transforms
+  // need 128+ VGPRs per lane in registers (2 waves per SIMD) and lose.
+  const bool lds_y = getenv("LLGC_LDS_YFFT") != nullptr;
+  const bool lds_x = getenv("LLGC_LDS_XFFT") != nullptr;
+  const bool wave_all = getenv("LLGC_WAVE_FFT") != nullptr;
+  c->use_wy = !lds_y && (wave_all ? (c->Py >= 64 && (c->Py < 2048 || c->nz <= 2))
+                                  : (c->Py >= 128 && c->Py <= 512));
   c->Ww = std::max(1, 6 / (3 * c->nz));
-  c->use_wx = c->Px >= 64 && c->Px <= kMaxLen && !getenv("LLGC_LDS_XFFT");
+  c->use_wxf = !lds_x && c->Px >= 64 && (wave_all || c->Px <= 512);
+  c->use_wxi = !lds_x && c->Px >= 64 && (wave_all || c->Px <= 128);
   c->Rw = (((c->ny + 3) / 4) * c->nz >= 512) ? 4 : 2;
   if (const char* s = getenv("LLGC_RW")) c->Rw = (atoi(s) >= 4) ? 4 : 2;
   c->Rwf = 2;
   if (const char* s = getenv("LLGC_RWF")) c->Rwf = (atoi(s) >= 4) ? 4 : 2;
   if (bplan) {
     // the fixed plan of every batched instance (no tuning overrides)
-    c->use_wx = c->use_wy = true;
+    c->use_wxf = c->use_wxi = c->use_wy = true;
     c->Rw = c->Rwf = kBatchRows;
     c->Ww = std::max(1, kBatchYWaves / (3 * c->nz));
   }
-  if (W * col > VPT * 512) {
+  if (W * col > ycap) {
     delete c;
     return LLGC_E_UNSUPPORTED;
   }
@@ -669,17 +691,18 @@ int llgc_create_ex(const llgc_grid* g, void* stream, int flags,
     delete c;
     return LLGC_E_UNSUPPORTED;
   }
-  hipFuncSetAttribute((const void*)k_xfwd<kT, true>,
+  hipFuncSetAttribute((const void*)k_xfwd<kTX, true>,
                       hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)c->lds_f);
-  hipFuncSetAttribute((const void*)k_xfwd<kT, false>,
+  hipFuncSetAttribute((const void*)k_xfwd<kTX, false>,
                       hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)c->lds_f);
-  hipFuncSetAttribute((const void*)k_xfield<kT>,
+  hipFuncSetAttribute((const void*)k_xfield<kTX>,
                       hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)c->lds_i);
   yspec_attr<256>(c->lds_y);
   yspec_attr<512>(c->lds_y);
+  if constexpr (kTyMax >= 1024) yspec_attr<1024>(c->lds_y);
   // --- buffers
   const size_t n3 = (size_t)3 * c->N;
   bool ok = hipMalloc(&c->yn, n3 * 4) == hipSuccess &&
@@ -1123,7 +1146,7 @@ int llgc_plan_info(const llgc_ctx* c, int32_t* info) {
   info[1] = c->Py;
   info[2] = c->Rf;
   info[3] = c->W;
-  info[4] = kT;
+  info[4] = kTX;
   info[5] = c->Ty;
   info[6] = (int32_t)c->lds_f;
   info[7] = (int32_t)c->lds_y;
@@ -1184,7 +1207,7 @@ extern "C" int llgc_adjoint(llgc_ctx* c, int64_t n_steps, double dt,
     return fail(c, LLGC_E_STATE, "set params and state before llgc_adjoint");
   if (n_steps < 1 || n0 < 1 || n1 < n0 || n1 > n_steps || !(dt > 0))
     return fail(c, LLGC_E_ARG, "bad step count, window or dt");
-  if (!c->use_wx)
+  if (c->Px < 64)
     return fail(c, LLGC_E_UNSUPPORTED, "adjoint needs padded nx >= 64");
   if (stride <= 0) stride = (int64_t)std::ceil(std::sqrt((double)n_steps));
   const int64_t S = stride;

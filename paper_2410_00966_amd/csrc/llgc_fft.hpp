@@ -137,7 +137,8 @@ __device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
 // Full transform: dir = -1 forward (exp(-i...)), +1 inverse (unnormalised).
 // VPT = complex values a thread may hold (register budget per pass).
 template <int VPT>
-__device__ void fft_lds(float2* s, int logL, int batch, const float2* tw,
+__device__ __forceinline__ void fft_lds(float2* s, int logL, int batch,
+                                        const float2* tw,
                         int logTw, float dir) {
   if (logL == 0) return;
   int logNs = 0;

@@ -29,7 +29,15 @@
 
 namespace llgc {
 
-constexpr int VPT = 32;   // complex values per thread in an FFT pass
+#ifndef LLGC_VPT
+#define LLGC_VPT 16
+#endif
+#ifndef LLGC_VPTY
+#define LLGC_VPTY LLGC_VPT
+#endif
+// complex values a thread holds in one LDS FFT pass: x-pass kernels, y pass
+constexpr int VPT = LLGC_VPT;
+constexpr int VPTY = LLGC_VPTY;
 
 // ---------------------------------------------------------------- tableaus
 // classic RK4
@@ -530,7 +538,7 @@ __global__ __launch_bounds__(T) void k_yspec(
     for (int e = threadIdx.x; e < ncol; e += T) lds[pidx(e)] = src[(size_t)e * nyp];
   }
   __syncthreads();
-  fft_lds<VPT>(lds, P.logPy, ncol, tw, logTw, -1.f);
+  fft_lds<VPTY>(lds, P.logPy, ncol, tw, logTw, -1.f);
   // pointwise product: per (w, ky), all 3*nz values
   constexpr int nz3 = 3 * NZ;
   const int Hy = P.Hy;
@@ -579,7 +587,7 @@ __global__ __launch_bounds__(T) void k_yspec(
     for (int q = 0; q < nz3; ++q) lds[pidx((w * nz3 + q) * Py + ky)] = Hf[q];
   }
   __syncthreads();
-  fft_lds<VPT>(lds, P.logPy, ncol, tw, logTw, 1.f);
+  fft_lds<VPTY>(lds, P.logPy, ncol, tw, logTw, 1.f);
   float2* dst = spec + (size_t)kx0 * nz * 3 * nyp;
   if (Py >= 2) {
     const int hq = nyp >> 1;          // row pairs actually stored
