@@ -157,6 +157,29 @@ def bench_batched(torch, t_end, n_plain):
     }
 
 
+def bench_wire(torch, nsteps):
+    """Nanowire 512x32x4 of 4 nm (Ku along x, cavity at its uniform mode,
+    sinc cavity drive), Dormand-Prince tol 1e-6: forward cell-steps/s."""
+    from paper_2410_00966_amd import inputs as I
+    from paper_2410_00966_amd.llgc import Sim
+    p, m0, _ = I.c2_nanowire()
+    s = Sim(p)
+    s.set_state(torch.from_numpy(m0))
+    s.run(nsteps=20, t_end=1.0)                        # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info = s.run(nsteps=nsteps, t_end=1.0)
+    torch.cuda.synchronize()
+    w = time.perf_counter() - t0
+    s.close()
+    return {"workload": ("nanowire 512x32x4 cells of 4 nm, Ku 5e3 J/m^3 x, "
+                         "cavity at the uniform mode, g/wc=0.02, sinc cavity "
+                         "drive, Dormand-Prince tol 1e-6"),
+            "value": p.ncells * info["accepted"] / w, "unit": "cell-steps/s",
+            "accepted": info["accepted"], "rejected": info["rejected"],
+            "ms_per_step": 1e3 * w / info["accepted"]}
+
+
 def bench_adjoint(torch, nsteps):
     """256x256x2 film with Ms and Ku maps, RK4 dt 1e-13 s: forward alone and
     forward with checkpoints + discrete adjoint of the loss
@@ -205,6 +228,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-t-end", type=float, default=10e-12)
     ap.add_argument("--batch-plain", type=int, default=32)
+    ap.add_argument("--no-wire", action="store_true")
+    ap.add_argument("--wire-steps", type=int, default=400)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=5000)
     ap.add_argument("--only", choices=("film", "adjoint", "batched"),
@@ -249,6 +274,7 @@ def main():
         return
     if args.only == "film":
         args.no_adjoint = args.no_batched = args.no_cpu_baseline = True
+        args.no_wire = True
     prob, m0, cfg = I.c3_film()
     brms = prob.brms
     # --- relaxation (untimed): alpha 0.5, no cavity coupling
@@ -331,6 +357,8 @@ def main():
         out["model_bytes_per_step"] = sb
         out["effective_GBs"] = sb * args.steps / wall / 1e9
     sim.close()
+    if not args.no_wire:
+        out["wire"] = bench_wire(torch, args.wire_steps)
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(torch, args.adjoint_steps)
     if not args.no_batched:

@@ -150,6 +150,6 @@ def gradient(prob, m0, a0, dt, nsteps, window, brms_dir):
                         requires_grad=True)
     L, _, _ = o.loss(m0, a0, dt, nsteps, window, ms, ku, bmag * bdir, eps0)
     L.backward()
-    return dict(loss=float(L), g_ms=ms.grad.numpy().copy(),
+    return dict(loss=float(L.detach()), g_ms=ms.grad.numpy().copy(),
                 g_ku=ku.grad.numpy().copy(), g_brms=float(bmag.grad),
                 g_eps0=float(eps0.grad))

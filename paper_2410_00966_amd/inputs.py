@@ -193,8 +193,8 @@ def smooth_map(nx: int, ny: int, nz: int, lo: float, hi: float, nmodes: int,
 
 # ---------------------------------------------------------------------------
 # Workload definitions.  Sizes and parameters follow the five synthetic
-# workloads the path is measured on; values the workload text leaves open are
-# the readings listed in the design notes.
+# workloads the path is measured on; where a workload leaves a value open,
+# the choice is stated at the workload.
 # ---------------------------------------------------------------------------
 
 # Cavity frequency of the small plain workload: the small-angle Kittel
@@ -232,12 +232,29 @@ def c3_film() -> tuple:
     return p, m0, dict(t_end=5e-9, relax_t=0.5e-9, relax_alpha=0.5)
 
 
+# uniform-mode frequency of the nanowire (prism factors, anisotropy field),
+# frozen from tests/golden/c2_uniform_mode_hz.txt
+C2_WC = 2.0 * math.pi * 9.897394623e9
+
+
 def c2_nanowire() -> tuple:
-    """512x32x4 cells of 4 nm, Ku1 5e3 J/m^3 along x, alpha 0.005, DP45."""
+    """512x32x4 cells of 4 nm, Ku1 5e3 J/m^3 along x, alpha 0.005, DP45;
+    cavity at the wire's uniform-mode frequency, g/wc = 0.02 with B_rms
+    along y, driven by a sinc pulse of 20 GHz bandwidth whose amplitude
+    gives a free-cavity field 2 |B_rms| |alpha| of about 1 mT."""
     p = Problem(nx=512, ny=32, nz=4, dx=4e-9, dy=4e-9, dz=4e-9,
                 ms=8.0e5, aex=1.3e-11, alpha=0.005, ku1=5e3,
                 anis_u=(1.0, 0.0, 0.0), bext=(0.0, 0.0, 0.0),
                 method=METHOD_DP45, tol=1e-6, dt=1e-14)
+    p.wc = C2_WC
+    p.kappa = 1e-3 * p.wc
+    b = brms_from_g(0.02 * p.wc, p.ms * p.ncells * p.vcell)
+    p.brms = (0.0, b, 0.0)
+    p.cdrive_kind = DRIVE_SINC
+    p.cdrive_w = 2.0 * math.pi * 20e9
+    # a sinc pulse of cut-off w delivers |alpha| ~ pi eps0 / (2 w) to a
+    # resonator below the cut-off
+    p.cdrive_amp = 1e-3 / (2.0 * b) * 2.0 * p.cdrive_w / math.pi
     m0 = tilted_uniform_state(p.shape, 0.0, 1e-3, seed=1002, axis="x",
                               toward="y")
     return p, m0, dict(t_end=10e-9)

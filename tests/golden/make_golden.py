@@ -34,10 +34,33 @@ def c1_kittel():
     return om / (2 * math.pi)
 
 
-if __name__ == "__main__":
-    f = c1_kittel()
-    with open(os.path.join(HERE, "c1_kittel_hz.txt"), "w") as fh:
-        fh.write("# Kittel frequency (Hz) of the small film workload, written by\n"
-                 "# tests/golden/make_golden.py from the oracle's tensor\n")
+def c2_uniform_mode():
+    """Uniform-mode (Kittel) frequency of the 512x32x4 nanowire of 4 nm
+    cells magnetised along its axis x by its anisotropy field 2 Ku/Ms
+    (Ku 5e3 J/m^3, Ms 8e5 A/m, no applied field), with the prism's
+    demagnetising factors from Aharoni's closed form."""
+    a, b, c = 512 * 4e-9 / 2, 32 * 4e-9 / 2, 4 * 4e-9 / 2
+    nxx = D.aharoni_prism_factor(b, c, a)
+    nyy = D.aharoni_prism_factor(c, a, b)
+    nzz = D.aharoni_prism_factor(a, b, c)
+    ms, ku = 8e5, 5e3
+    mu0ms = I.MU0 * ms
+    bk = 2 * ku / ms
+    om = I.GAMMA * math.sqrt((bk + (nyy - nxx) * mu0ms) *
+                             (bk + (nzz - nxx) * mu0ms))
+    return om / (2 * math.pi)
+
+
+def _write(name, what, f):
+    with open(os.path.join(HERE, name), "w") as fh:
+        fh.write(f"# {what} (Hz), written by\n"
+                 "# tests/golden/make_golden.py from the oracle\n")
         fh.write(f"{f:.9e}\n")
-    print(f)
+    print(name, f)
+
+
+if __name__ == "__main__":
+    _write("c1_kittel_hz.txt", "Kittel frequency of the small film workload",
+           c1_kittel())
+    _write("c2_uniform_mode_hz.txt",
+           "uniform-mode frequency of the nanowire workload", c2_uniform_mode())

@@ -1,0 +1,91 @@
+"""GPU parity at the full workload sizes, on outputs the FP64 oracle can
+compute in seconds:
+  * one right-hand-side evaluation (dm/dt per cell, B_eff per cell, d alpha
+    / dt) of the nanowire 512x32x4, the mapped film 256x256x2 and the
+    textured film 1024x1024x2, from their initial states with a non-zero
+    cavity amplitude, in the launch configuration the benchmark uses;
+  * the first accepted Dormand-Prince step of the textured film: the GPU's
+    step size replayed in the oracle, final state per cell.
+Tolerances as the small-grid parity tests: 2e-5 of the largest magnitude for
+fields and rates (FP32 FFT of 2048-point transforms against FP64), 1e-5 per
+cell after one step.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2410_00966_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+_ORACLES = {}
+
+
+def _oracle(name, p):
+    from oracle.llg import CavityLLG
+    if name not in _ORACLES:
+        _ORACLES[name] = CavityLLG(p, demag="fft")
+    return _ORACLES[name]
+
+
+WORKLOADS = {"nanowire": I.c2_nanowire, "mapped_film": I.c5_adjoint,
+             "textured_film": I.c3_film}
+
+
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_full_size_rhs(torch, name):
+    from paper_2410_00966_amd.llgc import Sim
+    r = WORKLOADS[name]()
+    p, m0 = r[0], r[1]
+    if not any(p.brms):
+        p.brms = (0.0, 1e-4, 0.0)
+    a = 0.7 - 0.4j
+    _say("full-size rhs", name, p.shape)
+    s = Sim(p)
+    dm, B, da = s.eval_rhs(torch.from_numpy(m0), a, 3e-12)
+    s.close()
+    o = _oracle(name, p)
+    dref, aref = o.rhs(m0.astype(np.float64), a, 3e-12)
+    Bref = o.effective_field(m0.astype(np.float64), a, 3e-12)
+    dm = dm.cpu().numpy()
+    B = B.cpu().numpy()
+    ed = np.abs(dm - dref).max() / np.abs(dref).max()
+    eB = np.abs(B - Bref).max() / np.abs(Bref).max()
+    _say(f"  rel err dm/dt {ed:.2e}  B {eB:.2e}  da {abs(da - aref):.3e}")
+    assert ed < 2e-5 and eB < 2e-5
+    assert abs(da - aref) <= 1e-9 * abs(aref)
+
+
+def test_full_size_first_dp45_step_of_the_textured_film(torch):
+    from paper_2410_00966_amd.llgc import Sim
+    p, m0, _ = I.c3_film()
+    _say("full-size first DP45 step", p.shape)
+    s = Sim(p)
+    s.set_state(torch.from_numpy(m0), 0.0, 0.2 + 0.1j)
+    _, info = s.run(nsteps=1, t_end=1.0)
+    m, t, a = s.get_state()
+    s.close()
+    assert info["accepted"] == 1
+    o = _oracle("textured_film", p)
+    mref, aref, tref = o.run_dp45_replay(m0.astype(np.float64), 0.2 + 0.1j,
+                                         [t])
+    dm = np.abs(m.cpu().numpy() - mref).max()
+    _say(f"  h = {t:.3e} s, rejected {info['rejected']}, max|dm| {dm:.2e}, "
+         f"|da| {abs(a - aref):.2e}")
+    assert dm < 1e-5
+    assert abs(a - aref) < 1e-7 * max(1.0, abs(aref))

@@ -388,3 +388,18 @@ def test_golden_dicke_worked_example(row):
         m, _ = _relax_macrospin(wz, lam, kappa, 0.5, [0.3, 0.0, 0.95],
                                 4e-9, 2e-13)
         assert abs(m[0]) == pytest.approx(mx_eq, abs=2e-6)
+
+
+def test_frozen_cavity_frequencies_match_golden_files():
+    """The cavity frequencies the inputs module hard-codes are the values
+    tests/golden/make_golden.py wrote from the oracle."""
+    import os
+    g = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+    def read(name):
+        return float([l for l in open(os.path.join(g, name))
+                      if not l.startswith("#")][0])
+    assert I.C1_WC == pytest.approx(2 * math.pi * read("c1_kittel_hz.txt"),
+                                    rel=1e-9)
+    assert I.C2_WC == pytest.approx(
+        2 * math.pi * read("c2_uniform_mode_hz.txt"), rel=1e-9)
