@@ -33,6 +33,7 @@ constexpr int kT = 256;               // pointwise / reduction threads
 #endif
 constexpr int kTX = LLGC_TX;          // threads of the LDS x-pass kernels
 constexpr int kTyMax = LLGC_TYMAX;    // largest LDS spectral workgroup
+constexpr int kYhEpt = 12;            // split y pass: elements per thread
 constexpr int kMaxLen = 2048;         // largest padded FFT length per axis
 constexpr size_t kLdsCap = 120 * 1024; // LDS per workgroup this plan uses
 constexpr int kBatchMaxLen = 256;     // batched plan: padded length per axis
@@ -58,6 +59,9 @@ struct llgc_ctx {
   bool use_wxf = false;  // register (wavefront) FFT in the forward x pass
   bool use_wxi = false;  // register (wavefront) inverse FFT in the field pass
   bool batch_plan = false;  // fixed plan shared with the batched engine
+  bool yhalf = false;    // LDS spectral pass split by ky parity (k_yspec_h)
+  int Tyh = 512;         // its workgroup size
+  size_t lds_yh = 0;     // its LDS bytes
   int Rw = 2;            // rows per tile of the wavefront field kernel
   int Rwf = 2;           // rows per tile of the wavefront forward x pass
   size_t lds_f, lds_i, lds_y;
@@ -256,6 +260,28 @@ int launch_yspec(llgc_ctx* c, Ctl* ctl, int stage, int mode) {
   }
   Timed tm(c, "k_yspec");
   dim3 g((c->Hx + c->W - 1) / c->W);
+  if (c->yhalf) {
+    const int nf = (int)xgrid(c, fwd_rows(c)).x;
+#define LLGC_YH_ARGS c->P, c->spec, c->K, ctl, c->W, c->tw, c->logTw, \
+                     c->partials, nf, stage, mode
+#define LLGC_YH(TT, EE)                                                      \
+    switch (c->nz) {                                                        \
+      case 1: hipLaunchKernelGGL((k_yspec_h<TT, 1, EE>), g, dim3(TT), c->lds_yh, c->stream, LLGC_YH_ARGS); break; \
+      case 2: hipLaunchKernelGGL((k_yspec_h<TT, 2, EE>), g, dim3(TT), c->lds_yh, c->stream, LLGC_YH_ARGS); break; \
+      default: hipLaunchKernelGGL((k_yspec_h<TT, 3, EE>), g, dim3(TT), c->lds_yh, c->stream, LLGC_YH_ARGS); break; \
+    }
+    if (c->nz == 4) {
+      hipLaunchKernelGGL((k_yspec_h<1024, 4, kYhEpt>), g, dim3(1024),
+                         c->lds_yh, c->stream, LLGC_YH_ARGS);
+    } else if (c->Tyh == 1024) { LLGC_YH(1024, kYhEpt) }
+    else { LLGC_YH(512, kYhEpt) }
+#undef LLGC_YH
+#undef LLGC_YH_ARGS
+    return check_launch(c, "k_yspec_h");
+  }
+  // k_yspec pairs the real columns kx = 0 and Px/2 into one slot
+  const int nslot = c->Px >= 2 ? c->Px / 2 : c->Hx;
+  g = dim3((nslot + c->W - 1) / c->W);
   if constexpr (kTyMax >= 1024) {
     if (c->Ty == 1024) yspec_nz<1024>(c, ctl, g, stage, mode);
   }
@@ -674,18 +700,38 @@ int llgc_create_ex(const llgc_grid* g, void* stream, int flags,
     c->Rw = c->Rwf = kBatchRows;
     c->Ww = std::max(1, kBatchYWaves / (3 * c->nz));
   }
-  if (W * col > ycap) {
+  // the ky-parity split of the LDS spectral pass: half the LDS per
+  // workgroup (two workgroups per CU) for long columns
+  {
+    const int hcol = W * 3 * c->nz * (c->Py / 2);
+    // 512 or 1024 threads, up to 12 elements each (the instances that
+    // compile without register spills: nz <= 3)
+    c->Tyh = hcol > kYhEpt * 512 ? 1024 : 512;
+    const char* s = getenv("LLGC_YHALF");
+    const bool fits = !c->use_wy && c->Py >= 4 &&
+                      hcol <= kYhEpt * c->Tyh && hcol <= VPTY * c->Tyh;
+    // used where a whole column set exceeds one workgroup (nz = 3, 4 at
+    // 2048 points); elsewhere the unsplit pass measured faster
+    c->yhalf = fits && ((W * col > ycap) || (c->nz <= 3 && s && atoi(s)));
+    c->lds_yh = sizeof(float2) * (lds_twiddles(c->logTw) +
+                                  padded_len((size_t)hcol));
+  }
+  if (!c->use_wy && !c->yhalf && W * col > ycap) {
     delete c;
     return LLGC_E_UNSUPPORTED;
   }
-  c->lds_f = sizeof(float2) * padded_len((size_t)(c->Rf / 2) * c->Px);
-  c->lds_i = sizeof(float2) * padded_len((size_t)3 * (c->Ri / 2) * c->Px);
-  c->lds_y = sizeof(float2) * padded_len((size_t)W * col);
+  const size_t twb = sizeof(float2) * lds_twiddles(c->logTw);  // LDS twiddles
+  c->lds_f = twb + sizeof(float2) * padded_len((size_t)(c->Rf / 2) * c->Px);
+  c->lds_i = twb + sizeof(float2) * padded_len((size_t)3 * (c->Ri / 2) * c->Px);
+  c->lds_y = twb + sizeof(float2) * padded_len((size_t)W * col);
   int dev = 0, maxlds = 65536;
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock,
                         dev);
-  size_t need = std::max(c->lds_f, std::max(c->lds_i, c->lds_y));
+  // LDS of the kernels this plan launches
+  const size_t need_y = c->use_wy ? 0 : (c->yhalf ? c->lds_yh : c->lds_y);
+  size_t need = std::max(c->use_wxf ? 0 : c->lds_f,
+                         std::max(c->use_wxi ? 0 : c->lds_i, need_y));
   if (need > (size_t)std::max(maxlds, 65536) && need > 65536) {
     c->err = "plan needs more LDS than the device offers";
     delete c;
@@ -700,9 +746,21 @@ int llgc_create_ex(const llgc_grid* g, void* stream, int flags,
   hipFuncSetAttribute((const void*)k_xfield<kTX>,
                       hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)c->lds_i);
-  yspec_attr<256>(c->lds_y);
-  yspec_attr<512>(c->lds_y);
-  if constexpr (kTyMax >= 1024) yspec_attr<1024>(c->lds_y);
+  if (c->yhalf) {
+    const void* fs[] = {
+        (const void*)k_yspec_h<512, 1, kYhEpt>, (const void*)k_yspec_h<512, 2, kYhEpt>,
+        (const void*)k_yspec_h<512, 3, kYhEpt>, (const void*)k_yspec_h<1024, 1, kYhEpt>,
+        (const void*)k_yspec_h<1024, 2, kYhEpt>, (const void*)k_yspec_h<1024, 3, kYhEpt>,
+        (const void*)k_yspec_h<1024, 4, kYhEpt>};
+    for (const void* f : fs)
+      hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)c->lds_yh);
+  }
+  if (!c->use_wy && !c->yhalf) {
+    yspec_attr<256>(c->lds_y);
+    yspec_attr<512>(c->lds_y);
+    if constexpr (kTyMax >= 1024) yspec_attr<1024>(c->lds_y);
+  }
   // --- buffers
   const size_t n3 = (size_t)3 * c->N;
   bool ok = hipMalloc(&c->yn, n3 * 4) == hipSuccess &&
@@ -1147,9 +1205,9 @@ int llgc_plan_info(const llgc_ctx* c, int32_t* info) {
   info[2] = c->Rf;
   info[3] = c->W;
   info[4] = kTX;
-  info[5] = c->Ty;
+  info[5] = c->yhalf ? c->Tyh : c->Ty;
   info[6] = (int32_t)c->lds_f;
-  info[7] = (int32_t)c->lds_y;
+  info[7] = (int32_t)(c->yhalf ? c->lds_yh : c->lds_y);
   return LLGC_OK;
 }
 

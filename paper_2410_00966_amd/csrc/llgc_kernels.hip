@@ -39,6 +39,22 @@ namespace llgc {
 constexpr int VPT = LLGC_VPT;
 constexpr int VPTY = LLGC_VPTY;
 
+// The Stockham passes of an L-point transform index the twiddle table at
+// k * Ltw / (Ns R) < Ltw / 2, so the first half of the table serves every
+// pass.  The LDS kernels copy it into the front of their LDS once, so that
+// each pass reads its twiddles from LDS rather than from global memory right
+// after a barrier.  Returns the entry count (even, so that the data after it
+// stays 16-byte aligned).
+__host__ __device__ __forceinline__ int lds_twiddles(int logTw) {
+  return logTw > 1 ? 1 << (logTw - 1) : 2;
+}
+__device__ __forceinline__ void stage_twiddles(float2* twl,
+                                               const float2* __restrict__ tw,
+                                               int logTw) {
+  const int n = 1 << (logTw > 0 ? logTw - 1 : 0);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) twl[i] = tw[i];
+}
+
 // ---------------------------------------------------------------- tableaus
 // classic RK4
 __constant__ double c_rk4_c[5] = {0.0, 0.0, 0.5, 0.5, 1.0};
@@ -243,9 +259,12 @@ __global__ __launch_bounds__(T) void k_xfwd(
     Prm P, const float* __restrict__ ys, float2* __restrict__ spec,
     Ctl* __restrict__ ctl, double* __restrict__ partials, int stage, int R,
     const float2* __restrict__ tw, int logTw, int mode) {
-  extern __shared__ float2 lds[];
+  extern __shared__ float2 lds_all[];
   __shared__ double red[16];
   if (ctl->done) return;
+  float2* twl = lds_all;
+  float2* lds = lds_all + lds_twiddles(logTw);
+  if (P.demag) stage_twiddles(twl, tw, logTw);
   const int nblk = gridDim.x;
   const int tile = xcd_tile(blockIdx.x, nblk);
   const int nz = P.nz;
@@ -331,7 +350,7 @@ __global__ __launch_bounds__(T) void k_xfwd(
     facc[0] += fc * br[c];
     if (!P.demag) continue;
     __syncthreads();
-    fft_lds<VPT>(lds, P.logPx, np, tw, logTw, -1.f);
+    fft_lds<VPT>(lds, P.logPx, np, twl, logTw, -1.f);
     // split the two real transforms and write the half spectrum: rows
     // (y0+2p, y0+2p+1) are adjacent -> one 16-byte store per (kx, p)
     const int H = P.Hx;
@@ -493,26 +512,75 @@ __global__ __launch_bounds__(T) void k_finish_stage(
 // K[kx][ky][comp][dz] (comp: xx yy zz xy xz yz; xz, yz coefficients of -i),
 // ky in [0, Py/2]; scaled by -mu0/(Px Py).  Spectrum rows have nyp (even)
 // entries; entries at y >= ny are zero and stay zero.
+// 3x3 demag-kernel product at one (kx, ky) for all nz layers.  Kp points at
+// K[kx][|ky|] (6 components x NZ offsets); sy = -1 on the mirrored half
+// (xy and yz are odd in ky); xz, yz are odd in the z offset.
+template <int NZ>
+__device__ __forceinline__ void kernel_product(const float* __restrict__ Kp,
+                                               float sy,
+                                               const float2 (&M)[3 * NZ],
+                                               float2 (&Hf)[3 * NZ]) {
+  float kk[6 * NZ];
+#pragma unroll
+  for (int q = 0; q < 6 * NZ; ++q) kk[q] = Kp[q];
+#pragma unroll
+  for (int q = 0; q < 3 * NZ; ++q) Hf[q] = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int zt = 0; zt < NZ; ++zt) {
+#pragma unroll
+    for (int zs = 0; zs < NZ; ++zs) {
+      const int d = zt - zs;
+      const int ad = d < 0 ? -d : d;
+      const float sz = d < 0 ? -1.f : 1.f;
+      const float kxx = kk[0 * NZ + ad], kyy = kk[1 * NZ + ad];
+      const float kzz = kk[2 * NZ + ad], kxy = sy * kk[3 * NZ + ad];
+      const float qxz = sz * kk[4 * NZ + ad];          // K_xz = -i qxz
+      const float qyz = sz * sy * kk[5 * NZ + ad];     // K_yz = -i qyz
+      const float2 mx = M[zs * 3 + 0], my = M[zs * 3 + 1], mz = M[zs * 3 + 2];
+      float2& hx = Hf[zt * 3 + 0];
+      float2& hy = Hf[zt * 3 + 1];
+      float2& hz = Hf[zt * 3 + 2];
+      hx.x += kxx * mx.x + kxy * my.x + qxz * mz.y;
+      hx.y += kxx * mx.y + kxy * my.y - qxz * mz.x;
+      hy.x += kxy * mx.x + kyy * my.x + qyz * mz.y;
+      hy.y += kxy * mx.y + kyy * my.y - qyz * mz.x;
+      hz.x += qxz * mx.y + qyz * my.y + kzz * mz.x;
+      hz.y += -qxz * mx.x - qyz * my.x + kzz * mz.y;
+    }
+  }
+}
+
 template <int T, int NZ>
 __global__ __launch_bounds__(T) void k_yspec(
     Prm P, float2* __restrict__ spec, const float* __restrict__ K,
     Ctl* __restrict__ ctl, int W, const float2* __restrict__ tw,
     int logTw, const double* __restrict__ partials, int nblk_f, int stage,
     int mode) {
-  extern __shared__ float2 lds[];
+  extern __shared__ float2 lds_all[];
   __shared__ double red[16];
   if (ctl->done) return;
+  float2* twl = lds_all;
+  float2* lds = lds_all + lds_twiddles(logTw);
+  stage_twiddles(twl, tw, logTw);
   // workgroup 0 also finishes the coupling sum of this stage
   if (blockIdx.x == 0) {
     finish_cavity(P, ctl, partials, nblk_f, stage, mode, red);
     __syncthreads();
   }
-  const int kx0 = blockIdx.x * W;
-  const int Wb = min(W, P.Hx - kx0);
+  constexpr int nz3 = 3 * NZ;
   const int ny = P.ny, nyp = P.nyp, Py = P.Py;
-  constexpr int nz = NZ;
-  const int ncol = Wb * nz * 3;
-  const float2* src = spec + (size_t)kx0 * nz * 3 * nyp;
+  // Column slots: slot s >= 1 is kx = s; slot 0 carries the two real
+  // columns kx = 0 (real part) and kx = Px/2 (imaginary part) as one complex
+  // sequence (Px >= 2), so the Px/2 + 1 columns fill exactly Px/2 slots.
+  const bool pair = P.Px >= 2;
+  const int hxn = P.Px >> 1;
+  const int nslot = pair ? hxn : P.Hx;
+  const int kx0 = blockIdx.x * W;
+  const int Wb = min(W, nslot - kx0);
+  const bool has_pair = pair && blockIdx.x == 0;   // slot 0 in this block
+  const int ncol = Wb * nz3;
+  const float2* src = spec + (size_t)kx0 * nz3 * nyp;
+  const float2* srcn = spec + (size_t)hxn * nz3 * nyp;
   if (Py >= 2) {
     // pairs of rows (y, y+1) per 16-byte load
     const int hp = Py >> 1;
@@ -524,9 +592,14 @@ __global__ __launch_bounds__(T) void k_yspec(
       for (int u = 0; u < U; ++u) {
         const int e = e0 + u * T;
         const int col = e / hp, y = (e - col * hp) << 1;
-        v[u] = (e < tot && y < ny)
-                   ? *(const float4*)(src + (size_t)col * nyp + y)
-                   : make_float4(0.f, 0.f, 0.f, 0.f);
+        v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (e < tot && y < ny) {
+          v[u] = *(const float4*)(src + (size_t)col * nyp + y);
+          if (has_pair && col < nz3) {
+            const float4 n = *(const float4*)(srcn + (size_t)col * nyp + y);
+            v[u] = make_float4(v[u].x, n.x, v[u].z, n.z);
+          }
+        }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -535,60 +608,59 @@ __global__ __launch_bounds__(T) void k_yspec(
       }
     }
   } else {
-    for (int e = threadIdx.x; e < ncol; e += T) lds[pidx(e)] = src[(size_t)e * nyp];
+    for (int e = threadIdx.x; e < ncol; e += T) {
+      float2 v = src[(size_t)e * nyp];
+      if (has_pair && e < nz3) v.y = srcn[(size_t)e * nyp].x;
+      lds[pidx(e)] = v;
+    }
   }
   __syncthreads();
-  fft_lds<VPTY>(lds, P.logPy, ncol, tw, logTw, -1.f);
+  fft_lds<VPTY>(lds, P.logPy, ncol, twl, logTw, -1.f);
   // pointwise product: per (w, ky), all 3*nz values
-  constexpr int nz3 = 3 * NZ;
   const int Hy = P.Hy;
   for (int e = threadIdx.x; e < Wb * Py; e += T) {
     const int w = e / Py, ky = e - w * Py;
+    float2 M[nz3], Hf[nz3];
+    if (has_pair && w == 0) {
+      // slot 0: split Z = X0 + i XN at (ky, -ky), apply each column's
+      // kernel, recombine; the results are real sequences, so
+      // W[-ky] = conj(Y0[ky]) + i conj(YN[ky]).  One thread per pair.
+      if (2 * ky > Py) continue;
+      const int km = (Py - ky) & (Py - 1);
+      float2 X0[nz3], XN[nz3], YN[nz3];
+#pragma unroll
+      for (int q = 0; q < nz3; ++q) {
+        const float2 z = lds[pidx(q * Py + ky)];
+        const float2 zm = lds[pidx(q * Py + km)];
+        X0[q] = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
+        XN[q] = make_float2(0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x));
+      }
+      kernel_product<NZ>(K + (size_t)ky * 6 * NZ, 1.f, X0, Hf);
+      kernel_product<NZ>(K + ((size_t)hxn * Hy + ky) * 6 * NZ, 1.f, XN, YN);
+#pragma unroll
+      for (int q = 0; q < nz3; ++q) {
+        lds[pidx(q * Py + ky)] = make_float2(Hf[q].x - YN[q].y,
+                                             Hf[q].y + YN[q].x);
+        if (km != ky)
+          lds[pidx(q * Py + km)] = make_float2(Hf[q].x + YN[q].y,
+                                               -Hf[q].y + YN[q].x);
+      }
+      continue;
+    }
     const int kx = kx0 + w;
     const bool lo = ky <= (Py >> 1);
     const int kyi = lo ? ky : Py - ky;
-    const float sy = lo ? 1.f : -1.f;   // odd-in-ky components flip
-    const float* Kp = K + ((size_t)kx * Hy + kyi) * 6 * nz;
-    float kk[6 * NZ];
 #pragma unroll
-    for (int q = 0; q < 6 * NZ; ++q) kk[q] = Kp[q];
-    float2 M[nz3], Hf[nz3];
-#pragma unroll
-    for (int q = 0; q < nz3; ++q) {
-      M[q] = lds[pidx((w * nz3 + q) * Py + ky)];
-      Hf[q] = make_float2(0.f, 0.f);
-    }
-#pragma unroll
-    for (int zt = 0; zt < nz; ++zt) {
-#pragma unroll
-      for (int zs = 0; zs < nz; ++zs) {
-        const int d = zt - zs;
-        const int ad = d < 0 ? -d : d;
-        const float sz = d < 0 ? -1.f : 1.f;   // xz, yz odd in dz
-        const float kxx = kk[0 * nz + ad], kyy = kk[1 * nz + ad];
-        const float kzz = kk[2 * nz + ad], kxy = sy * kk[3 * nz + ad];
-        const float qxz = sz * kk[4 * nz + ad];          // K_xz = -i qxz
-        const float qyz = sz * sy * kk[5 * nz + ad];     // K_yz = -i qyz
-        const float2 mx = M[zs * 3 + 0], my = M[zs * 3 + 1],
-                     mz = M[zs * 3 + 2];
-        // -i q * v = (q v.y, -q v.x)
-        float2& hx = Hf[zt * 3 + 0];
-        float2& hy = Hf[zt * 3 + 1];
-        float2& hz = Hf[zt * 3 + 2];
-        hx.x += kxx * mx.x + kxy * my.x + qxz * mz.y;
-        hx.y += kxx * mx.y + kxy * my.y - qxz * mz.x;
-        hy.x += kxy * mx.x + kyy * my.x + qyz * mz.y;
-        hy.y += kxy * mx.y + kyy * my.y - qyz * mz.x;
-        hz.x += qxz * mx.y + qyz * my.y + kzz * mz.x;
-        hz.y += -qxz * mx.x - qyz * my.x + kzz * mz.y;
-      }
-    }
+    for (int q = 0; q < nz3; ++q) M[q] = lds[pidx((w * nz3 + q) * Py + ky)];
+    kernel_product<NZ>(K + ((size_t)kx * Hy + kyi) * 6 * NZ,
+                       lo ? 1.f : -1.f, M, Hf);   // odd-in-ky parts flip
 #pragma unroll
     for (int q = 0; q < nz3; ++q) lds[pidx((w * nz3 + q) * Py + ky)] = Hf[q];
   }
   __syncthreads();
-  fft_lds<VPTY>(lds, P.logPy, ncol, tw, logTw, 1.f);
-  float2* dst = spec + (size_t)kx0 * nz * 3 * nyp;
+  fft_lds<VPTY>(lds, P.logPy, ncol, twl, logTw, 1.f);
+  float2* dst = spec + (size_t)kx0 * nz3 * nyp;
+  float2* dstn = spec + (size_t)hxn * nz3 * nyp;
   if (Py >= 2) {
     const int hq = nyp >> 1;          // row pairs actually stored
     const int tot = ncol * hq;
@@ -596,10 +668,123 @@ __global__ __launch_bounds__(T) void k_yspec(
       const int col = e / hq, y = (e - col * hq) << 1;
       float4 v = *(const float4*)(lds + pidx(col * Py + y));
       if (y + 1 >= ny) { v.z = 0.f; v.w = 0.f; }   // keep the pad zero
+      if (has_pair && col < nz3) {
+        *(float4*)(dstn + (size_t)col * nyp + y) =
+            make_float4(v.y, 0.f, v.w, 0.f);
+        v = make_float4(v.x, 0.f, v.z, 0.f);
+      }
       *(float4*)(dst + (size_t)col * nyp + y) = v;
     }
   } else {
-    for (int e = threadIdx.x; e < ncol; e += T) dst[(size_t)e * nyp] = lds[pidx(e)];
+    for (int e = threadIdx.x; e < ncol; e += T) {
+      const float2 v = lds[pidx(e)];
+      if (has_pair && e < nz3) {
+        dstn[(size_t)e * nyp] = make_float2(v.y, 0.f);
+        dst[(size_t)e * nyp] = make_float2(v.x, 0.f);
+      } else {
+        dst[(size_t)e * nyp] = v;
+      }
+    }
+  }
+}
+
+
+// ============================================================== k_yspec_h
+// Spectral pass split by ky parity.  A y column is zero beyond Py/2, so its
+// Py-point DFT splits exactly into the even-ky half (the Py/2-point DFT of
+// x[n]) and the odd-ky half (the Py/2-point DFT of x[n] w^n, w = exp(-2 pi
+// i / Py)); on the rows kept, y < Py/2, the inverse is
+//     y[n] = IDFT(Y_even)[n] + w^-n IDFT(Y_odd)[n]   (both unnormalised).
+// The halves run one after the other through an LDS buffer half the size of
+// k_yspec's, so two workgroups share a CU; the even result is parked in the
+// output rows and completed by the same thread in the odd half.  Thread t
+// owns elements e = t + i T (i < EPT) of the W * 3nz columns; the host
+// guarantees W * 3nz * Py/2 <= EPT * T.  Same contract as k_yspec.
+template <int T, int NZ, int EPT>
+__global__ __launch_bounds__(T, 4) void k_yspec_h(
+    Prm P, float2* __restrict__ spec, const float* __restrict__ K,
+    Ctl* __restrict__ ctl, int W, const float2* __restrict__ tw,
+    int logTw, const double* __restrict__ partials, int nblk_f, int stage,
+    int mode) {
+  extern __shared__ float2 lds_all[];
+  __shared__ double red[16];
+  if (ctl->done) return;
+  float2* twl = lds_all;
+  float2* lds = lds_all + lds_twiddles(logTw);
+  stage_twiddles(twl, tw, logTw);
+  if (blockIdx.x == 0) {
+    finish_cavity(P, ctl, partials, nblk_f, stage, mode, red);
+    __syncthreads();
+  }
+  constexpr int nz3 = 3 * NZ;
+  const int kx0 = blockIdx.x * W;
+  const int Wb = min(W, P.Hx - kx0);
+  const int ny = P.ny, nyp = P.nyp;
+  const int logPh = P.logPy - 1, Ph = 1 << logPh;
+  const int tot = (Wb * nz3) << logPh;
+  const int sh = logTw - P.logPy;       // table stride of exp(-2 pi i n / Py)
+  float2* col0 = spec + (size_t)kx0 * nz3 * nyp;
+  float2 xin[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = threadIdx.x + i * T;
+    const int c = e >> logPh, n = e & (Ph - 1);
+    xin[i] = (e < tot && n < ny) ? col0[(size_t)c * nyp + n]
+                                 : make_float2(0.f, 0.f);
+  }
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    // opaque copy of the transform length: keeps the FFT index arithmetic
+    // inside each half instead of live across both (register pressure)
+    int lph = logPh;
+    asm volatile("" : "+s"(lph));
+    const int phl = 1 << lph;
+    const int totl = (Wb * nz3) << lph;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = threadIdx.x + i * T;
+      if (e < totl) {
+        float2 v = xin[i];
+        if (h) v = cmul(v, twl[(e & (phl - 1)) << sh]);
+        lds[pidx(e)] = v;
+      }
+    }
+    __syncthreads();
+    fft_lds<VPTY>(lds, lph, Wb * nz3, twl, logTw, -1.f);
+    for (int e = threadIdx.x; e < (Wb << lph); e += T) {
+      const int w = e >> lph, k = e & (phl - 1);
+      const int ky = 2 * k + h;
+      const bool lo = ky <= phl;
+      const int kyi = lo ? ky : 2 * phl - ky;
+      float2 M[nz3], Hf[nz3];
+#pragma unroll
+      for (int q = 0; q < nz3; ++q)
+        M[q] = lds[pidx(((w * nz3 + q) << lph) + k)];
+      kernel_product<NZ>(K + ((size_t)(kx0 + w) * P.Hy + kyi) * 6 * NZ,
+                         lo ? 1.f : -1.f, M, Hf);
+#pragma unroll
+      for (int q = 0; q < nz3; ++q)
+        lds[pidx(((w * nz3 + q) << lph) + k)] = Hf[q];
+    }
+    __syncthreads();
+    fft_lds<VPTY>(lds, lph, Wb * nz3, twl, logTw, 1.f);
+    // (same elements as the thread loaded; not unrolled, to bound the
+    // number of loads in flight)
+#pragma unroll 1
+    for (int e = threadIdx.x; e < totl; e += T) {
+      const int c = e >> lph, n = e & (phl - 1);
+      if (n < nyp) {
+        float2* o = col0 + (size_t)c * nyp + n;
+        const float2 v = lds[pidx(e)];
+        if (h == 0) {
+          if (n < ny) *o = v;
+        } else {
+          *o = (n < ny) ? cadd(*o, wmulc(v, twl[n << sh]))
+                        : make_float2(0.f, 0.f);   // pad stays zero
+        }
+      }
+    }
+    __syncthreads();   // the LDS buffer is refilled by the next half
   }
 }
 
@@ -850,8 +1035,11 @@ __global__ __launch_bounds__(T) void k_xfield(
     Ctl* __restrict__ ctl, double* __restrict__ partials,
     double* __restrict__ rec, int stage, int R, Epi E,
     const float2* __restrict__ tw, int logTw) {
-  extern __shared__ float2 lds[];
+  extern __shared__ float2 lds_all[];
   if (ctl->done) return;
+  float2* twl = lds_all;
+  float2* lds = lds_all + lds_twiddles(logTw);
+  if (P.demag) stage_twiddles(twl, tw, logTw);
   const int nblk = gridDim.x;
   const int nz = P.nz;
   const int tile = xcd_tile(blockIdx.x, nblk);
@@ -896,7 +1084,7 @@ __global__ __launch_bounds__(T) void k_xfield(
       }
     }
     __syncthreads();
-    fft_lds<VPT>(lds, P.logPx, 3 * np, tw, logTw, 1.f);
+    fft_lds<VPT>(lds, P.logPx, 3 * np, twl, logTw, 1.f);
   }
   field_cells(P, ys, ctl, partials, stage, R, E, z, y0,
               [&](int r, int x) {

@@ -84,8 +84,11 @@ def test_tensor_matches_oracle(torch, grid, cell):
     s.close()
 
 
+# the last three have 2048-point y transforms (ragged ny), the case the
+# ky-parity split spectral pass serves (512- and 1024-thread workgroups)
 FIELD_GRIDS = [(32, 32, 1), (37, 23, 3), (1, 1, 1), (1, 9, 2), (16, 1, 4),
-               (64, 8, 2), (5, 3, 4)]
+               (64, 8, 2), (5, 3, 4), (20, 600, 2), (12, 530, 3),
+               (9, 700, 1)]
 
 
 @pytest.mark.parametrize("grid", FIELD_GRIDS)
@@ -107,7 +110,7 @@ def test_demag_field_matches_oracle(torch, grid):
 
 
 @pytest.mark.parametrize("grid", [(32, 32, 1), (37, 23, 3), (1, 1, 1),
-                                  (24, 1, 2), (20, 16, 4)])
+                                  (24, 1, 2), (20, 16, 4), (20, 600, 2)])
 def test_rhs_matches_oracle(torch, grid):
     nx, ny, nz = grid
     _say("rhs", grid)
