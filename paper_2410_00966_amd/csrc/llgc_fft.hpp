@@ -1,6 +1,6 @@
 // Batched in-LDS complex FFT for power-of-two lengths (gfx950).
 //
-// Stockham auto-sort, radix 8/4/2, in place in one LDS buffer: each pass
+// Stockham auto-sort, radix 16/8/4/2, in place in one LDS buffer: each pass
 // loads a thread's butterflies into registers, barriers, computes and
 // stores to the auto-sorted positions, barriers.  All threads of the
 // workgroup cooperate on a batch of `batch` transforms of length L stored
@@ -75,6 +75,27 @@ __device__ __forceinline__ void dft_small<8>(float2* v, float s) {
   v[7] = csub(e[3], o3);
 }
 
+template <>
+__device__ __forceinline__ void dft_small<16>(float2* v, float s) {
+  float2 e[8] = {v[0], v[2], v[4], v[6], v[8], v[10], v[12], v[14]};
+  float2 o[8] = {v[1], v[3], v[5], v[7], v[9], v[11], v[13], v[15]};
+  dft_small<8>(e, s);
+  dft_small<8>(o, s);
+  // w16^p = exp(s i pi p / 8)
+  const float c1 = 0.92387953251128676f, s1 = 0.38268343236508977f;
+  const float h = 0.70710678118654752f;
+  const float2 w[8] = {make_float2(1.f, 0.f),   make_float2(c1, s * s1),
+                       make_float2(h, s * h),    make_float2(s1, s * c1),
+                       make_float2(0.f, s),      make_float2(-s1, s * c1),
+                       make_float2(-h, s * h),   make_float2(-c1, s * s1)};
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    const float2 t = (p == 0) ? o[0] : cmul(o[p], w[p]);
+    v[p] = cadd(e[p], t);
+    v[p + 8] = csub(e[p], t);
+  }
+}
+
 // One Stockham pass of radix R over `batch` transforms of length L = 2^logL
 // held in LDS.  Ns = 2^logNs is the length of the sub-transforms already
 // done.  NB is the number of butterflies a thread holds in registers; the
@@ -83,7 +104,7 @@ template <int R, int NB>
 __device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
                                          int batch, const float2* tw,
                                          int logTw, float dir) {
-  constexpr int logR = (R == 2) ? 1 : (R == 4) ? 2 : 3;
+  constexpr int logR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
   const int logLr = logL - logR;
   const int Lr = 1 << logLr;
   const int nbf = batch << logLr;
@@ -135,20 +156,31 @@ __device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
 }
 
 // Full transform: dir = -1 forward (exp(-i...)), +1 inverse (unnormalised).
-// VPT = complex values a thread may hold (register budget per pass).
-template <int VPT>
+// VPT = complex values a thread may hold (register budget per pass); R16
+// allows radix-16 passes (fewer LDS round trips, more registers).
+template <int VPT, bool R16 = false>
 __device__ __forceinline__ void fft_lds(float2* s, int logL, int batch,
                                         const float2* tw,
                         int logTw, float dir) {
   if (logL == 0) return;
   int logNs = 0;
-  int rem = logL;
-  // radix plan: 8s, with the remainder as one 4, two 4s, or one 2
+  // radix plan: 16s (R16 and a thread may hold 16 values), then the
+  // remainder as one 8, one 4, two 4s, 8 + 4 in place of one 16, or one 2
+  int n16 = (R16 && VPT >= 16) ? logL / 4 : 0;
+  const int rem = logL - 4 * n16;
   int n8 = rem / 3, tail = rem % 3;
   int n4 = 0, n2 = 0;
   if (tail == 2) n4 = 1;
   if (tail == 1) {
-    if (n8 > 0) { n8 -= 1; n4 = 2; } else { n2 = 1; }
+    if (n8 > 0) { n8 -= 1; n4 = 2; }
+    else if (n16 > 0) { n16 -= 1; n8 = 1; n4 = 1; }
+    else { n2 = 1; }
+  }
+  if constexpr (R16 && VPT >= 16) {
+    for (int p = 0; p < n16; ++p) {
+      fft_pass<16, VPT / 16>(s, logL, logNs, batch, tw, logTw, dir);
+      logNs += 4;
+    }
   }
   for (int p = 0; p < n8; ++p) {
     fft_pass<8, VPT / 8>(s, logL, logNs, batch, tw, logTw, dir);

@@ -615,7 +615,7 @@ __global__ __launch_bounds__(T) void k_yspec(
     }
   }
   __syncthreads();
-  fft_lds<VPTY>(lds, P.logPy, ncol, twl, logTw, -1.f);
+  fft_lds<VPTY, true>(lds, P.logPy, ncol, twl, logTw, -1.f);
   // pointwise product: per (w, ky), all 3*nz values
   const int Hy = P.Hy;
   for (int e = threadIdx.x; e < Wb * Py; e += T) {
@@ -658,7 +658,7 @@ __global__ __launch_bounds__(T) void k_yspec(
     for (int q = 0; q < nz3; ++q) lds[pidx((w * nz3 + q) * Py + ky)] = Hf[q];
   }
   __syncthreads();
-  fft_lds<VPTY>(lds, P.logPy, ncol, twl, logTw, 1.f);
+  fft_lds<VPTY, true>(lds, P.logPy, ncol, twl, logTw, 1.f);
   float2* dst = spec + (size_t)kx0 * nz3 * nyp;
   float2* dstn = spec + (size_t)hxn * nz3 * nyp;
   if (Py >= 2) {
@@ -750,7 +750,7 @@ __global__ __launch_bounds__(T, 4) void k_yspec_h(
       }
     }
     __syncthreads();
-    fft_lds<VPTY>(lds, lph, Wb * nz3, twl, logTw, -1.f);
+    fft_lds<VPTY, true>(lds, lph, Wb * nz3, twl, logTw, -1.f);
     for (int e = threadIdx.x; e < (Wb << lph); e += T) {
       const int w = e >> lph, k = e & (phl - 1);
       const int ky = 2 * k + h;
@@ -767,7 +767,7 @@ __global__ __launch_bounds__(T, 4) void k_yspec_h(
         lds[pidx(((w * nz3 + q) << lph) + k)] = Hf[q];
     }
     __syncthreads();
-    fft_lds<VPTY>(lds, lph, Wb * nz3, twl, logTw, 1.f);
+    fft_lds<VPTY, true>(lds, lph, Wb * nz3, twl, logTw, 1.f);
     // (same elements as the thread loaded; not unrolled, to bound the
     // number of loads in flight)
 #pragma unroll 1
