@@ -85,76 +85,24 @@ def counted_traffic(kernel):
     return None
 
 
-def cpu_baseline(prob, m0):
-    """The oracle on the same workload and state: one right-hand-side
-    evaluation timed (tensor and FFT-kernel setup excluded), scaled to the
-    six evaluations an accepted Dormand-Prince step costs (FSAL)."""
+def cpu_baseline(prob, m0, dt):
+    """The oracle on the same workload and state: one Dormand-Prince attempt
+    (the six right-hand-side evaluations of an accepted FSAL step, at the
+    step size the GPU run settled on) timed on the host; tensor, FFT-kernel
+    set-up and the carried-over first stage are outside the timing."""
     from oracle.llg import CavityLLG
     o = CavityLLG(prob, demag="fft")
     m = m0.astype(np.float64)
+    k1m, k1a = o.rhs(m, 0j, 0.0)
     t0 = time.perf_counter()
-    o.rhs(m, 0j, 0.0)
+    o.dp45_attempt(m, 0j, 0.0, dt, k1m, k1a)
     el = time.perf_counter() - t0
-    return dict(value=prob.ncells / (6.0 * el), unit="cell-steps/s",
+    return dict(value=prob.ncells / el, unit="cell-steps/s",
                 cores=1, kind="oracle",
-                sample=("one right-hand-side evaluation (numpy float64, one "
-                        "thread) of the relaxed "
-                        f"{prob.nx}x{prob.ny}x{prob.nz} film, {el:.1f} s, "
-                        "scaled by the 6 evaluations per Dormand-Prince "
-                        "step"))
-
-
-def bench_batched(torch, t_end, n_plain):
-    """The 512-instance size/coupling sweep (grids U{16..128}^2 x U{1..4} of
-    5 nm cells, Dormand-Prince tol 1e-6) as one batch, against a sample of
-    the same instances solved one after another with standalone contexts.
-    Set-up (contexts, demag kernels) is outside both timed regions."""
-    from paper_2410_00966_amd import inputs as I
-    from paper_2410_00966_amd.llgc import Batch, Sim
-    inst = I.c4_instances()
-    probs = [p for p, _, _ in inst]
-    m0s = [m0 for _, m0, _ in inst]
-    t_set = time.perf_counter()
-    b = Batch(probs)
-    for s, m0 in zip(b.sims, m0s):
-        s.set_state(torch.from_numpy(m0))
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t_set
-    t0 = time.perf_counter()
-    _, infos, st = b.run(t_end=t_end)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    assert (st == 0).all(), st
-    cs = sum(p.ncells * i["accepted"] for p, i in zip(probs, infos))
-    b.close()
-    idx = np.linspace(0, len(probs) - 1, n_plain).round().astype(int)
-    wall_p, cs_p = 0.0, 0
-    for k in idx:
-        s = Sim(probs[k])
-        s.set_state(torch.from_numpy(m0s[k]))
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        _, info = s.run(t_end=t_end)
-        torch.cuda.synchronize()
-        wall_p += time.perf_counter() - t1
-        cs_p += probs[k].ncells * info["accepted"]
-        s.close()
-    rate_b, rate_p = cs / wall, cs_p / wall_p
-    return {
-        "workload": ("512 ragged instances, grids U{16..128}^2 x U{1..4} of "
-                     "5 nm, g/wc log-uniform 1e-3..1e-1, Bz U(0,0.3) T, "
-                     f"wc/2pi 5..15 GHz, Dormand-Prince tol 1e-6 to "
-                     f"{t_end * 1e12:g} ps"),
-        "value": rate_b, "unit": "cell-steps/s",
-        "cells": int(sum(p.ncells for p in probs)),
-        "accepted_total": int(sum(i["accepted"] for i in infos)),
-        "wall_s": wall, "setup_s": round(setup_s, 2),
-        "plain": {"value": rate_p, "unit": "cell-steps/s",
-                  "sample": (f"{len(idx)} evenly spaced instances solved one "
-                             "after another, standalone contexts"),
-                  "wall_s": wall_p},
-        "speedup_vs_plain": rate_b / rate_p,
-    }
+                sample=("one Dormand-Prince step (6 right-hand-side "
+                        "evaluations, numpy float64, one thread) of the "
+                        f"relaxed {prob.nx}x{prob.ny}x{prob.nz} film at "
+                        f"dt = {dt:.3g} s: {el:.1f} s"))
 
 
 def bench_wire(torch, nsteps):
@@ -366,7 +314,7 @@ def main():
                                        args.batch_plain)
     if not args.no_cpu_baseline:
         m_host = m_relaxed.cpu().numpy()
-        out["cpu_baseline"] = cpu_baseline(prob, m_host)
+        out["cpu_baseline"] = cpu_baseline(prob, m_host, info["dt"])
     print(json.dumps(out))
 
 
