@@ -184,37 +184,61 @@ int launch_xfwd(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
   const bool v4 = (c->nx % 4 == 0) && aligned16(ys) &&
                   (!c->ms_map || aligned16(c->ms_map));
   const size_t lds = c->P.demag ? c->lds_f : 0;
-  if (v4)
-    hipLaunchKernelGGL((k_xfwd<kTX, true>), xgrid(c, c->Rf), dim3(kTX), lds,
-                       c->stream, c->P, ys, c->spec, ctl, c->partials, stage,
-                       c->Rf, c->tw, c->logTw, mode);
-  else
-    hipLaunchKernelGGL((k_xfwd<kTX, false>), xgrid(c, c->Rf), dim3(kTX), lds,
-                       c->stream, c->P, ys, c->spec, ctl, c->partials, stage,
-                       c->Rf, c->tw, c->logTw, mode);
+#define LLGC_XF(V, LP)                                                      \
+  hipLaunchKernelGGL((k_xfwd<kTX, V, LP>), xgrid(c, c->Rf), dim3(kTX), lds,  \
+                     c->stream, c->P, ys, c->spec, ctl, c->partials, stage, \
+                     c->Rf, c->tw, c->logTw, mode)
+  if (v4) {
+    if (c->logPx == 11) LLGC_XF(true, 11);
+    else if (c->logPx == 10) LLGC_XF(true, 10);
+    else LLGC_XF(true, 0);
+  } else {
+    if (c->logPx == 11) LLGC_XF(false, 11);
+    else if (c->logPx == 10) LLGC_XF(false, 10);
+    else LLGC_XF(false, 0);
+  }
+#undef LLGC_XF
   return check_launch(c, "k_xfwd");
 }
 
-template <int T>
-void yspec_nz(llgc_ctx* c, Ctl* ctl, dim3 g, int stage, int mode) {
+// The LDS FFT kernels are specialised on the transform length for the
+// long transforms they serve (LP = log2 length; 0 = any length).
+template <int T, int LP>
+void yspec_nz_lp(llgc_ctx* c, Ctl* ctl, dim3 g, int stage, int mode) {
   const int nf = (int)xgrid(c, fwd_rows(c)).x;
 #define LLGC_YSPEC_ARGS c->P, c->spec, c->K, ctl, c->W, c->tw, c->logTw, \
                         c->partials, nf, stage, mode
   switch (c->nz) {
-    case 1: hipLaunchKernelGGL((k_yspec<T, 1>), g, dim3(T), c->lds_y, c->stream, LLGC_YSPEC_ARGS); break;
-    case 2: hipLaunchKernelGGL((k_yspec<T, 2>), g, dim3(T), c->lds_y, c->stream, LLGC_YSPEC_ARGS); break;
-    case 3: hipLaunchKernelGGL((k_yspec<T, 3>), g, dim3(T), c->lds_y, c->stream, LLGC_YSPEC_ARGS); break;
-    default: hipLaunchKernelGGL((k_yspec<T, 4>), g, dim3(T), c->lds_y, c->stream, LLGC_YSPEC_ARGS); break;
+    case 1: hipLaunchKernelGGL((k_yspec<T, 1, LP>), g, dim3(T), c->lds_y, c->stream, LLGC_YSPEC_ARGS); break;
+    case 2: hipLaunchKernelGGL((k_yspec<T, 2, LP>), g, dim3(T), c->lds_y, c->stream, LLGC_YSPEC_ARGS); break;
+    case 3: hipLaunchKernelGGL((k_yspec<T, 3, LP>), g, dim3(T), c->lds_y, c->stream, LLGC_YSPEC_ARGS); break;
+    default: hipLaunchKernelGGL((k_yspec<T, 4, LP>), g, dim3(T), c->lds_y, c->stream, LLGC_YSPEC_ARGS); break;
   }
 #undef LLGC_YSPEC_ARGS
 }
 
 template <int T>
+void yspec_nz(llgc_ctx* c, Ctl* ctl, dim3 g, int stage, int mode) {
+  switch (c->logPy) {
+    case 10: yspec_nz_lp<T, 10>(c, ctl, g, stage, mode); break;
+    case 11: yspec_nz_lp<T, 11>(c, ctl, g, stage, mode); break;
+    default: yspec_nz_lp<T, 0>(c, ctl, g, stage, mode); break;
+  }
+}
+
+template <int T, int LP>
+void yspec_attr_lp(size_t lds) {
+  hipFuncSetAttribute((const void*)k_yspec<T, 1, LP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipFuncSetAttribute((const void*)k_yspec<T, 2, LP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipFuncSetAttribute((const void*)k_yspec<T, 3, LP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipFuncSetAttribute((const void*)k_yspec<T, 4, LP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <int T>
 void yspec_attr(size_t lds) {
-  hipFuncSetAttribute((const void*)k_yspec<T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipFuncSetAttribute((const void*)k_yspec<T, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipFuncSetAttribute((const void*)k_yspec<T, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipFuncSetAttribute((const void*)k_yspec<T, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  yspec_attr_lp<T, 0>(lds);
+  yspec_attr_lp<T, 10>(lds);
+  yspec_attr_lp<T, 11>(lds);
 }
 
 // Spectral pass; its workgroup 0 also finishes the stage's coupling sum.
@@ -310,10 +334,19 @@ int launch_xfield(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
 #undef LLGC_XW_ARGS
     return check_launch(c, "k_xfield_w");
   }
-  hipLaunchKernelGGL(k_xfield<kTX>, xgrid(c, c->Ri), dim3(kTX),
-                     c->P.demag ? c->lds_i : 0, c->stream, c->P, ys, c->spec,
-                     ctl, c->partials, c->rec, stage, c->Ri, E, c->tw,
-                     c->logTw);
+#define LLGC_XI(LP)                                                         \
+  hipLaunchKernelGGL((k_xfield<kTX, LP>), xgrid(c, c->Ri), dim3(kTX),        \
+                     c->P.demag ? c->lds_i : 0, c->stream, c->P, ys,       \
+                     c->spec, ctl, c->partials, c->rec, stage, c->Ri, E,   \
+                     c->tw, c->logTw)
+  switch (c->logPx) {
+    case 8: LLGC_XI(8); break;
+    case 9: LLGC_XI(9); break;
+    case 10: LLGC_XI(10); break;
+    case 11: LLGC_XI(11); break;
+    default: LLGC_XI(0); break;
+  }
+#undef LLGC_XI
   return check_launch(c, "k_xfield");
 }
 
@@ -737,15 +770,23 @@ int llgc_create_ex(const llgc_grid* g, void* stream, int flags,
     delete c;
     return LLGC_E_UNSUPPORTED;
   }
-  hipFuncSetAttribute((const void*)k_xfwd<kTX, true>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)c->lds_f);
-  hipFuncSetAttribute((const void*)k_xfwd<kTX, false>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)c->lds_f);
-  hipFuncSetAttribute((const void*)k_xfield<kTX>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)c->lds_i);
+  {
+    const void* xf[] = {
+        (const void*)k_xfwd<kTX, true, 0>, (const void*)k_xfwd<kTX, true, 10>,
+        (const void*)k_xfwd<kTX, true, 11>, (const void*)k_xfwd<kTX, false, 0>,
+        (const void*)k_xfwd<kTX, false, 10>,
+        (const void*)k_xfwd<kTX, false, 11>};
+    for (const void* f : xf)
+      hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)c->lds_f);
+    const void* xi[] = {
+        (const void*)k_xfield<kTX, 0>, (const void*)k_xfield<kTX, 8>,
+        (const void*)k_xfield<kTX, 9>, (const void*)k_xfield<kTX, 10>,
+        (const void*)k_xfield<kTX, 11>};
+    for (const void* f : xi)
+      hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)c->lds_i);
+  }
   if (c->yhalf) {
     const void* fs[] = {
         (const void*)k_yspec_h<512, 1, kYhEpt>, (const void*)k_yspec_h<512, 2, kYhEpt>,

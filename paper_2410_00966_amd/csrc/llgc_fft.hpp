@@ -158,10 +158,14 @@ __device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
 // Full transform: dir = -1 forward (exp(-i...)), +1 inverse (unnormalised).
 // VPT = complex values a thread may hold (register budget per pass); R16
 // allows radix-16 passes (fewer LDS round trips, more registers).
-template <int VPT, bool R16 = false>
+// LOGL > 0 fixes the length at compile time (logL must then equal it): the
+// pass loops unroll and every stride and padded LDS offset becomes an
+// immediate, which removes most of the per-element address arithmetic.
+template <int VPT, bool R16 = false, int LOGL = 0>
 __device__ __forceinline__ void fft_lds(float2* s, int logL, int batch,
                                         const float2* tw,
                         int logTw, float dir) {
+  if constexpr (LOGL > 0) logL = LOGL;
   if (logL == 0) return;
   int logNs = 0;
   // radix plan: 16s (R16 and a thread may hold 16 values), then the
@@ -177,19 +181,23 @@ __device__ __forceinline__ void fft_lds(float2* s, int logL, int batch,
     else { n2 = 1; }
   }
   if constexpr (R16 && VPT >= 16) {
+#pragma unroll
     for (int p = 0; p < n16; ++p) {
       fft_pass<16, VPT / 16>(s, logL, logNs, batch, tw, logTw, dir);
       logNs += 4;
     }
   }
+#pragma unroll
   for (int p = 0; p < n8; ++p) {
     fft_pass<8, VPT / 8>(s, logL, logNs, batch, tw, logTw, dir);
     logNs += 3;
   }
+#pragma unroll
   for (int p = 0; p < n4; ++p) {
     fft_pass<4, VPT / 4>(s, logL, logNs, batch, tw, logTw, dir);
     logNs += 2;
   }
+#pragma unroll
   for (int p = 0; p < n2; ++p) {
     fft_pass<2, VPT / 2>(s, logL, logNs, batch, tw, logTw, dir);
     logNs += 1;

@@ -254,7 +254,8 @@ __device__ __forceinline__ void cavity_stage(const Prm& P, Ctl* c, int s,
 // y range are consecutive tiles).  LDS: (R/2) * Px complex.
 // mode 0: integrate (cavity stage in the last block); mode 1: evaluate.
 // V4: nx % 4 == 0 and 16-byte aligned planes (vector loads).
-template <int T, bool V4>
+// LP > 0: log2(Px) fixed at compile time (specialised FFT addressing).
+template <int T, bool V4, int LP = 0>
 __global__ __launch_bounds__(T) void k_xfwd(
     Prm P, const float* __restrict__ ys, float2* __restrict__ spec,
     Ctl* __restrict__ ctl, double* __restrict__ partials, int stage, int R,
@@ -350,7 +351,7 @@ __global__ __launch_bounds__(T) void k_xfwd(
     facc[0] += fc * br[c];
     if (!P.demag) continue;
     __syncthreads();
-    fft_lds<VPT>(lds, P.logPx, np, twl, logTw, -1.f);
+    fft_lds<VPT, false, LP>(lds, P.logPx, np, twl, logTw, -1.f);
     // split the two real transforms and write the half spectrum: rows
     // (y0+2p, y0+2p+1) are adjacent -> one 16-byte store per (kx, p)
     const int H = P.Hx;
@@ -550,7 +551,8 @@ __device__ __forceinline__ void kernel_product(const float* __restrict__ Kp,
   }
 }
 
-template <int T, int NZ>
+// LP > 0: log2(Py) fixed at compile time (specialised FFT addressing).
+template <int T, int NZ, int LP = 0>
 __global__ __launch_bounds__(T) void k_yspec(
     Prm P, float2* __restrict__ spec, const float* __restrict__ K,
     Ctl* __restrict__ ctl, int W, const float2* __restrict__ tw,
@@ -615,7 +617,7 @@ __global__ __launch_bounds__(T) void k_yspec(
     }
   }
   __syncthreads();
-  fft_lds<VPTY, true>(lds, P.logPy, ncol, twl, logTw, -1.f);
+  fft_lds<VPTY, true, LP>(lds, P.logPy, ncol, twl, logTw, -1.f);
   // pointwise product: per (w, ky), all 3*nz values
   const int Hy = P.Hy;
   for (int e = threadIdx.x; e < Wb * Py; e += T) {
@@ -658,7 +660,7 @@ __global__ __launch_bounds__(T) void k_yspec(
     for (int q = 0; q < nz3; ++q) lds[pidx((w * nz3 + q) * Py + ky)] = Hf[q];
   }
   __syncthreads();
-  fft_lds<VPTY, true>(lds, P.logPy, ncol, twl, logTw, 1.f);
+  fft_lds<VPTY, true, LP>(lds, P.logPy, ncol, twl, logTw, 1.f);
   float2* dst = spec + (size_t)kx0 * nz3 * nyp;
   float2* dstn = spec + (size_t)hxn * nz3 * nyp;
   if (Py >= 2) {
@@ -1029,7 +1031,8 @@ __device__ __forceinline__ void field_cells(const Prm& P,
 
 // ================================================================ k_xfield
 // 1D grid of ceil(ny/R)*nz tiles (as k_xfwd); LDS: 3 * (R/2) * Px complex.
-template <int T>
+// LP > 0: log2(Px) fixed at compile time (specialised FFT addressing).
+template <int T, int LP = 0>
 __global__ __launch_bounds__(T) void k_xfield(
     Prm P, const float* __restrict__ ys, const float2* __restrict__ spec,
     Ctl* __restrict__ ctl, double* __restrict__ partials,
@@ -1084,7 +1087,7 @@ __global__ __launch_bounds__(T) void k_xfield(
       }
     }
     __syncthreads();
-    fft_lds<VPT>(lds, P.logPx, 3 * np, twl, logTw, 1.f);
+    fft_lds<VPT, false, LP>(lds, P.logPx, 3 * np, twl, logTw, 1.f);
   }
   field_cells(P, ys, ctl, partials, stage, R, E, z, y0,
               [&](int r, int x) {
