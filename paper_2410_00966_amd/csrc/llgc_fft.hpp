@@ -33,6 +33,15 @@ __device__ __forceinline__ float2 cmul_si(float2 a, float s) {
   return make_float2(-s * a.y, s * a.x);
 }
 
+template <int R>
+struct RadixTag {
+  static constexpr int value = R;
+};
+template <int R>
+struct Log2C {
+  static constexpr int v = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
+};
+
 // R-point DFT in registers: X_p = sum_q v_q exp(s 2 pi i p q / R),
 // s = -1 forward, +1 inverse.
 template <int R>
@@ -96,11 +105,55 @@ __device__ __forceinline__ void dft_small<16>(float2* v, float s) {
   }
 }
 
+// R-point DFT whose inputs v[R/2..R-1] are zero (not read): the even
+// outputs are the R/2-point DFT of v[0..R/2-1], the odd ones that of
+// v[q] w_R^q.  Outputs in v[0..R-1].
+template <int R>
+__device__ __forceinline__ void dft_in_half(float2* v, float s) {
+  if constexpr (R == 2) {
+    v[1] = v[0];
+  } else {
+    constexpr int H = R / 2;
+    float2 e[H], o[H];
+#pragma unroll
+    for (int q = 0; q < H; ++q) e[q] = v[q];
+    // w_R^q = exp(s i 2 pi q / R), q < R/2
+    const float c1 = 0.92387953251128676f, s1 = 0.38268343236508977f;
+    const float h = 0.70710678118654752f;
+    o[0] = v[0];
+    if constexpr (R == 4) {
+      o[1] = cmul_si(v[1], s);
+    } else if constexpr (R == 8) {
+      o[1] = cmul(v[1], make_float2(h, s * h));
+      o[2] = cmul_si(v[2], s);
+      o[3] = cmul(v[3], make_float2(-h, s * h));
+    } else {
+      static_assert(R == 16, "radix 2, 4, 8 or 16");
+      const float2 w[8] = {make_float2(1.f, 0.f),  make_float2(c1, s * s1),
+                           make_float2(h, s * h),   make_float2(s1, s * c1),
+                           make_float2(0.f, s),     make_float2(-s1, s * c1),
+                           make_float2(-h, s * h),  make_float2(-c1, s * s1)};
+#pragma unroll
+      for (int q = 1; q < H; ++q) o[q] = cmul(v[q], w[q]);
+    }
+    dft_small<H>(e, s);
+    dft_small<H>(o, s);
+#pragma unroll
+    for (int m = 0; m < H; ++m) {
+      v[2 * m] = e[m];
+      v[2 * m + 1] = o[m];
+    }
+  }
+}
+
 // One Stockham pass of radix R over `batch` transforms of length L = 2^logL
 // held in LDS.  Ns = 2^logNs is the length of the sub-transforms already
 // done.  NB is the number of butterflies a thread holds in registers; the
 // caller guarantees batch * L / R <= NB * blockDim.x.
-template <int R, int NB>
+// PIN (first pass only, Ns = 1): inputs at positions >= L/2 are zero and
+// are not read.  POUT (last pass only, Ns = L/R): outputs at positions
+// >= L/2 are not needed and are not written.
+template <int R, int NB, bool PIN = false, bool POUT = false>
 __device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
                                          int batch, const float2* tw,
                                          int logTw, float dir) {
@@ -124,7 +177,8 @@ __device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
       const int t = b >> logLr, j = b & (Lr - 1);
       const int base = t << logL;
 #pragma unroll
-      for (int q = 0; q < R; ++q) v[i][q] = s[pidx(base + j + q * Lr)];
+      for (int q = 0; q < (PIN ? R / 2 : R); ++q)
+        v[i][q] = s[pidx(base + j + q * Lr)];
       const int k = j & (Ns - 1);
       if (k != 0) w1[i] = tw[(k << twshift) & twmask];
     }
@@ -146,10 +200,12 @@ __device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
           if (q + 1 < R) wq = cmul(wq, w);
         }
       }
-      dft_small<R>(v[i], dir);
+      if constexpr (PIN) dft_in_half<R>(v[i], dir);
+      else dft_small<R>(v[i], dir);
       const int out0 = (t << logL) + ((j - k) << logR) + k;
 #pragma unroll
-      for (int q = 0; q < R; ++q) s[pidx(out0 + q * Ns)] = v[i][q];
+      for (int q = 0; q < (POUT ? R / 2 : R); ++q)
+        s[pidx(out0 + q * Ns)] = v[i][q];
     }
   }
   __syncthreads();
@@ -161,7 +217,11 @@ __device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
 // LOGL > 0 fixes the length at compile time (logL must then equal it): the
 // pass loops unroll and every stride and padded LDS offset becomes an
 // immediate, which removes most of the per-element address arithmetic.
-template <int VPT, bool R16 = false, int LOGL = 0>
+// PIN: the input is zero from position L/2 on (zero padding; the first
+// pass does not read it).  POUT: only outputs below L/2 are used (the last
+// pass does not write the rest).
+template <int VPT, bool R16 = false, int LOGL = 0, bool PIN = false,
+          bool POUT = false>
 __device__ __forceinline__ void fft_lds(float2* s, int logL, int batch,
                                         const float2* tw,
                         int logTw, float dir) {
@@ -180,28 +240,34 @@ __device__ __forceinline__ void fft_lds(float2* s, int logL, int batch,
     else if (n16 > 0) { n16 -= 1; n8 = 1; n4 = 1; }
     else { n2 = 1; }
   }
+  const int npass = n16 + n8 + n4 + n2;
+  int p = 0;
+  // pass p of radix R; the first honours PIN, the last POUT
+  auto pass = [&](auto rtag) {
+    constexpr int R = decltype(rtag)::value;
+    constexpr int NB = VPT / R;
+    const bool first = p == 0, last = p == npass - 1;
+    if (PIN && first && POUT && last)
+      fft_pass<R, NB, PIN, POUT>(s, logL, logNs, batch, tw, logTw, dir);
+    else if (PIN && first)
+      fft_pass<R, NB, PIN, false>(s, logL, logNs, batch, tw, logTw, dir);
+    else if (POUT && last)
+      fft_pass<R, NB, false, POUT>(s, logL, logNs, batch, tw, logTw, dir);
+    else
+      fft_pass<R, NB>(s, logL, logNs, batch, tw, logTw, dir);
+    logNs += Log2C<R>::v;
+    ++p;
+  };
   if constexpr (R16 && VPT >= 16) {
 #pragma unroll
-    for (int p = 0; p < n16; ++p) {
-      fft_pass<16, VPT / 16>(s, logL, logNs, batch, tw, logTw, dir);
-      logNs += 4;
-    }
+    for (int q = 0; q < n16; ++q) pass(RadixTag<16>{});
   }
 #pragma unroll
-  for (int p = 0; p < n8; ++p) {
-    fft_pass<8, VPT / 8>(s, logL, logNs, batch, tw, logTw, dir);
-    logNs += 3;
-  }
+  for (int q = 0; q < n8; ++q) pass(RadixTag<8>{});
 #pragma unroll
-  for (int p = 0; p < n4; ++p) {
-    fft_pass<4, VPT / 4>(s, logL, logNs, batch, tw, logTw, dir);
-    logNs += 2;
-  }
+  for (int q = 0; q < n4; ++q) pass(RadixTag<4>{});
 #pragma unroll
-  for (int p = 0; p < n2; ++p) {
-    fft_pass<2, VPT / 2>(s, logL, logNs, batch, tw, logTw, dir);
-    logNs += 1;
-  }
+  for (int q = 0; q < n2; ++q) pass(RadixTag<2>{});
 }
 
 }  // namespace llgc

@@ -281,8 +281,9 @@ __global__ __launch_bounds__(T) void k_xfwd(
     const float* yc = ys + (size_t)c * N + (size_t)z * plane;
     double fc = 0.0;
     if (V4) {
-      // quads of 4 consecutive x; row pair p: rows y0+2p (re), y0+2p+1 (im)
-      const int qpr = Px >> 2;               // quads per padded row
+      // quads of 4 consecutive x; row pair p: rows y0+2p (re), y0+2p+1 (im);
+      // x < Px/2 only: the rest is zero padding the first pass does not read
+      const int qpr = Px >> 3;               // quads per half row
       const int nq = np * qpr;
       constexpr int U = 4;
       for (int q0 = threadIdx.x; q0 < nq; q0 += T * U) {
@@ -326,9 +327,10 @@ __global__ __launch_bounds__(T) void k_xfwd(
         }
       }
     } else {
-      const int tot = np * Px;
+      const int xl = Px > 1 ? Px >> 1 : 1;   // lower half of the row
+      const int tot = np * xl;
       for (int e = threadIdx.x; e < tot; e += T) {
-        const int p = e / Px, x = e - p * Px;
+        const int p = e / xl, x = e - p * xl;
         float2 v = make_float2(0.f, 0.f);
         if (x < nx) {
           const int ya = y0 + 2 * p;
@@ -345,13 +347,13 @@ __global__ __launch_bounds__(T) void k_xfwd(
             fc += (double)msv * (double)mv;
           }
         }
-        if (P.demag) lds[pidx(e)] = v;
+        if (P.demag) lds[pidx(p * Px + x)] = v;
       }
     }
     facc[0] += fc * br[c];
     if (!P.demag) continue;
     __syncthreads();
-    fft_lds<VPT, false, LP>(lds, P.logPx, np, twl, logTw, -1.f);
+    fft_lds<VPT, false, LP, true, false>(lds, P.logPx, np, twl, logTw, -1.f);
     // split the two real transforms and write the half spectrum: rows
     // (y0+2p, y0+2p+1) are adjacent -> one 16-byte store per (kx, p)
     const int H = P.Hx;
@@ -583,9 +585,11 @@ __global__ __launch_bounds__(T) void k_yspec(
   const int ncol = Wb * nz3;
   const float2* src = spec + (size_t)kx0 * nz3 * nyp;
   const float2* srcn = spec + (size_t)hxn * nz3 * nyp;
-  if (Py >= 2) {
-    // pairs of rows (y, y+1) per 16-byte load
-    const int hp = Py >> 1;
+  if (Py >= 4) {
+    // pairs of rows (y, y+1) per 16-byte load, lower half of each column
+    // only: rows >= Py/2 are zero padding and the first pass does not read
+    // them
+    const int hp = Py >> 2;
     const int tot = ncol * hp;
     constexpr int U = 8;
     for (int e0 = threadIdx.x; e0 < tot; e0 += T * U) {
@@ -606,18 +610,20 @@ __global__ __launch_bounds__(T) void k_yspec(
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int e = e0 + u * T;
-        if (e < tot) *(float4*)(lds + pidx(2 * e)) = v[u];
+        const int col = e / hp, y = (e - col * hp) << 1;
+        if (e < tot) *(float4*)(lds + pidx(col * Py + y)) = v[u];
       }
     }
   } else {
+    // Py = 1 or 2: row 0 is the only data row
     for (int e = threadIdx.x; e < ncol; e += T) {
       float2 v = src[(size_t)e * nyp];
       if (has_pair && e < nz3) v.y = srcn[(size_t)e * nyp].x;
-      lds[pidx(e)] = v;
+      lds[pidx(e * Py)] = v;
     }
   }
   __syncthreads();
-  fft_lds<VPTY, true, LP>(lds, P.logPy, ncol, twl, logTw, -1.f);
+  fft_lds<VPTY, true, LP, true, false>(lds, P.logPy, ncol, twl, logTw, -1.f);
   // pointwise product: per (w, ky), all 3*nz values
   const int Hy = P.Hy;
   for (int e = threadIdx.x; e < Wb * Py; e += T) {
@@ -660,7 +666,7 @@ __global__ __launch_bounds__(T) void k_yspec(
     for (int q = 0; q < nz3; ++q) lds[pidx((w * nz3 + q) * Py + ky)] = Hf[q];
   }
   __syncthreads();
-  fft_lds<VPTY, true, LP>(lds, P.logPy, ncol, twl, logTw, 1.f);
+  fft_lds<VPTY, true, LP, false, true>(lds, P.logPy, ncol, twl, logTw, 1.f);
   float2* dst = spec + (size_t)kx0 * nz3 * nyp;
   float2* dstn = spec + (size_t)hxn * nz3 * nyp;
   if (Py >= 2) {
@@ -1087,7 +1093,7 @@ __global__ __launch_bounds__(T) void k_xfield(
       }
     }
     __syncthreads();
-    fft_lds<VPT, false, LP>(lds, P.logPx, 3 * np, twl, logTw, 1.f);
+    fft_lds<VPT, false, LP, false, true>(lds, P.logPx, 3 * np, twl, logTw, 1.f);
   }
   field_cells(P, ys, ctl, partials, stage, R, E, z, y0,
               [&](int r, int x) {
