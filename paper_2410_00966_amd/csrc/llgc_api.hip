@@ -712,8 +712,8 @@ int llgc_create_ex(const llgc_grid* g, void* stream, int flags,
   while (c->Ty < kTyMax && W * col > VPTY * c->Ty) c->Ty *= 2;
   // One wavefront per transform with the FFT in registers where that was
   // measured faster than the LDS Stockham kernels (gfx950, DP45 steps of
-  // 64^2 x 4 ... 1024^2 x 2 grids): y columns of 128..512 points, forward
-  // x rows of 64..512, field-pass x rows of 64..128.  Longer transforms
+  // 32^2 x 2 ... 1024^2 x 2 grids): y columns of 128..512 points, forward
+  // x rows of 64..256, field-pass x rows of 64..128.  Longer transforms
   // need 128+ VGPRs per lane in registers (2 waves per SIMD) and lose.
   const bool lds_y = getenv("LLGC_LDS_YFFT") != nullptr;
   const bool lds_x = getenv("LLGC_LDS_XFFT") != nullptr;
@@ -721,7 +721,7 @@ int llgc_create_ex(const llgc_grid* g, void* stream, int flags,
   c->use_wy = !lds_y && (wave_all ? (c->Py >= 64 && (c->Py < 2048 || c->nz <= 2))
                                   : (c->Py >= 128 && c->Py <= 512));
   c->Ww = std::max(1, 6 / (3 * c->nz));
-  c->use_wxf = !lds_x && c->Px >= 64 && (wave_all || c->Px <= 512);
+  c->use_wxf = !lds_x && c->Px >= 64 && (wave_all || c->Px <= 256);
   c->use_wxi = !lds_x && c->Px >= 64 && (wave_all || c->Px <= 128);
   c->Rw = (((c->ny + 3) / 4) * c->nz >= 512) ? 4 : 2;
   if (const char* s = getenv("LLGC_RW")) c->Rw = (atoi(s) >= 4) ? 4 : 2;

@@ -572,7 +572,8 @@ __global__ __launch_bounds__(T) void k_yspec(
     __syncthreads();
   }
   constexpr int nz3 = 3 * NZ;
-  const int ny = P.ny, nyp = P.nyp, Py = P.Py;
+  const int lpy = LP > 0 ? LP : P.logPy;
+  const int ny = P.ny, nyp = P.nyp, Py = 1 << lpy;
   // Column slots: slot s >= 1 is kx = s; slot 0 carries the two real
   // columns kx = 0 (real part) and kx = Px/2 (imaginary part) as one complex
   // sequence (Px >= 2), so the Px/2 + 1 columns fill exactly Px/2 slots.
@@ -597,7 +598,7 @@ __global__ __launch_bounds__(T) void k_yspec(
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int e = e0 + u * T;
-        const int col = e / hp, y = (e - col * hp) << 1;
+        const int col = e >> (lpy - 2), y = (e & (hp - 1)) << 1;
         v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (e < tot && y < ny) {
           v[u] = *(const float4*)(src + (size_t)col * nyp + y);
@@ -610,7 +611,7 @@ __global__ __launch_bounds__(T) void k_yspec(
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int e = e0 + u * T;
-        const int col = e / hp, y = (e - col * hp) << 1;
+        const int col = e >> (lpy - 2), y = (e & (hp - 1)) << 1;
         if (e < tot) *(float4*)(lds + pidx(col * Py + y)) = v[u];
       }
     }
@@ -627,7 +628,7 @@ __global__ __launch_bounds__(T) void k_yspec(
   // pointwise product: per (w, ky), all 3*nz values
   const int Hy = P.Hy;
   for (int e = threadIdx.x; e < Wb * Py; e += T) {
-    const int w = e / Py, ky = e - w * Py;
+    const int w = e >> lpy, ky = e & (Py - 1);
     float2 M[nz3], Hf[nz3];
     if (has_pair && w == 0) {
       // slot 0: split Z = X0 + i XN at (ky, -ky), apply each column's
@@ -669,11 +670,13 @@ __global__ __launch_bounds__(T) void k_yspec(
   fft_lds<VPTY, true, LP, false, true>(lds, P.logPy, ncol, twl, logTw, 1.f);
   float2* dst = spec + (size_t)kx0 * nz3 * nyp;
   float2* dstn = spec + (size_t)hxn * nz3 * nyp;
-  if (Py >= 2) {
-    const int hq = nyp >> 1;          // row pairs actually stored
+  if (Py >= 4) {
+    // row pairs of the lower half; those at y >= nyp are not stored
+    const int hq = Py >> 2;
     const int tot = ncol * hq;
     for (int e = threadIdx.x; e < tot; e += T) {
-      const int col = e / hq, y = (e - col * hq) << 1;
+      const int col = e >> (lpy - 2), y = (e & (hq - 1)) << 1;
+      if (y >= nyp) continue;
       float4 v = *(const float4*)(lds + pidx(col * Py + y));
       if (y + 1 >= ny) { v.z = 0.f; v.w = 0.f; }   // keep the pad zero
       if (has_pair && col < nz3) {
@@ -684,8 +687,9 @@ __global__ __launch_bounds__(T) void k_yspec(
       *(float4*)(dst + (size_t)col * nyp + y) = v;
     }
   } else {
+    // Py = 1 or 2: row 0 is the only data row (the pad row stays zero)
     for (int e = threadIdx.x; e < ncol; e += T) {
-      const float2 v = lds[pidx(e)];
+      const float2 v = lds[pidx(e * Py)];
       if (has_pair && e < nz3) {
         dstn[(size_t)e * nyp] = make_float2(v.y, 0.f);
         dst[(size_t)e * nyp] = make_float2(v.x, 0.f);
@@ -953,8 +957,14 @@ __device__ __forceinline__ void field_cells(const Prm& P,
   double acc[3] = {0.0, 0.0, 0.0};
   float emax = 0.f;
   const int ncellb = R * nx;
+  // (r, x) of element e advanced incrementally (no division per cell)
+  const int sr = blockDim.x / nx, sx = blockDim.x - sr * nx;
+  int ri = threadIdx.x / nx, xi = threadIdx.x - ri * nx;
   for (int e = threadIdx.x; e < ncellb; e += blockDim.x) {
-    const int r = e / nx, x = e - r * nx;
+    const int r = ri, x = xi;
+    xi += sx;
+    ri += sr;
+    if (xi >= nx) { xi -= nx; ++ri; }
     const int y = y0 + r;
     if (y >= ny) continue;
     const int i = (z * ny + y) * nx + x;
