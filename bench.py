@@ -63,10 +63,9 @@ def kernel_bytes(plan, prob, method, kernel):
     return 0
 
 
-def counted_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the library sources as they are now;
-    otherwise None (the kernel changed since the counters were taken)."""
+def _counter_line(tag, kernel):
+    """Value of `tag kernel V sources H` in the committed counter summary
+    when H is the hash of the library sources as they are now, else None."""
     import glob
     import hashlib
     path = os.path.join(ROOT, "profiles", "film_1024x1024x2_hbm_counters.md")
@@ -79,10 +78,17 @@ def counted_traffic(kernel):
             h.update(fh.read())
     for line in open(path):
         w = line.split()
-        if (len(w) == 5 and w[0] == "traffic_bytes_per_launch"
-                and w[1] == kernel and w[3] == "sources"):
+        if (len(w) == 5 and w[0] == tag and w[1] == kernel
+                and w[3] == "sources"):
             return float(w[2]) if w[4] == h.hexdigest()[:16] else None
     return None
+
+
+def counted_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the library sources as they are now;
+    otherwise None (the kernel changed since the counters were taken)."""
+    return _counter_line("traffic_bytes_per_launch", kernel)
 
 
 def cpu_baseline(prob, m0, dt):
@@ -103,6 +109,59 @@ def cpu_baseline(prob, m0, dt):
                         "evaluations, numpy float64, one thread) of the "
                         f"relaxed {prob.nx}x{prob.ny}x{prob.nz} film at "
                         f"dt = {dt:.3g} s: {el:.1f} s"))
+
+
+def bench_batched(torch, t_end, n_plain):
+    """The 512-instance size/coupling sweep (grids U{16..128}^2 x U{1..4} of
+    5 nm cells, Dormand-Prince tol 1e-6) as one batch, against a sample of
+    the same instances solved one after another with standalone contexts.
+    Set-up (contexts, demag kernels) is outside both timed regions."""
+    from paper_2410_00966_amd import inputs as I
+    from paper_2410_00966_amd.llgc import Batch, Sim
+    inst = I.c4_instances()
+    probs = [p for p, _, _ in inst]
+    m0s = [m0 for _, m0, _ in inst]
+    t_set = time.perf_counter()
+    b = Batch(probs)
+    for s, m0 in zip(b.sims, m0s):
+        s.set_state(torch.from_numpy(m0))
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_set
+    t0 = time.perf_counter()
+    _, infos, st = b.run(t_end=t_end)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assert (st == 0).all(), st
+    cs = sum(p.ncells * i["accepted"] for p, i in zip(probs, infos))
+    b.close()
+    idx = np.linspace(0, len(probs) - 1, n_plain).round().astype(int)
+    wall_p, cs_p = 0.0, 0
+    for k in idx:
+        s = Sim(probs[k])
+        s.set_state(torch.from_numpy(m0s[k]))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, info = s.run(t_end=t_end)
+        torch.cuda.synchronize()
+        wall_p += time.perf_counter() - t1
+        cs_p += probs[k].ncells * info["accepted"]
+        s.close()
+    rate_b, rate_p = cs / wall, cs_p / wall_p
+    return {
+        "workload": ("512 ragged instances, grids U{16..128}^2 x U{1..4} of "
+                     "5 nm, g/wc log-uniform 1e-3..1e-1, Bz U(0,0.3) T, "
+                     f"wc/2pi 5..15 GHz, Dormand-Prince tol 1e-6 to "
+                     f"{t_end * 1e12:g} ps"),
+        "value": rate_b, "unit": "cell-steps/s",
+        "cells": int(sum(p.ncells for p in probs)),
+        "accepted_total": int(sum(i["accepted"] for i in infos)),
+        "wall_s": wall, "setup_s": round(setup_s, 2),
+        "plain": {"value": rate_p, "unit": "cell-steps/s",
+                  "sample": (f"{len(idx)} evenly spaced instances solved one "
+                             "after another, standalone contexts"),
+                  "wall_s": wall_p},
+        "speedup_vs_plain": rate_b / rate_p,
+    }
 
 
 def bench_wire(torch, nsteps):
@@ -294,6 +353,10 @@ def main():
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": counted_traffic(dom),
+            # fraction of the launch the SIMDs spend issuing its VALU
+            # instructions (counted; the kernel's actual limiter)
+            "valu_issue_frac": _counter_line("valu_issue_frac_per_launch",
+                                             dom),
             "bytes_per_launch": byts, "avg_launch_us": per_launch_s * 1e6,
         }
         counts = {k: v[1] / info["accepted"] for k, v in kt.items()}
