@@ -84,11 +84,12 @@ def test_tensor_matches_oracle(torch, grid, cell):
     s.close()
 
 
-# the last three have 2048-point y transforms (ragged ny), the case the
-# ky-parity split spectral pass serves (512- and 1024-thread workgroups)
+# the last five have long y transforms with ragged ny: 2048 points with
+# nz = 1..4 (the last two through the ky-parity split pass) and 1024 points
+# with nz = 4 (the length-specialised LDS pass)
 FIELD_GRIDS = [(32, 32, 1), (37, 23, 3), (1, 1, 1), (1, 9, 2), (16, 1, 4),
                (64, 8, 2), (5, 3, 4), (20, 600, 2), (12, 530, 3),
-               (9, 700, 1)]
+               (9, 700, 1), (6, 300, 4), (5, 520, 4)]
 
 
 @pytest.mark.parametrize("grid", FIELD_GRIDS)
