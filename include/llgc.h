@@ -217,6 +217,10 @@ int llgc_demag_tensor(llgc_ctx *ctx, double *out, int64_t cap);
  * launch counts, and writes the kernel names joined by ';' into `names`
  * (size names_cap).  Synchronises the stream.  `reset` != 0 clears. */
 int llgc_set_timing(llgc_ctx *ctx, int32_t enable);
+/* Restricts timing to the launches of one kernel (name as reported by
+ * llgc_kernel_times; NULL or "" = all kernels), so that the events perturb
+ * a timed run as little as possible.  Events are pooled per context. */
+int llgc_set_timing_only(llgc_ctx *ctx, const char *kernel);
 int llgc_kernel_times(llgc_ctx *ctx, double *ms, int64_t *launches,
                       int32_t cap, char *names, int32_t names_cap,
                       int32_t reset);

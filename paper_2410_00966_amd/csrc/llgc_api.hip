@@ -87,6 +87,8 @@ struct llgc_ctx {
   double kernel_mu0 = 0.0;
   std::string err;
   bool timing = false;
+  std::string timing_only;            // time only this kernel ("" = all)
+  std::vector<hipEvent_t> event_pool; // reusable timing events
   std::map<std::string, TimerRec> timers;
 };
 
@@ -117,19 +119,24 @@ int pow2_ceil(int v) {
 }
 
 // Events around a launch when timing is on.
+hipEvent_t pooled_event(llgc_ctx* c);
+
 struct Timed {
   llgc_ctx* c;
   const char* name;
+  bool on;
   hipEvent_t a = nullptr, b = nullptr;
-  Timed(llgc_ctx* cc, const char* n) : c(cc), name(n) {
-    if (c->timing) {
-      hipEventCreate(&a);
-      hipEventCreate(&b);
+  Timed(llgc_ctx* cc, const char* n)
+      : c(cc), name(n),
+        on(cc->timing && (cc->timing_only.empty() || cc->timing_only == n)) {
+    if (on) {
+      a = pooled_event(c);
+      b = pooled_event(c);
       hipEventRecord(a, c->stream);
     }
   }
   ~Timed() {
-    if (c->timing) {
+    if (on) {
       hipEventRecord(b, c->stream);
       auto& t = c->timers[name];
       t.pending.emplace_back(a, b);
@@ -625,6 +632,17 @@ void fill_prm(llgc_ctx* c) {
   P.dt_max = p.dt_max > 0 ? p.dt_max : 1e-10;
 }
 
+hipEvent_t pooled_event(llgc_ctx* c) {
+  hipEvent_t e = nullptr;
+  if (!c->event_pool.empty()) {
+    e = c->event_pool.back();
+    c->event_pool.pop_back();
+  } else {
+    hipEventCreate(&e);
+  }
+  return e;
+}
+
 int timers_collect(llgc_ctx* c) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (auto& kv : c->timers) {
@@ -632,8 +650,8 @@ int timers_collect(llgc_ctx* c) {
       float ms = 0.f;
       hipEventElapsedTime(&ms, pr.first, pr.second);
       kv.second.ms += ms;
-      hipEventDestroy(pr.first);
-      hipEventDestroy(pr.second);
+      c->event_pool.push_back(pr.first);
+      c->event_pool.push_back(pr.second);
     }
     kv.second.pending.clear();
   }
@@ -857,6 +875,7 @@ int llgc_destroy(llgc_ctx* c) {
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
   timers_collect(c);
+  for (hipEvent_t e : c->event_pool) hipEventDestroy(e);
   hipFree(c->yn);
   hipFree(c->yb[0]);
   hipFree(c->yb[1]);
@@ -1212,6 +1231,12 @@ int llgc_demag_tensor(llgc_ctx* c, double* out, int64_t cap) {
 int llgc_set_timing(llgc_ctx* c, int32_t enable) {
   if (!c) return LLGC_E_ARG;
   c->timing = enable != 0;
+  return LLGC_OK;
+}
+
+int llgc_set_timing_only(llgc_ctx* c, const char* kernel) {
+  if (!c) return LLGC_E_ARG;
+  c->timing_only = kernel ? kernel : "";
   return LLGC_OK;
 }
 

@@ -28,7 +28,7 @@ EXPORTED = ("llgc_create", "llgc_destroy", "llgc_last_error",
             "llgc_demag_tensor", "llgc_set_timing", "llgc_kernel_times",
             "llgc_plan_info", "llgc_create_ex", "llgc_batch_create",
             "llgc_batch_destroy", "llgc_batch_last_error",
-            "llgc_batch_instance", "llgc_batch_run")
+            "llgc_batch_instance", "llgc_batch_run", "llgc_set_timing_only")
 PLAN_BATCH = 1
 
 
@@ -121,6 +121,7 @@ def load():
         "llgc_batch_instance": ([vp, i32], vp),
         "llgc_batch_run": ([vp, i64, dbl, i32, P(dbl), i64, P(i64),
                             P(RunInfo), P(i32)], ctypes.c_int),
+        "llgc_set_timing_only": ([vp, ctypes.c_char_p], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -318,9 +319,12 @@ class Sim:
             "llgc_demag_tensor")
         return out.reshape(6, self.prob.nz, self.prob.ny, self.prob.nx)
 
-    def set_timing(self, on=True):
+    def set_timing(self, on=True, only=None):
+        """Per-kernel HIP-event timing; `only` restricts it to one kernel."""
         self._check(self.L.llgc_set_timing(self.h, 1 if on else 0),
                     "llgc_set_timing")
+        self._check(self.L.llgc_set_timing_only(
+            self.h, only.encode() if only else None), "llgc_set_timing_only")
 
     def kernel_times(self, reset=False):
         cap = 32
