@@ -773,7 +773,7 @@ int llgc_create_ex(const llgc_grid* g, void* stream, int flags,
   }
   const size_t twb = sizeof(float2) * lds_twiddles(c->logTw);  // LDS twiddles
   c->lds_f = twb + sizeof(float2) * padded_len((size_t)(c->Rf / 2) * c->Px);
-  c->lds_i = twb + sizeof(float2) * padded_len((size_t)3 * (c->Ri / 2) * c->Px);
+  c->lds_i = sizeof(float2) * padded_len_s<6>((size_t)3 * (c->Ri / 2) * c->Px);
   c->lds_y = twb + sizeof(float2) * padded_len((size_t)W * col);
   int dev = 0, maxlds = 65536;
   hipGetDevice(&dev);

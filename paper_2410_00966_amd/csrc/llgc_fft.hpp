@@ -15,6 +15,16 @@ namespace llgc {
 // strided Stockham stores over the banks and keeps even indices 16-byte
 // aligned (pairs 2i, 2i+1 never straddle a gap).
 __host__ __device__ __forceinline__ int pidx(int i) { return i + ((i >> 4) << 1); }
+// The same with 2 slots every 2^PS values (PS = 4 is pidx): less LDS for
+// kernels whose occupancy is bound by it, at more bank conflicts.
+template <int PS>
+__host__ __device__ __forceinline__ int pidx_s(int i) {
+  return i + ((i >> PS) << 1);
+}
+template <int PS>
+__host__ __device__ __forceinline__ size_t padded_len_s(size_t n) {
+  return n + ((n >> PS) << 1) + 2;
+}
 __host__ __device__ __forceinline__ size_t padded_len(size_t n) {
   return n + ((n >> 4) << 1) + 2;
 }
@@ -153,7 +163,7 @@ __device__ __forceinline__ void dft_in_half(float2* v, float s) {
 // PIN (first pass only, Ns = 1): inputs at positions >= L/2 are zero and
 // are not read.  POUT (last pass only, Ns = L/R): outputs at positions
 // >= L/2 are not needed and are not written.
-template <int R, int NB, bool PIN = false, bool POUT = false>
+template <int R, int NB, bool PIN = false, bool POUT = false, int PS = 4>
 __device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
                                          int batch, const float2* tw,
                                          int logTw, float dir) {
@@ -178,7 +188,7 @@ __device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
       const int base = t << logL;
 #pragma unroll
       for (int q = 0; q < (PIN ? R / 2 : R); ++q)
-        v[i][q] = s[pidx(base + j + q * Lr)];
+        v[i][q] = s[pidx_s<PS>(base + j + q * Lr)];
       const int k = j & (Ns - 1);
       if (k != 0) w1[i] = tw[(k << twshift) & twmask];
     }
@@ -205,7 +215,7 @@ __device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
       const int out0 = (t << logL) + ((j - k) << logR) + k;
 #pragma unroll
       for (int q = 0; q < (POUT ? R / 2 : R); ++q)
-        s[pidx(out0 + q * Ns)] = v[i][q];
+        s[pidx_s<PS>(out0 + q * Ns)] = v[i][q];
     }
   }
   __syncthreads();
@@ -221,7 +231,7 @@ __device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
 // pass does not read it).  POUT: only outputs below L/2 are used (the last
 // pass does not write the rest).
 template <int VPT, bool R16 = false, int LOGL = 0, bool PIN = false,
-          bool POUT = false>
+          bool POUT = false, int PS = 4>
 __device__ __forceinline__ void fft_lds(float2* s, int logL, int batch,
                                         const float2* tw,
                         int logTw, float dir) {
@@ -248,13 +258,14 @@ __device__ __forceinline__ void fft_lds(float2* s, int logL, int batch,
     constexpr int NB = VPT / R;
     const bool first = p == 0, last = p == npass - 1;
     if (PIN && first && POUT && last)
-      fft_pass<R, NB, PIN, POUT>(s, logL, logNs, batch, tw, logTw, dir);
+      fft_pass<R, NB, PIN, POUT, PS>(s, logL, logNs, batch, tw, logTw, dir);
     else if (PIN && first)
-      fft_pass<R, NB, PIN, false>(s, logL, logNs, batch, tw, logTw, dir);
+      fft_pass<R, NB, PIN, false, PS>(s, logL, logNs, batch, tw, logTw, dir);
     else if (POUT && last)
-      fft_pass<R, NB, false, POUT>(s, logL, logNs, batch, tw, logTw, dir);
+      fft_pass<R, NB, false, POUT, PS>(s, logL, logNs, batch, tw, logTw, dir);
     else
-      fft_pass<R, NB>(s, logL, logNs, batch, tw, logTw, dir);
+      fft_pass<R, NB, false, false, PS>(s, logL, logNs, batch, tw, logTw,
+                                        dir);
     logNs += Log2C<R>::v;
     ++p;
   };

@@ -1054,11 +1054,11 @@ __global__ __launch_bounds__(T) void k_xfield(
     Ctl* __restrict__ ctl, double* __restrict__ partials,
     double* __restrict__ rec, int stage, int R, Epi E,
     const float2* __restrict__ tw, int logTw) {
-  extern __shared__ float2 lds_all[];
+  // LDS: the 3 (R/2) transforms only, lightly padded (2 slots per 64), so
+  // that three workgroups fit a CU; twiddles are read from global memory
+  extern __shared__ float2 lds[];
   if (ctl->done) return;
-  float2* twl = lds_all;
-  float2* lds = lds_all + lds_twiddles(logTw);
-  if (P.demag) stage_twiddles(twl, tw, logTw);
+  constexpr int PS = 6;
   const int nblk = gridDim.x;
   const int nz = P.nz;
   const int tile = xcd_tile(blockIdx.x, nblk);
@@ -1097,21 +1097,22 @@ __global__ __launch_bounds__(T) void k_xfield(
         float2 A = make_float2(v[u].x, v[u].y), B = make_float2(v[u].z, v[u].w);
         if (k == 0 || 2 * k == Px) { A.y = 0.f; B.y = 0.f; }
         const int sp = (c * np + p) * Px;
-        lds[pidx(sp + k)] = make_float2(A.x - B.y, A.y + B.x);
+        lds[pidx_s<PS>(sp + k)] = make_float2(A.x - B.y, A.y + B.x);
         if (k != 0 && 2 * k != Px)
-          lds[pidx(sp + Px - k)] = make_float2(A.x + B.y, -A.y + B.x);
+          lds[pidx_s<PS>(sp + Px - k)] = make_float2(A.x + B.y, -A.y + B.x);
       }
     }
     __syncthreads();
-    fft_lds<VPT, false, LP, false, true>(lds, P.logPx, 3 * np, twl, logTw, 1.f);
+    fft_lds<VPT, false, LP, false, true, PS>(lds, P.logPx, 3 * np, tw, logTw,
+                                             1.f);
   }
   field_cells(P, ys, ctl, partials, stage, R, E, z, y0,
               [&](int r, int x) {
                 const int p = r >> 1;
                 const bool hi = r & 1;
-                const float2 vx = lds[pidx((0 * np + p) * Px + x)];
-                const float2 vy = lds[pidx((1 * np + p) * Px + x)];
-                const float2 vz = lds[pidx((2 * np + p) * Px + x)];
+                const float2 vx = lds[pidx_s<PS>((0 * np + p) * Px + x)];
+                const float2 vy = lds[pidx_s<PS>((1 * np + p) * Px + x)];
+                const float2 vz = lds[pidx_s<PS>((2 * np + p) * Px + x)];
                 return hi ? make_float3(vx.y, vy.y, vz.y)
                           : make_float3(vx.x, vy.x, vz.x);
               }, blockIdx.x);
