@@ -312,8 +312,9 @@ def main():
     if not args.no_timing:
         sim.set_timing(True)
         sim.kernel_times(reset=True)
+    winfo = None
     if args.warmup > 0:
-        sim.run(nsteps=args.warmup, t_end=1.0)
+        _, winfo = sim.run(nsteps=args.warmup, t_end=1.0)
     if not args.no_timing:
         kw = sim.kernel_times(reset=True)
         kw = kw or {"k_yspec": (1.0, 1)}
@@ -368,8 +369,17 @@ def main():
                                              dom),
             "bytes_per_launch": byts, "avg_launch_us": per_launch_s * 1e6,
         }
-        # per-kernel table from the warm-up (all kernels timed there)
-        counts = {k: v[1] / max(1, args.warmup) for k, v in kw.items()}
+        # per-kernel table from the warm-up (all kernels timed there).
+        # Model bytes per step count the launches that did work: one per
+        # right-hand-side evaluation for the stage kernels, one per attempt
+        # for the step kernels (launches queued past the end of a run exit
+        # at once on the device flag and move no data).
+        wi = winfo or info
+        acc = max(1, wi["accepted"])
+        per_att = (wi["accepted"] + wi["rejected"]) / acc
+        counts = {k: (wi["rhs_evals"] / acc
+                      if k in ("k_xfwd", "k_yspec", "k_xfield") else per_att)
+                  for k in kw}
         sb = sum(kernel_bytes(plan, prob, "dp45", k) * c
                  for k, c in counts.items())
         out["kernels"] = {k: {"ms": round(v[0], 3), "launches": v[1],
