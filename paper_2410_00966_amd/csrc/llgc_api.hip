@@ -38,7 +38,7 @@ constexpr int kMaxLen = 2048;         // largest padded FFT length per axis
 constexpr size_t kLdsCap = 120 * 1024; // LDS per workgroup this plan uses
 constexpr int kBatchMaxLen = 256;     // batched plan: padded length per axis
 constexpr int kBatchRows = 4;         // batched plan: rows per x-pass tile
-constexpr int kBatchYWaves = 12;      // batched plan: wavefronts per y block
+constexpr int kBatchTy = kBYT;        // batched plan: spectral workgroup threads
 
 struct TimerRec {
   double ms = 0.0;
@@ -54,7 +54,7 @@ struct llgc_ctx {
   double dx, dy, dz;
   int Px, Py, Hx, Hy, logPx, logPy, logTw;
   int Rf, Ri, W, Ty;
-  int Ww = 1;            // kx columns per wavefront-FFT spectral block
+  int Ww = 1;            // kx columns per register-FFT spectral block
   bool use_wy = false;   // register (wavefront) FFT along y
   bool use_wxf = false;  // register (wavefront) FFT in the forward x pass
   bool use_wxi = false;  // register (wavefront) inverse FFT in the field pass
@@ -746,10 +746,17 @@ int llgc_create_ex(const llgc_grid* g, void* stream, int flags,
   c->Rwf = 2;
   if (const char* s = getenv("LLGC_RWF")) c->Rwf = (atoi(s) >= 4) ? 4 : 2;
   if (bplan) {
-    // the fixed plan of every batched instance (no tuning overrides)
-    c->use_wxf = c->use_wxi = c->use_wy = true;
+    // the fixed plan of every batched instance (no tuning overrides):
+    // register FFTs along x, the LDS spectral pass with kBatchTy threads
+    // and as many column slots per workgroup as its VPTY * kBatchTy
+    // elements hold (measured 1.3-2x faster per element than the register
+    // spectral pass at 64..256 points once the GPU is full)
+    c->use_wxf = c->use_wxi = true;
+    c->use_wy = false;
     c->Rw = c->Rwf = kBatchRows;
-    c->Ww = std::max(1, kBatchYWaves / (3 * c->nz));
+    c->Ty = kBatchTy;
+    W = std::max(1, std::min(VPTY * kBatchTy / col, c->Px / 2));
+    c->W = W;
   }
   // the ky-parity split of the LDS spectral pass: half the LDS per
   // workgroup (two workgroups per CU) for long columns
@@ -763,7 +770,8 @@ int llgc_create_ex(const llgc_grid* g, void* stream, int flags,
                       hcol <= kYhEpt * c->Tyh && hcol <= VPTY * c->Tyh;
     // used where a whole column set exceeds one workgroup (nz = 3, 4 at
     // 2048 points); elsewhere the unsplit pass measured faster
-    c->yhalf = fits && ((W * col > ycap) || (c->nz <= 3 && s && atoi(s)));
+    c->yhalf = !bplan && fits &&
+               ((W * col > ycap) || (c->nz <= 3 && s && atoi(s)));
     c->lds_yh = sizeof(float2) * (lds_twiddles(c->logTw) +
                                   padded_len((size_t)hcol));
   }

@@ -10,7 +10,7 @@
 namespace llgc {
 
 constexpr int kBXT = 384;   // x pass / field: 6 wavefronts (4-row tiles)
-constexpr int kBYT = 768;   // spectral pass: 12 wavefronts
+constexpr int kBYT = 512;   // spectral pass: 8 wavefronts (LDS FFT)
 constexpr int kBPT = 256;   // pointwise (k_begin) threads
 
 // Device-resident description of one instance.
@@ -19,8 +19,8 @@ struct BInst {
   Ctl* ctl;
   const float2* tw;
   int logTw;
-  int nrx, nry;         // Px / 64, Py / 64 (1, 2 or 4)
-  int Ww;               // kx columns per spectral workgroup
+  int nrx;              // Px / 64 (1, 2 or 4)
+  int W;                // column slots per spectral workgroup
   int nf;               // x-pass / field tiles
   int nbeg;             // k_begin workgroups
   float *yn, *k1, *y7, *k7, *y2;   // operands of the attempt start
@@ -53,20 +53,7 @@ __global__ __launch_bounds__(kBXT) void kb_xfwd(const BInst* __restrict__ I,
   }
 }
 
-template <int NZ>
-__device__ __forceinline__ void kb_yspec_nz(const BInst& B, int stage,
-                                            int mode, int blk, float2* lds) {
-#define LLGC_BY_ARGS B.P, B.spec, B.K, B.ctl, B.Ww, B.tw, B.logTw, \
-                     B.partials, B.nf, stage, mode, blk, lds
-  switch (B.nry) {
-    case 1: yspec_w_body<NZ, 1>(LLGC_BY_ARGS); break;
-    case 2: yspec_w_body<NZ, 2>(LLGC_BY_ARGS); break;
-    default: yspec_w_body<NZ, 4>(LLGC_BY_ARGS); break;
-  }
-#undef LLGC_BY_ARGS
-}
-
-__global__ __launch_bounds__(kBYT) void kb_yspec(const BInst* __restrict__ I,
+__global__ __launch_bounds__(kBYT, 4) void kb_yspec(const BInst* __restrict__ I,
                                                  const int2* __restrict__ it,
                                                  int stage, int mode) {
   extern __shared__ float2 lds[];
@@ -79,12 +66,15 @@ __global__ __launch_bounds__(kBYT) void kb_yspec(const BInst* __restrict__ I,
     finish_cavity(B.P, B.ctl, B.partials, B.nf, stage, mode, red);
     return;
   }
+#define LLGC_BY_ARGS B.P, B.spec, B.K, B.ctl, B.W, B.tw, B.logTw, \
+                     B.partials, B.nf, stage, mode, w.y, lds
   switch (B.P.nz) {
-    case 1: kb_yspec_nz<1>(B, stage, mode, w.y, lds); break;
-    case 2: kb_yspec_nz<2>(B, stage, mode, w.y, lds); break;
-    case 3: kb_yspec_nz<3>(B, stage, mode, w.y, lds); break;
-    default: kb_yspec_nz<4>(B, stage, mode, w.y, lds); break;
+    case 1: yspec_l_body<kBYT, 1, 0>(LLGC_BY_ARGS); break;
+    case 2: yspec_l_body<kBYT, 2, 0>(LLGC_BY_ARGS); break;
+    case 3: yspec_l_body<kBYT, 3, 0>(LLGC_BY_ARGS); break;
+    default: yspec_l_body<kBYT, 4, 0>(LLGC_BY_ARGS); break;
   }
+#undef LLGC_BY_ARGS
 }
 
 __global__ __launch_bounds__(kBXT) void kb_xfield(const BInst* __restrict__ I,

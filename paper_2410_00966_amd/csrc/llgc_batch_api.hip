@@ -13,6 +13,7 @@ struct llgc_batch {
   int* act = nullptr;
   int* flags = nullptr;        // [0]: finished count, [1 + k]: done flag k
   int n_x = 0, n_y = 0, n_b = 0, n_act = 0;
+  size_t cap_x = 0, cap_y = 0, cap_b = 0;   // work-table capacities
   size_t lds_x = 0, lds_f = 0, lds_y = 0;
   std::string err;
 };
@@ -38,8 +39,9 @@ int bfail(llgc_batch* b, int code, const char* fmt, ...) {
   } while (0)
 
 int b_tiles(const llgc_ctx* c) { return (int)xgrid(c, kBatchRows).x; }
+// spectral workgroups: column slots (kx = 0 and Px/2 share slot 0) per W
 int b_yblocks(const llgc_ctx* c) {
-  return c->P.demag ? (c->Hx + c->Ww - 1) / c->Ww : 1;
+  return c->P.demag ? (c->Px / 2 + c->W - 1) / c->W : 1;
 }
 
 BInst make_binst(llgc_ctx* c, bool rk4) {
@@ -49,8 +51,7 @@ BInst make_binst(llgc_ctx* c, bool rk4) {
   B.tw = c->tw;
   B.logTw = c->logTw;
   B.nrx = c->Px / 64;
-  B.nry = c->Py / 64;
-  B.Ww = c->Ww;
+  B.W = c->W;
   B.nf = b_tiles(c);
   B.nbeg = n_pointwise_blocks(c);
   // the operands launch_begin passes
@@ -93,6 +94,8 @@ int batch_tables(llgc_batch* b, const std::vector<char>& active) {
   b->n_b = (int)ib.size();
   b->n_act = (int)act.size();
   if (b->n_act == 0) return LLGC_OK;
+  if (ix.size() > b->cap_x || iy.size() > b->cap_y || ib.size() > b->cap_b)
+    return bfail(b, LLGC_E_STATE, "work tables exceed their allocation");
   BHIPCHK(b, hipMemcpy(b->it_x, ix.data(), ix.size() * sizeof(int2),
                        hipMemcpyHostToDevice));
   BHIPCHK(b, hipMemcpy(b->it_y, iy.data(), iy.size() * sizeof(int2),
@@ -140,13 +143,18 @@ int llgc_batch_create(const llgc_grid* grids, int32_t n, void* stream,
     }
     const llgc_ctx* c = b->inst[k];
     cx += b_tiles(c);
-    cy += (c->Hx + c->Ww - 1) / c->Ww;
+    cy += (c->Px / 2 + c->W - 1) / c->W;   // demag may be set later
     cb += n_pointwise_blocks(c);
     b->lds_x = std::max(b->lds_x, sizeof(float2) * (kBXT / 64) * c->Px);
     b->lds_f = std::max(b->lds_f, sizeof(float) * 3 * kBatchRows * c->nx);
-    b->lds_y = std::max(b->lds_y, sizeof(float2) * (kBYT / 64) *
-                                      std::min(c->Py / 64, 8) * 64);
+    b->lds_y = std::max(b->lds_y, c->lds_y);
   }
+  hipFuncSetAttribute((const void*)kb_yspec,
+                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)b->lds_y);
+  b->cap_x = cx;
+  b->cap_y = cy;
+  b->cap_b = cb;
   bool ok = hipMalloc(&b->dI, sizeof(BInst) * n) == hipSuccess &&
             hipMalloc(&b->it_x, sizeof(int2) * cx) == hipSuccess &&
             hipMalloc(&b->it_y, sizeof(int2) * cy) == hipSuccess &&

@@ -553,21 +553,21 @@ __device__ __forceinline__ void kernel_product(const float* __restrict__ Kp,
   }
 }
 
-// LP > 0: log2(Py) fixed at compile time (specialised FFT addressing).
+// Spectral pass of column block `blk` (a workgroup of T threads; LDS
+// `lds_all` as sized by the plan).  LP > 0: log2(Py) fixed at compile time
+// (specialised FFT addressing).
 template <int T, int NZ, int LP = 0>
-__global__ __launch_bounds__(T) void k_yspec(
-    Prm P, float2* __restrict__ spec, const float* __restrict__ K,
+__device__ __forceinline__ void yspec_l_body(
+    const Prm& P, float2* __restrict__ spec, const float* __restrict__ K,
     Ctl* __restrict__ ctl, int W, const float2* __restrict__ tw,
     int logTw, const double* __restrict__ partials, int nblk_f, int stage,
-    int mode) {
-  extern __shared__ float2 lds_all[];
+    int mode, int blk, float2* lds_all) {
   __shared__ double red[16];
-  if (ctl->done) return;
   float2* twl = lds_all;
   float2* lds = lds_all + lds_twiddles(logTw);
   stage_twiddles(twl, tw, logTw);
   // workgroup 0 also finishes the coupling sum of this stage
-  if (blockIdx.x == 0) {
+  if (blk == 0) {
     finish_cavity(P, ctl, partials, nblk_f, stage, mode, red);
     __syncthreads();
   }
@@ -580,9 +580,9 @@ __global__ __launch_bounds__(T) void k_yspec(
   const bool pair = P.Px >= 2;
   const int hxn = P.Px >> 1;
   const int nslot = pair ? hxn : P.Hx;
-  const int kx0 = blockIdx.x * W;
+  const int kx0 = blk * W;
   const int Wb = min(W, nslot - kx0);
-  const bool has_pair = pair && blockIdx.x == 0;   // slot 0 in this block
+  const bool has_pair = pair && blk == 0;   // slot 0 in this block
   const int ncol = Wb * nz3;
   const float2* src = spec + (size_t)kx0 * nz3 * nyp;
   const float2* srcn = spec + (size_t)hxn * nz3 * nyp;
@@ -634,25 +634,28 @@ __global__ __launch_bounds__(T) void k_yspec(
       // slot 0: split Z = X0 + i XN at (ky, -ky), apply each column's
       // kernel, recombine; the results are real sequences, so
       // W[-ky] = conj(Y0[ky]) + i conj(YN[ky]).  One thread per pair.
+      // (Y0 is parked in LDS while YN is formed: fewer live registers)
       if (2 * ky > Py) continue;
       const int km = (Py - ky) & (Py - 1);
-      float2 X0[nz3], XN[nz3], YN[nz3];
+      float2 XN[nz3];
 #pragma unroll
       for (int q = 0; q < nz3; ++q) {
         const float2 z = lds[pidx(q * Py + ky)];
         const float2 zm = lds[pidx(q * Py + km)];
-        X0[q] = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
+        M[q] = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
         XN[q] = make_float2(0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x));
       }
-      kernel_product<NZ>(K + (size_t)ky * 6 * NZ, 1.f, X0, Hf);
-      kernel_product<NZ>(K + ((size_t)hxn * Hy + ky) * 6 * NZ, 1.f, XN, YN);
+      kernel_product<NZ>(K + (size_t)ky * 6 * NZ, 1.f, M, Hf);
+#pragma unroll
+      for (int q = 0; q < nz3; ++q) lds[pidx(q * Py + ky)] = Hf[q];
+      kernel_product<NZ>(K + ((size_t)hxn * Hy + ky) * 6 * NZ, 1.f, XN, Hf);
 #pragma unroll
       for (int q = 0; q < nz3; ++q) {
-        lds[pidx(q * Py + ky)] = make_float2(Hf[q].x - YN[q].y,
-                                             Hf[q].y + YN[q].x);
+        const float2 y0 = lds[pidx(q * Py + ky)];
+        lds[pidx(q * Py + ky)] = make_float2(y0.x - Hf[q].y, y0.y + Hf[q].x);
         if (km != ky)
-          lds[pidx(q * Py + km)] = make_float2(Hf[q].x + YN[q].y,
-                                               -Hf[q].y + YN[q].x);
+          lds[pidx(q * Py + km)] = make_float2(y0.x + Hf[q].y,
+                                               -y0.y + Hf[q].x);
       }
       continue;
     }
@@ -698,6 +701,18 @@ __global__ __launch_bounds__(T) void k_yspec(
       }
     }
   }
+}
+
+template <int T, int NZ, int LP = 0>
+__global__ __launch_bounds__(T) void k_yspec(
+    Prm P, float2* __restrict__ spec, const float* __restrict__ K,
+    Ctl* __restrict__ ctl, int W, const float2* __restrict__ tw,
+    int logTw, const double* __restrict__ partials, int nblk_f, int stage,
+    int mode) {
+  extern __shared__ float2 lds_all[];
+  if (ctl->done) return;
+  yspec_l_body<T, NZ, LP>(P, spec, K, ctl, W, tw, logTw, partials, nblk_f,
+                          stage, mode, blockIdx.x, lds_all);
 }
 
 
