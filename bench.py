@@ -136,9 +136,11 @@ def bench_batched(torch, t_end, n_plain):
     b.close()
     idx = np.linspace(0, len(probs) - 1, n_plain).round().astype(int)
     wall_p, cs_p = 0.0, 0
+    kinds = []
     for k in idx:
         s = Sim(probs[k])
         s.set_state(torch.from_numpy(m0s[k]))
+        kinds.append(s.autotune(reps=5))       # untimed: best plain plan
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         _, info = s.run(t_end=t_end)
@@ -158,7 +160,9 @@ def bench_batched(torch, t_end, n_plain):
         "wall_s": wall, "setup_s": round(setup_s, 2),
         "plain": {"value": rate_p, "unit": "cell-steps/s",
                   "sample": (f"{len(idx)} evenly spaced instances solved one "
-                             "after another, standalone contexts"),
+                             "after another, standalone contexts with "
+                             "autotuned plans (tuning untimed)"),
+                  "plan_kinds": kinds,
                   "wall_s": wall_p},
         "speedup_vs_plain": rate_b / rate_p,
     }
@@ -172,6 +176,7 @@ def bench_wire(torch, nsteps):
     p, m0, _ = I.c2_nanowire()
     s = Sim(p)
     s.set_state(torch.from_numpy(m0))
+    kind = s.autotune(reps=10)                         # untimed
     s.run(nsteps=20, t_end=1.0)                        # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -184,7 +189,7 @@ def bench_wire(torch, nsteps):
                          "drive, Dormand-Prince tol 1e-6"),
             "value": p.ncells * info["accepted"] / w, "unit": "cell-steps/s",
             "accepted": info["accepted"], "rejected": info["rejected"],
-            "ms_per_step": 1e3 * w / info["accepted"]}
+            "ms_per_step": 1e3 * w / info["accepted"], "plan_kind": kind}
 
 
 def bench_adjoint(torch, nsteps):
@@ -303,6 +308,7 @@ def main():
     prob.brms = brms
     sim.set_params(prob)
     sim.set_state(m_relaxed, 0.0, 0j)
+    kind = sim.autotune(reps=10)       # plan kinds timed on this grid
     plan = sim.plan_info()
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
@@ -350,6 +356,7 @@ def main():
             "accepted": info["accepted"], "rejected": info["rejected"],
             "rhs_evals": info["rhs_evals"],
             "relax_steps": rinfo["accepted"], "setup_s": round(setup_s, 2),
+            "plan_kind": kind,
         },
     }
     if not args.no_timing:

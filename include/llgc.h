@@ -179,6 +179,25 @@ int llgc_eval_rhs(llgc_ctx *ctx, const float *m_dev, double a_re,
                   double a_im, double t, float *dmdt_dev, float *beff_dev,
                   double *dadt);
 
+/* Plan autotuner for the demag convolution of Eq. (llg)'s effective field
+ * (section "The LLG equation in Mumax3").  Each of the three FFT passes (y
+ * spectral pass, forward x pass, field x pass) can hold its transforms in
+ * registers (one wavefront per transform) or in LDS (Stockham passes); which
+ * is faster depends on the padded lengths, the layer count and how full the
+ * GPU is.  With `reps` > 0, times every feasible combination on this
+ * context's grid (two rounds of `reps` right-hand-side evaluations of the
+ * current state, result discarded), keeps the fastest and records it for
+ * the grid shape (nx, ny, nz, demag on/off) in a process-wide table; with
+ * `reps` <= 0, applies the recorded choice for this shape if there is one
+ * and otherwise keeps the current plan.  The integrator state is not
+ * changed; results of later calls differ from the untuned plan's only by
+ * float32 rounding.  `choice` (host, may be NULL) receives the plan kind:
+ * bit 0 register y pass, bit 1 register forward x pass, bit 2 register
+ * field x pass.  Not thread-safe against other calls on the same context.
+ * Errors: LLGC_E_ARG (NULL context, or a batch-plan instance, whose plan
+ * is fixed), LLGC_E_STATE (no params), LLGC_E_HIP. */
+int llgc_autotune(llgc_ctx *ctx, int32_t reps, int32_t *choice);
+
 /* Gradient of a cavity observable by the discrete adjoint of the RK4 path.
  * Runs `n_steps` RK4 steps of size `dt` from the current state (the state
  * advances), with the loss

@@ -10,6 +10,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -233,12 +235,26 @@ void yspec_nz(llgc_ctx* c, Ctl* ctl, dim3 g, int stage, int mode) {
   }
 }
 
+// Dynamic-LDS limit of a kernel: process-wide, so it only ever grows (a
+// later, smaller context must not shrink the limit an earlier one needs).
+void raise_lds_limit(const void* f, size_t bytes) {
+  static std::map<const void*, size_t> cur;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& v = cur[f];
+  if (bytes > v) {
+    hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)bytes);
+    v = bytes;
+  }
+}
+
 template <int T, int LP>
 void yspec_attr_lp(size_t lds) {
-  hipFuncSetAttribute((const void*)k_yspec<T, 1, LP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipFuncSetAttribute((const void*)k_yspec<T, 2, LP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipFuncSetAttribute((const void*)k_yspec<T, 3, LP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipFuncSetAttribute((const void*)k_yspec<T, 4, LP>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  raise_lds_limit((const void*)k_yspec<T, 1, LP>, lds);
+  raise_lds_limit((const void*)k_yspec<T, 2, LP>, lds);
+  raise_lds_limit((const void*)k_yspec<T, 3, LP>, lds);
+  raise_lds_limit((const void*)k_yspec<T, 4, LP>, lds);
 }
 
 template <int T>
@@ -658,6 +674,133 @@ int timers_collect(llgc_ctx* c) {
   return LLGC_OK;
 }
 
+// Quantities that follow from the FFT kinds in use_wy / use_wxf / use_wxi and
+// the rows and columns per workgroup: the ky-split choice, LDS sizes (checked
+// against the device) and the kernels' LDS limits.
+int plan_derive(llgc_ctx* c) {
+  const int col = 3 * c->nz * c->Py;
+  const int ycap = VPTY * kTyMax;       // complex values one workgroup holds
+  const int W = c->W;
+  // the ky-parity split of the LDS spectral pass: half the LDS per
+  // workgroup (two workgroups per CU) for long columns
+  {
+    const int hcol = W * 3 * c->nz * (c->Py / 2);
+    // 512 or 1024 threads, up to 12 elements each (the instances that
+    // compile without register spills: nz <= 3)
+    c->Tyh = hcol > kYhEpt * 512 ? 1024 : 512;
+    const char* s = getenv("LLGC_YHALF");
+    const bool fits = !c->use_wy && c->Py >= 4 &&
+                      hcol <= kYhEpt * c->Tyh && hcol <= VPTY * c->Tyh;
+    // used where a whole column set exceeds one workgroup (nz = 3, 4 at
+    // 2048 points); elsewhere the unsplit pass measured faster
+    c->yhalf = !c->batch_plan && fits &&
+               ((W * col > ycap) || (c->nz <= 3 && s && atoi(s)));
+    c->lds_yh = sizeof(float2) * (lds_twiddles(c->logTw) +
+                                  padded_len((size_t)hcol));
+  }
+  if (!c->use_wy && !c->yhalf && W * col > ycap)
+    return fail(c, LLGC_E_UNSUPPORTED, "column set exceeds one workgroup");
+  const size_t twb = sizeof(float2) * lds_twiddles(c->logTw);  // LDS twiddles
+  c->lds_f = twb + sizeof(float2) * padded_len((size_t)(c->Rf / 2) * c->Px);
+  c->lds_i = sizeof(float2) * padded_len_s<6>((size_t)3 * (c->Ri / 2) * c->Px);
+  c->lds_y = twb + sizeof(float2) * padded_len((size_t)W * col);
+  int dev = 0, maxlds = 65536;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                        dev);
+  // LDS of the kernels this plan launches
+  const size_t need_y = c->use_wy ? 0 : (c->yhalf ? c->lds_yh : c->lds_y);
+  size_t need = std::max(c->use_wxf ? 0 : c->lds_f,
+                         std::max(c->use_wxi ? 0 : c->lds_i, need_y));
+  if (need > (size_t)std::max(maxlds, 65536) && need > 65536)
+    return fail(c, LLGC_E_UNSUPPORTED,
+                "plan needs more LDS than the device offers");
+  {
+    const void* xf[] = {
+        (const void*)k_xfwd<kTX, true, 0>, (const void*)k_xfwd<kTX, true, 10>,
+        (const void*)k_xfwd<kTX, true, 11>, (const void*)k_xfwd<kTX, false, 0>,
+        (const void*)k_xfwd<kTX, false, 10>,
+        (const void*)k_xfwd<kTX, false, 11>};
+    for (const void* f : xf)
+      raise_lds_limit(f, c->lds_f);
+    const void* xi[] = {
+        (const void*)k_xfield<kTX, 0>, (const void*)k_xfield<kTX, 8>,
+        (const void*)k_xfield<kTX, 9>, (const void*)k_xfield<kTX, 10>,
+        (const void*)k_xfield<kTX, 11>};
+    for (const void* f : xi)
+      raise_lds_limit(f, c->lds_i);
+  }
+  if (c->yhalf) {
+    const void* fs[] = {
+        (const void*)k_yspec_h<512, 1, kYhEpt>, (const void*)k_yspec_h<512, 2, kYhEpt>,
+        (const void*)k_yspec_h<512, 3, kYhEpt>, (const void*)k_yspec_h<1024, 1, kYhEpt>,
+        (const void*)k_yspec_h<1024, 2, kYhEpt>, (const void*)k_yspec_h<1024, 3, kYhEpt>,
+        (const void*)k_yspec_h<1024, 4, kYhEpt>};
+    for (const void* f : fs)
+      raise_lds_limit(f, c->lds_yh);
+  }
+  if (!c->use_wy && !c->yhalf) {
+    yspec_attr<256>(c->lds_y);
+    yspec_attr<512>(c->lds_y);
+    if constexpr (kTyMax >= 1024) yspec_attr<1024>(c->lds_y);
+  }
+  return LLGC_OK;
+}
+
+// ---------------------------------------------------------------- autotune
+// A plan kind says which passes keep their FFT in registers: bit 0 the
+// spectral (y) pass, bit 1 the forward x pass, bit 2 the field x pass; rows
+// and columns per workgroup follow each kind as in the default plan.
+bool plan_kind_ok(const llgc_ctx* c, int k) {
+  if ((k & 1) && !(c->Py >= 64 && c->Py <= 2048 &&
+                   (c->Py < 2048 || c->nz <= 2)))
+    return false;
+  if ((k & 6) && !(c->Px >= 64 && c->Px <= 2048)) return false;
+  return true;
+}
+int plan_kind(const llgc_ctx* c) {
+  return (c->use_wy ? 1 : 0) | (c->use_wxf ? 2 : 0) | (c->use_wxi ? 4 : 0);
+}
+void plan_set_kind(llgc_ctx* c, int k) {
+  c->use_wy = (k & 1) != 0;
+  c->use_wxf = (k & 2) != 0;
+  c->use_wxi = (k & 4) != 0;
+}
+
+// Mean milliseconds of one right-hand-side evaluation (forward x pass,
+// spectral pass, field pass) under the current plan, over `reps`
+// evaluations of the current state into a scratch k register.
+int time_rhs(llgc_ctx* c, int reps, double* ms) {
+  Ctl h{};
+  h.t_end = 1e300;
+  if (int r = ctl_write(c, c->ctl_eval, &h)) return r;
+  const Epi E = epi_eval(c->kb[1], nullptr);
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return fail(c, LLGC_E_HIP, "hipEventCreate failed");
+  }
+  int r = rhs_stage(c, c->yn, c->ctl_eval, 1, E, 1);   // untimed first call
+  if (!r && hipEventRecord(e0, c->stream) != hipSuccess)
+    r = fail(c, LLGC_E_HIP, "hipEventRecord failed");
+  for (int i = 0; i < reps && !r; ++i)
+    r = rhs_stage(c, c->yn, c->ctl_eval, 1, E, 1);
+  float t = 0.f;
+  if (!r && (hipEventRecord(e1, c->stream) != hipSuccess ||
+             hipEventSynchronize(e1) != hipSuccess ||
+             hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+    r = fail(c, LLGC_E_HIP, "timing events failed");
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *ms = (double)t / std::max(1, reps);
+  return r;
+}
+
+// Tuned plan kinds per grid shape (process-wide).
+std::map<std::tuple<int, int, int, int>, int> g_tuned;
+std::mutex g_tuned_mu;
+
 }  // namespace
 
 // ================================================================== C ABI
@@ -758,75 +901,9 @@ int llgc_create_ex(const llgc_grid* g, void* stream, int flags,
     W = std::max(1, std::min(VPTY * kBatchTy / col, c->Px / 2));
     c->W = W;
   }
-  // the ky-parity split of the LDS spectral pass: half the LDS per
-  // workgroup (two workgroups per CU) for long columns
-  {
-    const int hcol = W * 3 * c->nz * (c->Py / 2);
-    // 512 or 1024 threads, up to 12 elements each (the instances that
-    // compile without register spills: nz <= 3)
-    c->Tyh = hcol > kYhEpt * 512 ? 1024 : 512;
-    const char* s = getenv("LLGC_YHALF");
-    const bool fits = !c->use_wy && c->Py >= 4 &&
-                      hcol <= kYhEpt * c->Tyh && hcol <= VPTY * c->Tyh;
-    // used where a whole column set exceeds one workgroup (nz = 3, 4 at
-    // 2048 points); elsewhere the unsplit pass measured faster
-    c->yhalf = !bplan && fits &&
-               ((W * col > ycap) || (c->nz <= 3 && s && atoi(s)));
-    c->lds_yh = sizeof(float2) * (lds_twiddles(c->logTw) +
-                                  padded_len((size_t)hcol));
-  }
-  if (!c->use_wy && !c->yhalf && W * col > ycap) {
+  if (int r = plan_derive(c)) {
     delete c;
-    return LLGC_E_UNSUPPORTED;
-  }
-  const size_t twb = sizeof(float2) * lds_twiddles(c->logTw);  // LDS twiddles
-  c->lds_f = twb + sizeof(float2) * padded_len((size_t)(c->Rf / 2) * c->Px);
-  c->lds_i = sizeof(float2) * padded_len_s<6>((size_t)3 * (c->Ri / 2) * c->Px);
-  c->lds_y = twb + sizeof(float2) * padded_len((size_t)W * col);
-  int dev = 0, maxlds = 65536;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock,
-                        dev);
-  // LDS of the kernels this plan launches
-  const size_t need_y = c->use_wy ? 0 : (c->yhalf ? c->lds_yh : c->lds_y);
-  size_t need = std::max(c->use_wxf ? 0 : c->lds_f,
-                         std::max(c->use_wxi ? 0 : c->lds_i, need_y));
-  if (need > (size_t)std::max(maxlds, 65536) && need > 65536) {
-    c->err = "plan needs more LDS than the device offers";
-    delete c;
-    return LLGC_E_UNSUPPORTED;
-  }
-  {
-    const void* xf[] = {
-        (const void*)k_xfwd<kTX, true, 0>, (const void*)k_xfwd<kTX, true, 10>,
-        (const void*)k_xfwd<kTX, true, 11>, (const void*)k_xfwd<kTX, false, 0>,
-        (const void*)k_xfwd<kTX, false, 10>,
-        (const void*)k_xfwd<kTX, false, 11>};
-    for (const void* f : xf)
-      hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)c->lds_f);
-    const void* xi[] = {
-        (const void*)k_xfield<kTX, 0>, (const void*)k_xfield<kTX, 8>,
-        (const void*)k_xfield<kTX, 9>, (const void*)k_xfield<kTX, 10>,
-        (const void*)k_xfield<kTX, 11>};
-    for (const void* f : xi)
-      hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)c->lds_i);
-  }
-  if (c->yhalf) {
-    const void* fs[] = {
-        (const void*)k_yspec_h<512, 1, kYhEpt>, (const void*)k_yspec_h<512, 2, kYhEpt>,
-        (const void*)k_yspec_h<512, 3, kYhEpt>, (const void*)k_yspec_h<1024, 1, kYhEpt>,
-        (const void*)k_yspec_h<1024, 2, kYhEpt>, (const void*)k_yspec_h<1024, 3, kYhEpt>,
-        (const void*)k_yspec_h<1024, 4, kYhEpt>};
-    for (const void* f : fs)
-      hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)c->lds_yh);
-  }
-  if (!c->use_wy && !c->yhalf) {
-    yspec_attr<256>(c->lds_y);
-    yspec_attr<512>(c->lds_y);
-    if constexpr (kTyMax >= 1024) yspec_attr<1024>(c->lds_y);
+    return r;
   }
   // --- buffers
   const size_t n3 = (size_t)3 * c->N;
@@ -1205,6 +1282,61 @@ int llgc_eval_rhs(llgc_ctx* c, const float* m, double are, double aim,
     dadt[0] = e.rhs_dadt_re;
     dadt[1] = e.rhs_dadt_im;
   }
+  return LLGC_OK;
+}
+
+int llgc_autotune(llgc_ctx* c, int32_t reps, int32_t* choice) {
+  if (!c) return LLGC_E_ARG;
+  if (c->batch_plan)
+    return fail(c, LLGC_E_ARG, "batch-plan contexts keep their fixed plan");
+  if (!c->have_params)
+    return fail(c, LLGC_E_STATE, "set params before tuning");
+  const auto key = std::make_tuple(c->nx, c->ny, c->nz, c->P.demag ? 1 : 0);
+  const int k0 = plan_kind(c);
+  int best = k0;
+  const bool timing = c->timing;
+  c->timing = false;                     // keep tuning out of the timers
+  struct Restore {
+    llgc_ctx* c;
+    bool t;
+    ~Restore() { c->timing = t; }
+  } restore{c, timing};
+  if (reps <= 0) {
+    std::lock_guard<std::mutex> lock(g_tuned_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) best = it->second;
+  } else {
+    // two rounds over the candidate kinds (the first also brings the clocks
+    // up); each kind keeps its faster round
+    double tbest[8];
+    for (double& v : tbest) v = 1e300;
+    for (int round = 0; round < 2; ++round) {
+      for (int k = 0; k < 8; ++k) {
+        if (!plan_kind_ok(c, k)) continue;
+        plan_set_kind(c, k);
+        if (plan_derive(c)) continue;             // does not fit this grid
+        double ms = 0.0;
+        if (int r = time_rhs(c, reps, &ms)) {
+          plan_set_kind(c, k0);
+          plan_derive(c);
+          return r;
+        }
+        tbest[k] = std::min(tbest[k], ms);
+      }
+    }
+    for (int k = 0; k < 8; ++k)
+      if (tbest[k] < tbest[best]) best = k;
+    std::lock_guard<std::mutex> lock(g_tuned_mu);
+    g_tuned[key] = best;
+  }
+  plan_set_kind(c, best);
+  if (int r = plan_derive(c)) {
+    plan_set_kind(c, k0);
+    plan_derive(c);
+    return r;
+  }
+  if (choice) *choice = best;
+  c->err.clear();
   return LLGC_OK;
 }
 

@@ -149,9 +149,7 @@ int llgc_batch_create(const llgc_grid* grids, int32_t n, void* stream,
     b->lds_f = std::max(b->lds_f, sizeof(float) * 3 * kBatchRows * c->nx);
     b->lds_y = std::max(b->lds_y, c->lds_y);
   }
-  hipFuncSetAttribute((const void*)kb_yspec,
-                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)b->lds_y);
+  raise_lds_limit((const void*)kb_yspec, b->lds_y);
   b->cap_x = cx;
   b->cap_y = cy;
   b->cap_b = cb;

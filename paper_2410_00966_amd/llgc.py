@@ -28,7 +28,8 @@ EXPORTED = ("llgc_create", "llgc_destroy", "llgc_last_error",
             "llgc_demag_tensor", "llgc_set_timing", "llgc_kernel_times",
             "llgc_plan_info", "llgc_create_ex", "llgc_batch_create",
             "llgc_batch_destroy", "llgc_batch_last_error",
-            "llgc_batch_instance", "llgc_batch_run", "llgc_set_timing_only")
+            "llgc_batch_instance", "llgc_batch_run", "llgc_set_timing_only",
+            "llgc_autotune")
 PLAN_BATCH = 1
 
 
@@ -122,6 +123,7 @@ def load():
         "llgc_batch_run": ([vp, i64, dbl, i32, P(dbl), i64, P(i64),
                             P(RunInfo), P(i32)], ctypes.c_int),
         "llgc_set_timing_only": ([vp, ctypes.c_char_p], ctypes.c_int),
+        "llgc_autotune": ([vp, i32, P(i32)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -318,6 +320,16 @@ class Sim:
             self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n),
             "llgc_demag_tensor")
         return out.reshape(6, self.prob.nz, self.prob.ny, self.prob.nx)
+
+    def autotune(self, reps=20):
+        """Times the register/LDS FFT plan kinds on this grid and keeps the
+        fastest (reps <= 0: reuse the kind recorded for this grid shape).
+        Returns the kind: bit 0 register y pass, bit 1 register forward x
+        pass, bit 2 register field x pass."""
+        k = ctypes.c_int32(-1)
+        self._check(self.L.llgc_autotune(self.h, int(reps), ctypes.byref(k)),
+                    "llgc_autotune")
+        return k.value
 
     def set_timing(self, on=True, only=None):
         """Per-kernel HIP-event timing; `only` restricts it to one kernel."""

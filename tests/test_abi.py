@@ -110,3 +110,10 @@ def test_batch_and_plan_entry_points_reject_bad_arguments():
     assert L.llgc_batch_last_error(None) == b"null batch"
     assert L.llgc_batch_instance(None, 0) is None
     assert L.llgc_batch_run(None, 0, 0.0, 0, None, 0, None, None, None) == -1
+
+
+def test_autotune_rejects_null_context():
+    llgc, L = _lib()
+    k = ctypes.c_int32(-1)
+    assert L.llgc_autotune(None, 5, ctypes.byref(k)) == -1
+    assert k.value == -1
