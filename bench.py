@@ -141,6 +141,8 @@ def bench_batched(torch, t_end, n_plain):
         s = Sim(probs[k])
         s.set_state(torch.from_numpy(m0s[k]))
         kinds.append(s.autotune(reps=5))       # untimed: best plain plan
+        s.run(nsteps=1, t_end=t_end)           # untimed: graph capture
+        s.set_state(torch.from_numpy(m0s[k]))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         _, info = s.run(t_end=t_end)
@@ -161,7 +163,8 @@ def bench_batched(torch, t_end, n_plain):
         "plain": {"value": rate_p, "unit": "cell-steps/s",
                   "sample": (f"{len(idx)} evenly spaced instances solved one "
                              "after another, standalone contexts with "
-                             "autotuned plans (tuning untimed)"),
+                             "autotuned plans (tuning and graph capture "
+                             "untimed)"),
                   "plan_kinds": kinds,
                   "wall_s": wall_p},
         "speedup_vs_plain": rate_b / rate_p,

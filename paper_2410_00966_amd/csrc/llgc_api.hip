@@ -92,6 +92,14 @@ struct llgc_ctx {
   std::string timing_only;            // time only this kernel ("" = all)
   std::vector<hipEvent_t> event_pool; // reusable timing events
   std::map<std::string, TimerRec> timers;
+  // HIP graphs of the integrator's launch sequences (index 0: a chunk of
+  // Dormand-Prince attempts, 1: one RK4 step), with the launch arguments
+  // they were captured with
+  bool graphs = true;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
+  std::vector<unsigned char> graph_sig[2];
 };
 
 namespace {
@@ -801,6 +809,100 @@ int time_rhs(llgc_ctx* c, int reps, double* ms) {
 std::map<std::tuple<int, int, int, int>, int> g_tuned;
 std::mutex g_tuned_mu;
 
+// ------------------------------------------------------- launch sequences
+constexpr int kDpChunk = 8;   // Dormand-Prince attempts per host check
+
+// The launches of one chunk, issued on c->stream: kind 0 = kDpChunk
+// Dormand-Prince attempts (stages 2..7, then the next attempt's start),
+// kind 1 = one RK4 step (stages 1..4).
+int chunk_direct(llgc_ctx* c, int kind) {
+  int r = LLGC_OK;
+  if (kind == 1) {
+    for (int s = 1; s <= 4 && !r; ++s) {
+      const float* ys = (s == 1) ? c->yn : c->yb[(s + 1) % 2];
+      r = rhs_stage(c, ys, c->ctl, s, epi_rk4(c, s), 0);
+    }
+    return r;
+  }
+  for (int b = 0; b < kDpChunk && !r; ++b) {
+    for (int s = 2; s <= 7 && !r; ++s)
+      r = rhs_stage(c, c->yb[s % 2], c->ctl, s, epi_dp(c, s), 0);
+    if (!r) r = launch_begin(c);
+  }
+  return r;
+}
+
+// Everything a captured chunk depends on besides device memory contents:
+// the parameters passed by value, the plan and the record buffer.
+std::vector<unsigned char> chunk_signature(const llgc_ctx* c) {
+  std::vector<unsigned char> v;
+  auto put = [&v](const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    v.insert(v.end(), b, b + n);
+  };
+  put(&c->P, sizeof(Prm));
+  const int plan[] = {c->use_wy, c->use_wxf, c->use_wxi, c->yhalf, c->Rf,
+                      c->Ri, c->W, c->Ty, c->Ww, c->Rw, c->Rwf, c->Tyh};
+  put(plan, sizeof(plan));
+  put(&c->rec, sizeof(c->rec));
+  put(&c->ms_map, sizeof(c->ms_map));
+  put(&c->ku_map, sizeof(c->ku_map));
+  return v;
+}
+
+void graph_release(llgc_ctx* c, int kind) {
+  if (c->graph_exec[kind]) hipGraphExecDestroy(c->graph_exec[kind]);
+  if (c->graph[kind]) hipGraphDestroy(c->graph[kind]);
+  c->graph_exec[kind] = nullptr;
+  c->graph[kind] = nullptr;
+  c->graph_sig[kind].clear();
+}
+
+// One chunk, replayed from a HIP graph captured on a private stream (only
+// kernel nodes: no copies or memsets inside); re-captured when the
+// signature changes.  Timed runs launch directly (events stay outside
+// graphs).
+int run_chunk(llgc_ctx* c, int kind) {
+  if (!c->graphs || c->timing) return chunk_direct(c, kind);
+  std::vector<unsigned char> sig = chunk_signature(c);
+  if (!c->graph_exec[kind] || sig != c->graph_sig[kind]) {
+    graph_release(c, kind);
+    if (!c->cap_stream)
+      HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream,
+                                         hipStreamNonBlocking));
+    // capture records the launches without running them; the graph then
+    // runs on the caller's stream, after the work already queued there
+    hipStream_t user = c->stream;
+    c->stream = c->cap_stream;
+    int r = LLGC_OK;
+    if (hipStreamBeginCapture(c->cap_stream,
+                              hipStreamCaptureModeThreadLocal) != hipSuccess)
+      r = fail(c, LLGC_E_HIP, "hipStreamBeginCapture failed");
+    else
+      r = chunk_direct(c, kind);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    c->stream = user;
+    if (!r && e != hipSuccess)
+      r = fail(c, LLGC_E_HIP, "hipStreamEndCapture: %s",
+               hipGetErrorString(e));
+    if (!r && hipGraphInstantiate(&c->graph_exec[kind], g, nullptr,
+                                  nullptr, 0) != hipSuccess) {
+      c->graph_exec[kind] = nullptr;
+      r = fail(c, LLGC_E_HIP, "hipGraphInstantiate failed");
+    }
+    if (r) {
+      if (g) hipGraphDestroy(g);
+      (void)hipGetLastError();
+      return r;
+    }
+    c->graph[kind] = g;
+    c->graph_sig[kind] = std::move(sig);
+  }
+  HIPCHK(c, hipGraphLaunch(c->graph_exec[kind], c->stream));
+  return LLGC_OK;
+}
+
 }  // namespace
 
 // ================================================================== C ABI
@@ -829,6 +931,7 @@ int llgc_create_ex(const llgc_grid* g, void* stream, int flags,
   c->dx = g->dx; c->dy = g->dy; c->dz = g->dz;
   c->stream = (hipStream_t)stream;
   c->batch_plan = bplan;
+  c->graphs = getenv("LLGC_NO_GRAPHS") == nullptr;
   c->Px = g->nx == 1 ? 1 : pow2_ceil(2 * g->nx);
   c->Py = g->ny == 1 ? 1 : pow2_ceil(2 * g->ny);
   if (bplan) {
@@ -961,6 +1064,9 @@ int llgc_destroy(llgc_ctx* c) {
   else hipDeviceSynchronize();
   timers_collect(c);
   for (hipEvent_t e : c->event_pool) hipEventDestroy(e);
+  graph_release(c, 0);
+  graph_release(c, 1);
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   hipFree(c->yn);
   hipFree(c->yb[0]);
   hipFree(c->yb[1]);
@@ -1220,24 +1326,13 @@ int llgc_run(llgc_ctx* c, int64_t nsteps, double t_end, int32_t rec_every,
     return r;
   int r = LLGC_OK;
   if (rp.rk4) {
-    for (int64_t n = 0; n < rp.nsteps && !r; ++n) {
-      for (int s = 1; s <= 4 && !r; ++s) {
-        const float* ys = (s == 1) ? c->yn : c->yb[(s + 1) % 2];
-        r = rhs_stage(c, ys, c->ctl, s, epi_rk4(c, s), 0);
-      }
-    }
+    for (int64_t n = 0; n < rp.nsteps && !r; ++n) r = run_chunk(c, 1);
   } else if (!rp.done) {
     const int64_t max_attempts = 50000000;
     int64_t attempts = 0;
     while (!r) {
-      const int batch = 8;
-      for (int b = 0; b < batch && !r; ++b) {
-        for (int s = 2; s <= 7 && !r; ++s) {
-          r = rhs_stage(c, c->yb[s % 2], c->ctl, s, epi_dp(c, s), 0);
-        }
-        if (!r) r = launch_begin(c);
-        attempts++;
-      }
+      r = run_chunk(c, 0);
+      attempts += kDpChunk;
       if (r) break;
       int done = 0;
       HIPCHK(c, hipMemcpyAsync(&done, &c->ctl->done, sizeof(int),

@@ -16,6 +16,11 @@ struct llgc_batch {
   size_t cap_x = 0, cap_y = 0, cap_b = 0;   // work-table capacities
   size_t lds_x = 0, lds_f = 0, lds_y = 0;
   std::string err;
+  // HIP graph of one round of attempts over the current work tables
+  bool graphs = true;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
 };
 
 namespace {
@@ -42,6 +47,13 @@ int b_tiles(const llgc_ctx* c) { return (int)xgrid(c, kBatchRows).x; }
 // spectral workgroups: column slots (kx = 0 and Px/2 share slot 0) per W
 int b_yblocks(const llgc_ctx* c) {
   return c->P.demag ? (c->Px / 2 + c->W - 1) / c->W : 1;
+}
+
+void bgraph_release(llgc_batch* b) {
+  if (b->gexec) hipGraphExecDestroy(b->gexec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
 }
 
 BInst make_binst(llgc_ctx* c, bool rk4) {
@@ -93,6 +105,7 @@ int batch_tables(llgc_batch* b, const std::vector<char>& active) {
   b->n_y = (int)iy.size();
   b->n_b = (int)ib.size();
   b->n_act = (int)act.size();
+  bgraph_release(b);                 // launch sizes change with the tables
   if (b->n_act == 0) return LLGC_OK;
   if (ix.size() > b->cap_x || iy.size() > b->cap_y || ib.size() > b->cap_b)
     return bfail(b, LLGC_E_STATE, "work tables exceed their allocation");
@@ -122,6 +135,74 @@ int batch_stage(llgc_batch* b, int stage) {
   return LLGC_OK;
 }
 
+constexpr int kBatchRound = 8;   // attempts per host check
+
+// One round of attempts for every active instance, issued on b->stream.
+int batch_round_direct(llgc_batch* b, bool rk4) {
+  int r = LLGC_OK;
+  for (int q = 0; q < kBatchRound && !r; ++q) {
+    if (rk4) {
+      for (int s = 1; s <= 4 && !r; ++s) r = batch_stage(b, s);
+      if (!r)
+        hipLaunchKernelGGL(kb_finish_step, dim3(b->n_act), dim3(256), 0,
+                           b->stream, b->dI, b->act, 2, b->flags);
+    } else {
+      for (int s = 2; s <= 7 && !r; ++s) r = batch_stage(b, s);
+      if (!r) {
+        hipLaunchKernelGGL(kb_finish_step, dim3(b->n_act), dim3(256), 0,
+                           b->stream, b->dI, b->act, 3, b->flags);
+        hipLaunchKernelGGL(kb_begin, dim3(b->n_b), dim3(kBPT), 0,
+                           b->stream, b->dI, b->it_b);
+      }
+    }
+  }
+  if (!r) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+      r = bfail(b, LLGC_E_HIP, "batched launch failed: %s",
+                hipGetErrorString(e));
+  }
+  return r;
+}
+
+// The round replayed from a HIP graph (kernel nodes only), captured once per
+// set of work tables on a private stream and launched on b->stream.
+int batch_round(llgc_batch* b, bool rk4) {
+  if (!b->graphs) return batch_round_direct(b, rk4);
+  if (!b->gexec) {
+    if (!b->cap_stream)
+      BHIPCHK(b, hipStreamCreateWithFlags(&b->cap_stream,
+                                          hipStreamNonBlocking));
+    hipStream_t user = b->stream;
+    b->stream = b->cap_stream;
+    int r = LLGC_OK;
+    if (hipStreamBeginCapture(b->cap_stream,
+                              hipStreamCaptureModeThreadLocal) != hipSuccess)
+      r = bfail(b, LLGC_E_HIP, "hipStreamBeginCapture failed");
+    else
+      r = batch_round_direct(b, rk4);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+    b->stream = user;
+    if (!r && e != hipSuccess)
+      r = bfail(b, LLGC_E_HIP, "hipStreamEndCapture: %s",
+                hipGetErrorString(e));
+    if (!r && hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0) !=
+                  hipSuccess) {
+      b->gexec = nullptr;
+      r = bfail(b, LLGC_E_HIP, "hipGraphInstantiate failed");
+    }
+    if (r) {
+      if (g) hipGraphDestroy(g);
+      (void)hipGetLastError();
+      return r;
+    }
+    b->graph = g;
+  }
+  BHIPCHK(b, hipGraphLaunch(b->gexec, b->stream));
+  return LLGC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -133,6 +214,7 @@ int llgc_batch_create(const llgc_grid* grids, int32_t n, void* stream,
   llgc_batch* b = new llgc_batch();
   b->n = n;
   b->stream = (hipStream_t)stream;
+  b->graphs = getenv("LLGC_NO_GRAPHS") == nullptr;
   b->inst.assign(n, nullptr);
   size_t cx = 0, cy = 0, cb = 0;
   for (int k = 0; k < n; ++k) {
@@ -169,6 +251,8 @@ int llgc_batch_create(const llgc_grid* grids, int32_t n, void* stream,
 
 int llgc_batch_destroy(llgc_batch* b) {
   if (!b) return LLGC_OK;
+  bgraph_release(b);
+  if (b->cap_stream) hipStreamDestroy(b->cap_stream);
   for (auto* c : b->inst) llgc_destroy(c);
   hipFree(b->dI);
   hipFree(b->it_x);
@@ -229,26 +313,12 @@ int llgc_batch_run(llgc_batch* b, int64_t nsteps, double t_end,
   if (int r = batch_tables(b, active)) return r;
   int r = LLGC_OK;
   int ndone = ndone0, ndone_tables = ndone0;
-  const int64_t max_rounds = 50000000 / 8;
+  const int64_t max_rounds = 50000000 / kBatchRound;
+  // a graph from an earlier run may hold the other method's launches
+  bgraph_release(b);
   for (int64_t round = 0; ndone < n && !r; ++round) {
-    for (int q = 0; q < 8 && !r; ++q) {
-      if (rk4) {
-        for (int s = 1; s <= 4 && !r; ++s) r = batch_stage(b, s);
-        if (!r)
-          hipLaunchKernelGGL(kb_finish_step, dim3(b->n_act), dim3(256), 0,
-                             b->stream, b->dI, b->act, 2, b->flags);
-      } else {
-        for (int s = 2; s <= 7 && !r; ++s) r = batch_stage(b, s);
-        if (!r) {
-          hipLaunchKernelGGL(kb_finish_step, dim3(b->n_act), dim3(256), 0,
-                             b->stream, b->dI, b->act, 3, b->flags);
-          hipLaunchKernelGGL(kb_begin, dim3(b->n_b), dim3(kBPT), 0,
-                             b->stream, b->dI, b->it_b);
-        }
-      }
-    }
+    r = batch_round(b, rk4);
     if (r) break;
-    BHIPCHK(b, hipGetLastError());
     BHIPCHK(b, hipMemcpyAsync(&ndone, b->flags, sizeof(int),
                               hipMemcpyDeviceToHost, b->stream));
     BHIPCHK(b, hipStreamSynchronize(b->stream));
