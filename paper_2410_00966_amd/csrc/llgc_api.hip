@@ -39,7 +39,6 @@ constexpr int kYhEpt = 12;            // split y pass: elements per thread
 constexpr int kMaxLen = 2048;         // largest padded FFT length per axis
 constexpr size_t kLdsCap = 120 * 1024; // LDS per workgroup this plan uses
 constexpr int kBatchMaxLen = 256;     // batched plan: padded length per axis
-constexpr int kBatchRows = 4;         // batched plan: rows per x-pass tile
 constexpr int kBatchTy = kBYT;        // batched plan: spectral workgroup threads
 
 struct TimerRec {
@@ -197,6 +196,12 @@ int launch_xfwd(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
     }
 #undef LLGC_FW_ARGS
     return check_launch(c, "k_xfwd_w");
+  }
+  if (c->batch_plan) {
+    hipLaunchKernelGGL((k_xfwd3<kTX>), xgrid(c, c->Rf), dim3(kTX),
+                       c->P.demag ? c->lds_f : 0, c->stream, c->P, ys,
+                       c->spec, ctl, c->partials, c->Rf, c->tw, c->logTw);
+    return check_launch(c, "k_xfwd3");
   }
   const bool v4 = (c->nx % 4 == 0) && aligned16(ys) &&
                   (!c->ms_map || aligned16(c->ms_map));
@@ -364,6 +369,13 @@ int launch_xfield(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
     }
 #undef LLGC_XW_ARGS
     return check_launch(c, "k_xfield_w");
+  }
+  if (c->batch_plan) {
+    hipLaunchKernelGGL((k_xfield_b<kTX>), xgrid(c, c->Ri), dim3(kTX),
+                       c->P.demag ? c->lds_i : 0, c->stream, c->P, ys,
+                       c->spec, ctl, c->partials, c->rec, stage, c->Ri, E,
+                       c->tw, c->logTw);
+    return check_launch(c, "k_xfield_b");
   }
 #define LLGC_XI(LP)                                                         \
   hipLaunchKernelGGL((k_xfield<kTX, LP>), xgrid(c, c->Ri), dim3(kTX),        \
@@ -709,7 +721,8 @@ int plan_derive(llgc_ctx* c) {
   if (!c->use_wy && !c->yhalf && W * col > ycap)
     return fail(c, LLGC_E_UNSUPPORTED, "column set exceeds one workgroup");
   const size_t twb = sizeof(float2) * lds_twiddles(c->logTw);  // LDS twiddles
-  c->lds_f = twb + sizeof(float2) * padded_len((size_t)(c->Rf / 2) * c->Px);
+  c->lds_f = twb + sizeof(float2) * padded_len((size_t)(c->batch_plan ? 3 : 1) *
+                                                (c->Rf / 2) * c->Px);
   c->lds_i = sizeof(float2) * padded_len_s<6>((size_t)3 * (c->Ri / 2) * c->Px);
   c->lds_y = twb + sizeof(float2) * padded_len((size_t)W * col);
   int dev = 0, maxlds = 65536;
@@ -737,6 +750,8 @@ int plan_derive(llgc_ctx* c) {
         (const void*)k_xfield<kTX, 11>};
     for (const void* f : xi)
       raise_lds_limit(f, c->lds_i);
+    raise_lds_limit((const void*)k_xfwd3<kTX>, c->lds_f);
+    raise_lds_limit((const void*)k_xfield_b<kTX>, c->lds_i);
   }
   if (c->yhalf) {
     const void* fs[] = {
@@ -935,7 +950,8 @@ int llgc_create_ex(const llgc_grid* g, void* stream, int flags,
   c->Px = g->nx == 1 ? 1 : pow2_ceil(2 * g->nx);
   c->Py = g->ny == 1 ? 1 : pow2_ceil(2 * g->ny);
   if (bplan) {
-    // the batched kernels hold every transform in registers: >= 64 points
+    // batch plan: padded lengths of at least 64 (one plan family for the
+    // 16..128-cell instances of a sweep)
     c->Px = std::max(c->Px, 64);
     c->Py = std::max(c->Py, 64);
   }
@@ -997,9 +1013,13 @@ int llgc_create_ex(const llgc_grid* g, void* stream, int flags,
     // and as many column slots per workgroup as its VPTY * kBatchTy
     // elements hold (measured 1.3-2x faster per element than the register
     // spectral pass at 64..256 points once the GPU is full)
-    c->use_wxf = c->use_wxi = true;
-    c->use_wy = false;
-    c->Rw = c->Rwf = kBatchRows;
+    c->use_wxf = c->use_wxi = c->use_wy = false;
+    // x passes: the 3 (R/2) transforms of a tile fill one kTX-thread
+    // workgroup (VPT values each); tiles split ny evenly
+    const int npmax = std::max(1, VPT * kTX / (3 * c->Px));
+    const int pairs = (c->ny + 1) / 2;
+    const int nty = (pairs + npmax - 1) / npmax;
+    c->Rf = c->Ri = 2 * ((pairs + nty - 1) / nty);
     c->Ty = kBatchTy;
     W = std::max(1, std::min(VPTY * kBatchTy / col, c->Px / 2));
     c->W = W;

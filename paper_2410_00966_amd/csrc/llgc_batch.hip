@@ -9,7 +9,7 @@
 
 namespace llgc {
 
-constexpr int kBXT = 384;   // x pass / field: 6 wavefronts (4-row tiles)
+constexpr int kBXT = 512;   // x pass / field: LDS FFT of 3 (R/2) rows
 constexpr int kBYT = 512;   // spectral pass: 8 wavefronts (LDS FFT)
 constexpr int kBPT = 256;   // pointwise (k_begin) threads
 
@@ -19,7 +19,7 @@ struct BInst {
   Ctl* ctl;
   const float2* tw;
   int logTw;
-  int nrx;              // Px / 64 (1, 2 or 4)
+  int R;                // rows per x-pass / field tile
   int W;                // column slots per spectral workgroup
   int nf;               // x-pass / field tiles
   int nbeg;             // k_begin workgroups
@@ -45,12 +45,8 @@ __global__ __launch_bounds__(kBXT) void kb_xfwd(const BInst* __restrict__ I,
   const int2 w = bitem(it);
   const BInst& B = I[w.x];
   if (B.ctl->done) return;
-  const float* ys = B.ys[stage];
-  switch (B.nrx) {
-    case 1: xfwd_w_body<1>(B.P, ys, B.spec, B.partials, 4, B.tw, B.logTw, w.y, w.y, zl); break;
-    case 2: xfwd_w_body<2>(B.P, ys, B.spec, B.partials, 4, B.tw, B.logTw, w.y, w.y, zl); break;
-    default: xfwd_w_body<4>(B.P, ys, B.spec, B.partials, 4, B.tw, B.logTw, w.y, w.y, zl); break;
-  }
+  xfwd3_body<kBXT>(B.P, B.ys[stage], B.spec, B.partials, B.R, B.tw, B.logTw,
+                   w.y, w.y, zl);
 }
 
 __global__ __launch_bounds__(kBYT, 4) void kb_yspec(const BInst* __restrict__ I,
@@ -80,17 +76,12 @@ __global__ __launch_bounds__(kBYT, 4) void kb_yspec(const BInst* __restrict__ I,
 __global__ __launch_bounds__(kBXT) void kb_xfield(const BInst* __restrict__ I,
                                                   const int2* __restrict__ it,
                                                   int stage) {
-  extern __shared__ float bdl[];
+  extern __shared__ float2 lds[];
   const int2 w = bitem(it);
   const BInst& B = I[w.x];
   if (B.ctl->done) return;
-  const float* ys = B.ys[stage];
-  const Epi& E = B.E[stage];
-  switch (B.nrx) {
-    case 1: xfield_w_body<1>(B.P, ys, B.spec, B.ctl, B.partials, stage, 4, E, B.tw, B.logTw, w.y, w.y, bdl); break;
-    case 2: xfield_w_body<2>(B.P, ys, B.spec, B.ctl, B.partials, stage, 4, E, B.tw, B.logTw, w.y, w.y, bdl); break;
-    default: xfield_w_body<4>(B.P, ys, B.spec, B.ctl, B.partials, stage, 4, E, B.tw, B.logTw, w.y, w.y, bdl); break;
-  }
+  xfield_l_body<kBXT, 0>(B.P, B.ys[stage], B.spec, B.ctl, B.partials, stage,
+                         B.R, B.E[stage], B.tw, B.logTw, w.y, w.y, lds);
 }
 
 // One workgroup per active instance (`act` lists them).

@@ -43,7 +43,7 @@ int bfail(llgc_batch* b, int code, const char* fmt, ...) {
                    hipGetErrorString(e_));                                  \
   } while (0)
 
-int b_tiles(const llgc_ctx* c) { return (int)xgrid(c, kBatchRows).x; }
+int b_tiles(const llgc_ctx* c) { return (int)xgrid(c, c->Rf).x; }
 // spectral workgroups: column slots (kx = 0 and Px/2 share slot 0) per W
 int b_yblocks(const llgc_ctx* c) {
   return c->P.demag ? (c->Px / 2 + c->W - 1) / c->W : 1;
@@ -62,7 +62,7 @@ BInst make_binst(llgc_ctx* c, bool rk4) {
   B.ctl = c->ctl;
   B.tw = c->tw;
   B.logTw = c->logTw;
-  B.nrx = c->Px / 64;
+  B.R = c->Rf;
   B.W = c->W;
   B.nf = b_tiles(c);
   B.nbeg = n_pointwise_blocks(c);
@@ -227,11 +227,13 @@ int llgc_batch_create(const llgc_grid* grids, int32_t n, void* stream,
     cx += b_tiles(c);
     cy += (c->Px / 2 + c->W - 1) / c->W;   // demag may be set later
     cb += n_pointwise_blocks(c);
-    b->lds_x = std::max(b->lds_x, sizeof(float2) * (kBXT / 64) * c->Px);
-    b->lds_f = std::max(b->lds_f, sizeof(float) * 3 * kBatchRows * c->nx);
+    b->lds_x = std::max(b->lds_x, c->lds_f);
+    b->lds_f = std::max(b->lds_f, c->lds_i);
     b->lds_y = std::max(b->lds_y, c->lds_y);
   }
   raise_lds_limit((const void*)kb_yspec, b->lds_y);
+  raise_lds_limit((const void*)kb_xfwd, b->lds_x);
+  raise_lds_limit((const void*)kb_xfield, b->lds_f);
   b->cap_x = cx;
   b->cap_y = cy;
   b->cap_b = cb;

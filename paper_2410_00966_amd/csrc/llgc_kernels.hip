@@ -379,6 +379,95 @@ __global__ __launch_bounds__(T) void k_xfwd(
   if (threadIdx.x == 0) partials[blockIdx.x] = facc[0];
 }
 
+// ================================================================= k_xfwd3
+// Forward x pass of the batch plan: the 3 components x (R/2) row pairs of a
+// tile are transformed together in LDS (3 (R/2) Px complex), so short rows
+// still fill the workgroup; partial sums indexed by tile.
+template <int T>
+__device__ __forceinline__ void xfwd3_body(
+    const Prm& P, const float* __restrict__ ys, float2* __restrict__ spec,
+    double* __restrict__ partials, int R, const float2* __restrict__ tw,
+    int logTw, int tile, int slot, float2* lds_all) {
+  __shared__ double red[16];
+  float2* twl = lds_all;
+  float2* lds = lds_all + lds_twiddles(logTw);
+  if (P.demag) stage_twiddles(twl, tw, logTw);
+  const int nz = P.nz;
+  const int z = tile % nz;
+  const int y0 = (tile / nz) * R;
+  const int np = R >> 1;
+  const int Px = P.Px, nx = P.nx, ny = P.ny, nyp = P.nyp, N = P.ncell;
+  const int plane = nx * ny;
+  const float* msz = P.ms_map ? P.ms_map + (size_t)z * plane : nullptr;
+  // rows y0+2p (real part) and y0+2p+1 (imaginary part), x < Px/2 only:
+  // the rest is zero padding the first pass does not read
+  const int xl = Px > 1 ? Px >> 1 : 1;
+  const int per = np * xl;
+  double facc[1] = {0.0};   // sum of Ms m . B_rms over the tile
+  for (int e = threadIdx.x; e < 3 * per; e += T) {
+    const int c = e / per;
+    const int q = e - c * per;
+    const int p = q / xl, x = q - p * xl;
+    const double br = c == 0 ? P.brxd : (c == 1 ? P.bryd : P.brzd);
+    float2 v = make_float2(0.f, 0.f);
+    if (x < nx) {
+      const float* yc = ys + (size_t)c * N + (size_t)z * plane;
+      const int ya = y0 + 2 * p;
+      if (ya < ny) {
+        const float msv = msz ? msz[ya * nx + x] : P.ms;
+        const float mv = yc[ya * nx + x];
+        v.x = msv * mv;
+        facc[0] += (double)msv * (double)mv * br;
+      }
+      if (ya + 1 < ny) {
+        const float msv = msz ? msz[(ya + 1) * nx + x] : P.ms;
+        const float mv = yc[(ya + 1) * nx + x];
+        v.y = msv * mv;
+        facc[0] += (double)msv * (double)mv * br;
+      }
+    }
+    if (P.demag) lds[pidx((c * np + p) * Px + x)] = v;
+  }
+  if (P.demag) {
+    __syncthreads();
+    fft_lds<VPT, false, 0, true, false>(lds, P.logPx, 3 * np, twl, logTw,
+                                        -1.f);
+    // split the two real transforms, write the half spectrum: rows
+    // (y0+2p, y0+2p+1) are adjacent -> one 16-byte store per (c, kx, p)
+    const int H = P.Hx;
+    const int totw = 3 * np * H;
+    for (int e = threadIdx.x; e < totw; e += T) {
+      const int cp = e % (3 * np), k = e / (3 * np);
+      const int c = cp / np, p = cp - c * np;
+      const int b = cp * Px;
+      const float2 z1 = lds[pidx(b + k)];
+      const float2 z2 = lds[pidx(b + ((Px - k) & (Px - 1)))];
+      // A = (Z[k] + conj Z[-k]) / 2 ; B = (Z[k] - conj Z[-k]) / (2i)
+      float4 v = make_float4(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y),
+                             0.5f * (z1.y + z2.y), -0.5f * (z1.x - z2.x));
+      const int ya = y0 + 2 * p;
+      if (ya < ny) {
+        if (ya + 1 >= ny) { v.z = 0.f; v.w = 0.f; }   // keep the pad zero
+        float2* row = spec + ((size_t)(k * nz + z) * 3 + c) * nyp;
+        *(float4*)(row + ya) = v;
+      }
+    }
+  }
+  block_sum<1>(facc, red);
+  if (threadIdx.x == 0) partials[slot] = facc[0];
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void k_xfwd3(
+    Prm P, const float* __restrict__ ys, float2* __restrict__ spec,
+    Ctl* __restrict__ ctl, double* __restrict__ partials, int R,
+    const float2* __restrict__ tw, int logTw) {
+  extern __shared__ float2 lds_all[];
+  if (ctl->done) return;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  xfwd3_body<T>(P, ys, spec, partials, R, tw, logTw, tile, tile, lds_all);
+}
+
 // ================================================================ k_xfwd_w
 // Forward x pass with the FFT in registers (Px = 64 * NR): one wavefront per
 // (component, row pair) of an R-row tile.  Lane l, register r loads x =
@@ -1063,20 +1152,18 @@ __device__ __forceinline__ void field_cells(const Prm& P,
 // ================================================================ k_xfield
 // 1D grid of ceil(ny/R)*nz tiles (as k_xfwd); LDS: 3 * (R/2) * Px complex.
 // LP > 0: log2(Px) fixed at compile time (specialised FFT addressing).
+// Field pass of tile `tile` (partial sums into slot `slot`); LDS `lds`
+// holds the 3 (R/2) transforms only, lightly padded (2 slots per 64), so
+// that three workgroups fit a CU; twiddles are read from global memory.
 template <int T, int LP = 0>
-__global__ __launch_bounds__(T) void k_xfield(
-    Prm P, const float* __restrict__ ys, const float2* __restrict__ spec,
-    Ctl* __restrict__ ctl, double* __restrict__ partials,
-    double* __restrict__ rec, int stage, int R, Epi E,
-    const float2* __restrict__ tw, int logTw) {
-  // LDS: the 3 (R/2) transforms only, lightly padded (2 slots per 64), so
-  // that three workgroups fit a CU; twiddles are read from global memory
-  extern __shared__ float2 lds[];
-  if (ctl->done) return;
+__device__ __forceinline__ void xfield_l_body(
+    const Prm& P, const float* __restrict__ ys,
+    const float2* __restrict__ spec, const Ctl* __restrict__ ctl,
+    double* __restrict__ partials, int stage, int R, const Epi& E,
+    const float2* __restrict__ tw, int logTw, int tile, int slot,
+    float2* lds) {
   constexpr int PS = 6;
-  const int nblk = gridDim.x;
   const int nz = P.nz;
-  const int tile = xcd_tile(blockIdx.x, nblk);
   const int z = tile % nz;
   const int y0 = (tile / nz) * R;
   const int np = R >> 1;
@@ -1130,7 +1217,34 @@ __global__ __launch_bounds__(T) void k_xfield(
                 const float2 vz = lds[pidx_s<PS>((2 * np + p) * Px + x)];
                 return hi ? make_float3(vx.y, vy.y, vz.y)
                           : make_float3(vx.x, vy.x, vz.x);
-              }, blockIdx.x);
+              }, slot);
+}
+
+template <int T, int LP = 0>
+__global__ __launch_bounds__(T) void k_xfield(
+    Prm P, const float* __restrict__ ys, const float2* __restrict__ spec,
+    Ctl* __restrict__ ctl, double* __restrict__ partials,
+    double* __restrict__ rec, int stage, int R, Epi E,
+    const float2* __restrict__ tw, int logTw) {
+  extern __shared__ float2 lds[];
+  if (ctl->done) return;
+  xfield_l_body<T, LP>(P, ys, spec, ctl, partials, stage, R, E, tw, logTw,
+                       xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, lds);
+}
+
+// The field pass of the batch plan: partial sums indexed by tile (as the
+// batched kernels index them), so that both sum in the same order.
+template <int T>
+__global__ __launch_bounds__(T) void k_xfield_b(
+    Prm P, const float* __restrict__ ys, const float2* __restrict__ spec,
+    Ctl* __restrict__ ctl, double* __restrict__ partials,
+    double* __restrict__ rec, int stage, int R, Epi E,
+    const float2* __restrict__ tw, int logTw) {
+  extern __shared__ float2 lds[];
+  if (ctl->done) return;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  xfield_l_body<T, 0>(P, ys, spec, ctl, partials, stage, R, E, tw, logTw,
+                      tile, tile, lds);
 }
 
 // ============================================================== k_xfield_w
