@@ -1205,7 +1205,7 @@ __device__ __forceinline__ void xfield_l_body(
       }
     }
     __syncthreads();
-    fft_lds<VPT, false, LP, false, true, PS>(lds, P.logPx, 3 * np, tw, logTw,
+    fft_lds<VPT, true, LP, false, true, PS>(lds, P.logPx, 3 * np, tw, logTw,
                                              1.f);
   }
   field_cells(P, ys, ctl, partials, stage, R, E, z, y0,
