@@ -430,7 +430,7 @@ __device__ __forceinline__ void xfwd3_body(
   }
   if (P.demag) {
     __syncthreads();
-    fft_lds<VPT, false, 0, true, false>(lds, P.logPx, 3 * np, twl, logTw,
+    fft_lds<VPT, true, 0, true, false>(lds, P.logPx, 3 * np, twl, logTw,
                                         -1.f);
     // split the two real transforms, write the half spectrum: rows
     // (y0+2p, y0+2p+1) are adjacent -> one 16-byte store per (c, kx, p)
