@@ -163,7 +163,11 @@ __device__ __forceinline__ void dft_in_half(float2* v, float s) {
 // PIN (first pass only, Ns = 1): inputs at positions >= L/2 are zero and
 // are not read.  POUT (last pass only, Ns = L/R): outputs at positions
 // >= L/2 are not needed and are not written.
-template <int R, int NB, bool PIN = false, bool POUT = false, int PS = 4>
+// TT: `tw` is this pass's twiddle table, tw[(q-1) Ns + k] = exp(-2 pi i k q
+// / (Ns R)) (q = 1..R-1), read per power instead of forming the powers of
+// the base twiddle by repeated products (fewer VALU operations).
+template <int R, int NB, bool PIN = false, bool POUT = false, int PS = 4,
+          bool TT = false>
 __device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
                                          int batch, const float2* tw,
                                          int logTw, float dir) {
@@ -190,7 +194,7 @@ __device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
       for (int q = 0; q < (PIN ? R / 2 : R); ++q)
         v[i][q] = s[pidx_s<PS>(base + j + q * Lr)];
       const int k = j & (Ns - 1);
-      if (k != 0) w1[i] = tw[(k << twshift) & twmask];
+      if (!TT && k != 0) w1[i] = tw[(k << twshift) & twmask];
     }
   }
   __syncthreads();
@@ -200,7 +204,14 @@ __device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
     if (b < nbf) {
       const int t = b >> logLr, j = b & (Lr - 1);
       const int k = j & (Ns - 1);
-      if (k != 0) {
+      if (TT && k != 0) {
+#pragma unroll
+        for (int q = 1; q < R; ++q) {
+          float2 wq = tw[(q - 1) * Ns + k];
+          wq.y *= -dir;   // table holds exp(-i ...); inverse conjugates
+          v[i][q] = cmul(v[i][q], wq);
+        }
+      } else if (k != 0) {
         float2 w = w1[i];
         w.y *= -dir;   // table holds exp(-i ...); inverse conjugates
         float2 wq = w;
@@ -230,42 +241,109 @@ __device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
 // PIN: the input is zero from position L/2 on (zero padding; the first
 // pass does not read it).  POUT: only outputs below L/2 are used (the last
 // pass does not write the rest).
-template <int VPT, bool R16 = false, int LOGL = 0, bool PIN = false,
-          bool POUT = false, int PS = 4>
-__device__ __forceinline__ void fft_lds(float2* s, int logL, int batch,
-                                        const float2* tw,
-                        int logTw, float dir) {
-  if constexpr (LOGL > 0) logL = LOGL;
-  if (logL == 0) return;
-  int logNs = 0;
-  // radix plan: 16s (R16 and a thread may hold 16 values), then the
-  // remainder as one 8, one 4, two 4s, 8 + 4 in place of one 16, or one 2
+// Radix plan of a length-2^logL transform: 16s (R16 and a thread may hold
+// 16 values), then the remainder as one 8, one 4, two 4s, 8 + 4 in place of
+// one 16, or one 2; passes run in that order.
+struct FftPlan {
+  int n16, n8, n4, n2;
+};
+__host__ __device__ constexpr FftPlan fft_plan(int VPT, bool R16, int logL) {
   int n16 = (R16 && VPT >= 16) ? logL / 4 : 0;
   const int rem = logL - 4 * n16;
-  int n8 = rem / 3, tail = rem % 3;
-  int n4 = 0, n2 = 0;
+  int n8 = rem / 3, n4 = 0, n2 = 0;
+  const int tail = rem % 3;
   if (tail == 2) n4 = 1;
   if (tail == 1) {
     if (n8 > 0) { n8 -= 1; n4 = 2; }
     else if (n16 > 0) { n16 -= 1; n8 = 1; n4 = 1; }
     else { n2 = 1; }
   }
+  return FftPlan{n16, n8, n4, n2};
+}
+
+// Entries of the per-pass twiddle tables of that plan: (R-1) Ns for every
+// pass after the first.
+__host__ __device__ constexpr int fft_tt_len(int VPT, bool R16, int logL) {
+  const FftPlan pl = fft_plan(VPT, R16, logL);
+  int logNs = 0, n = 0;
+  auto add = [&](int logR, int count) {
+    for (int q = 0; q < count; ++q) {
+      if (logNs > 0) n += ((1 << logR) - 1) << logNs;
+      logNs += logR;
+    }
+  };
+  add(4, pl.n16);
+  add(3, pl.n8);
+  add(2, pl.n4);
+  add(1, pl.n2);
+  return n;
+}
+
+// Fills the per-pass twiddle tables (fft_tt_len entries at `tt`) from the
+// table tw[m] = exp(-2 pi i m / 2^logTw) in global memory; the caller
+// synchronises before the first transform.
+template <int VPT, bool R16, int LOGL>
+__device__ __forceinline__ void fft_tt_build(float2* tt,
+                                             const float2* __restrict__ tw,
+                                             int logTw) {
+  constexpr FftPlan pl = fft_plan(VPT, R16, LOGL);
+  int logNs = 0, off = 0;
+  const int mask = (1 << logTw) - 1;
+  auto fill = [&](int logR, int count) {
+    for (int c = 0; c < count; ++c) {
+      if (logNs > 0) {
+        const int Ns = 1 << logNs, n = ((1 << logR) - 1) << logNs;
+        const int sh = logTw - logNs - logR;
+        for (int e = threadIdx.x; e < n; e += blockDim.x) {
+          const int q = 1 + (e >> logNs), k = e & (Ns - 1);
+          tt[off + e] = tw[((k * q) << sh) & mask];
+        }
+        off += n;
+      }
+      logNs += logR;
+    }
+  };
+  fill(4, pl.n16);
+  fill(3, pl.n8);
+  fill(2, pl.n4);
+  fill(1, pl.n2);
+}
+
+// TT (with LOGL > 0): `tw` holds the per-pass twiddle tables of
+// fft_tt_build instead of the plain table.
+template <int VPT, bool R16 = false, int LOGL = 0, bool PIN = false,
+          bool POUT = false, int PS = 4, bool TT = false>
+__device__ __forceinline__ void fft_lds(float2* s, int logL, int batch,
+                                        const float2* tw,
+                        int logTw, float dir) {
+  static_assert(!TT || LOGL > 0, "twiddle tables need a fixed length");
+  if constexpr (LOGL > 0) logL = LOGL;
+  if (logL == 0) return;
+  int logNs = 0;
+  const FftPlan pl = fft_plan(VPT, R16, logL);
+  const int n16 = pl.n16, n8 = pl.n8, n4 = pl.n4, n2 = pl.n2;
   const int npass = n16 + n8 + n4 + n2;
   int p = 0;
+  int toff = 0;   // this pass's table offset (TT)
   // pass p of radix R; the first honours PIN, the last POUT
   auto pass = [&](auto rtag) {
     constexpr int R = decltype(rtag)::value;
     constexpr int NB = VPT / R;
     const bool first = p == 0, last = p == npass - 1;
+    const float2* twp = TT ? tw + toff : tw;
     if (PIN && first && POUT && last)
-      fft_pass<R, NB, PIN, POUT, PS>(s, logL, logNs, batch, tw, logTw, dir);
+      fft_pass<R, NB, PIN, POUT, PS, TT>(s, logL, logNs, batch, twp, logTw,
+                                         dir);
     else if (PIN && first)
-      fft_pass<R, NB, PIN, false, PS>(s, logL, logNs, batch, tw, logTw, dir);
+      fft_pass<R, NB, PIN, false, PS, TT>(s, logL, logNs, batch, twp, logTw,
+                                          dir);
     else if (POUT && last)
-      fft_pass<R, NB, false, POUT, PS>(s, logL, logNs, batch, tw, logTw, dir);
+      fft_pass<R, NB, false, POUT, PS, TT>(s, logL, logNs, batch, twp,
+                                           logTw, dir);
     else
-      fft_pass<R, NB, false, false, PS>(s, logL, logNs, batch, tw, logTw,
-                                        dir);
+      fft_pass<R, NB, false, false, PS, TT>(s, logL, logNs, batch, twp,
+                                            logTw, dir);
+    if (logNs > 0) toff += (R - 1) << logNs;
     logNs += Log2C<R>::v;
     ++p;
   };

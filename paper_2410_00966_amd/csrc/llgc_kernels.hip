@@ -45,8 +45,13 @@ constexpr int VPTY = LLGC_VPTY;
 // each pass reads its twiddles from LDS rather than from global memory right
 // after a barrier.  Returns the entry count (even, so that the data after it
 // stays 16-byte aligned).
-__host__ __device__ __forceinline__ int lds_twiddles(int logTw) {
+__host__ __device__ constexpr int lds_twiddles(int logTw) {
   return logTw > 1 ? 1 << (logTw - 1) : 2;
+}
+// LDS entries ahead of the spectral pass's data: per-pass twiddle tables
+// for a compile-time length 2^LP, else the staged half of the plain table.
+__host__ __device__ constexpr int yspec_tw_len(int LP, int logTw) {
+  return LP > 0 ? fft_tt_len(LLGC_VPTY, true, LP) : lds_twiddles(logTw);
 }
 __device__ __forceinline__ void stage_twiddles(float2* twl,
                                                const float2* __restrict__ tw,
@@ -652,9 +657,13 @@ __device__ __forceinline__ void yspec_l_body(
     int logTw, const double* __restrict__ partials, int nblk_f, int stage,
     int mode, int blk, float2* lds_all) {
   __shared__ double red[16];
+  // compile-time lengths read per-pass twiddle tables (fewer VALU
+  // operations); otherwise the first half of the plain table is staged
+  constexpr bool TT = LP > 0;
   float2* twl = lds_all;
-  float2* lds = lds_all + lds_twiddles(logTw);
-  stage_twiddles(twl, tw, logTw);
+  float2* lds = lds_all + yspec_tw_len(LP, logTw);
+  if constexpr (TT) fft_tt_build<VPTY, true, LP>(twl, tw, logTw);
+  else stage_twiddles(twl, tw, logTw);
   // workgroup 0 also finishes the coupling sum of this stage
   if (blk == 0) {
     finish_cavity(P, ctl, partials, nblk_f, stage, mode, red);
@@ -713,7 +722,8 @@ __device__ __forceinline__ void yspec_l_body(
     }
   }
   __syncthreads();
-  fft_lds<VPTY, true, LP, true, false>(lds, P.logPy, ncol, twl, logTw, -1.f);
+  fft_lds<VPTY, true, LP, true, false, 4, TT>(lds, P.logPy, ncol, twl, logTw,
+                                             -1.f);
   // pointwise product: per (w, ky), all 3*nz values
   const int Hy = P.Hy;
   for (int e = threadIdx.x; e < Wb * Py; e += T) {
@@ -759,7 +769,8 @@ __device__ __forceinline__ void yspec_l_body(
     for (int q = 0; q < nz3; ++q) lds[pidx((w * nz3 + q) * Py + ky)] = Hf[q];
   }
   __syncthreads();
-  fft_lds<VPTY, true, LP, false, true>(lds, P.logPy, ncol, twl, logTw, 1.f);
+  fft_lds<VPTY, true, LP, false, true, 4, TT>(lds, P.logPy, ncol, twl, logTw,
+                                             1.f);
   float2* dst = spec + (size_t)kx0 * nz3 * nyp;
   float2* dstn = spec + (size_t)hxn * nz3 * nyp;
   if (Py >= 4) {

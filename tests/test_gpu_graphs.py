@@ -126,3 +126,30 @@ def test_batch_graph_equals_direct(torch):
         assert np.array_equal(og[k][0], od[k][0])
         assert og[k][1] == od[k][1] and og[k][2] == od[k][2]
         assert np.array_equal(rg[k], rd[k])
+
+
+def test_plan_change_between_graph_runs(torch):
+    """A run (graph captured), autotuning (plan may change), another run:
+    equal to the same sequence with direct launches, where the second
+    context takes the recorded kind for the shape (reps=0)."""
+    from paper_2410_00966_amd.llgc import Sim
+    p, m0 = _problem(100, 70, 2, I.METHOD_DP45, seed=9)
+
+    def seq(direct, reps):
+        s = _with_env(direct, lambda: Sim(p))
+        s.set_state(torch.from_numpy(m0))
+        s.run(nsteps=20, t_end=1.0)
+        kind = s.autotune(reps=reps)
+        rec, info = s.run(nsteps=40, t_end=1.0, record_every=4, rec_cap=32)
+        m, t, a = s.get_state()
+        s.close()
+        return kind, m.cpu().numpy(), t, a, rec, info
+
+    kg, mg, tg, ag, rg, ig = seq(False, 5)
+    kd, md, td, ad, rd, idd = seq(True, 0)
+    _say("  kinds", kg, kd, "accepted", ig["accepted"], idd["accepted"])
+    assert kg == kd
+    assert ig["accepted"] == idd["accepted"]
+    assert tg == td and ag == ad
+    assert np.array_equal(mg, md)
+    assert np.array_equal(rg, rd)
