@@ -246,6 +246,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-t-end", type=float, default=10e-12)
     ap.add_argument("--batch-plain", type=int, default=32)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default plan (profiling runs: no tuning "
+                         "launches in the counters)")
     ap.add_argument("--no-wire", action="store_true")
     ap.add_argument("--wire-steps", type=int, default=400)
     ap.add_argument("--no-adjoint", action="store_true")
@@ -311,7 +314,7 @@ def main():
     prob.brms = brms
     sim.set_params(prob)
     sim.set_state(m_relaxed, 0.0, 0j)
-    kind = sim.autotune(reps=10)       # plan kinds timed on this grid
+    kind = sim.autotune(reps=0 if args.no_tune else 10)   # plan kinds timed
     plan = sim.plan_info()
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
