@@ -162,7 +162,13 @@ int llgc_cavity_enabled(const llgc_ctx *ctx);
  * `rec_cap` rows; `n_rec` receives the count.  `info` may be NULL.
  * Errors: LLGC_E_STATE (no params/state), LLGC_E_DT_UNDERFLOW,
  * LLGC_E_NONFINITE (adaptive error non-finite until underflow), LLGC_E_HIP.
- * On a DP45 failure the state is the last accepted one. */
+ * On a DP45 failure the state is the last accepted one.
+ * Launches: the kernels of a chunk (8 DP45 attempts, or one RK4 step) are
+ * captured once into a HIP graph on a private stream and replayed on the
+ * context's stream; the graph is captured again after anything passed by
+ * value changes (params, plan, record buffer).  Timed contexts
+ * (llgc_set_timing) and contexts created with the environment variable
+ * LLGC_NO_GRAPHS set launch directly; results are identical either way. */
 int llgc_run(llgc_ctx *ctx, int64_t nsteps, double t_end,
              int32_t record_every, double *rec, int64_t rec_cap,
              int64_t *n_rec, llgc_run_info *info);
@@ -284,6 +290,9 @@ llgc_ctx *llgc_batch_instance(llgc_batch *b, int32_t k);
  * each instance's llgc_run status) may be NULL.  Returns LLGC_OK when every
  * instance succeeded, else the first failing instance's status (its
  * message in llgc_batch_last_error).
+ * Each round of 8 attempts over the active instances is one HIP graph
+ * (captured again when finished instances are retired from the work
+ * tables), unless LLGC_NO_GRAPHS was set when the batch was created.
  * Errors: LLGC_E_STATE (an instance without params/state), LLGC_E_ARG
  * (mixed methods, records without a buffer), LLGC_E_HIP. */
 int llgc_batch_run(llgc_batch *b, int64_t nsteps, double t_end,

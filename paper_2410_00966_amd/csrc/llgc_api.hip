@@ -892,12 +892,16 @@ int run_chunk(llgc_ctx* c, int kind) {
     // runs on the caller's stream, after the work already queued there
     hipStream_t user = c->stream;
     c->stream = c->cap_stream;
-    int r = LLGC_OK;
     if (hipStreamBeginCapture(c->cap_stream,
-                              hipStreamCaptureModeThreadLocal) != hipSuccess)
-      r = fail(c, LLGC_E_HIP, "hipStreamBeginCapture failed");
-    else
-      r = chunk_direct(c, kind);
+                              hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      // capture unavailable (e.g. the caller is capturing this thread):
+      // this context launches directly from now on
+      c->stream = user;
+      (void)hipGetLastError();
+      c->graphs = false;
+      return chunk_direct(c, kind);
+    }
+    int r = chunk_direct(c, kind);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
     c->stream = user;

@@ -175,12 +175,15 @@ int batch_round(llgc_batch* b, bool rk4) {
                                           hipStreamNonBlocking));
     hipStream_t user = b->stream;
     b->stream = b->cap_stream;
-    int r = LLGC_OK;
     if (hipStreamBeginCapture(b->cap_stream,
-                              hipStreamCaptureModeThreadLocal) != hipSuccess)
-      r = bfail(b, LLGC_E_HIP, "hipStreamBeginCapture failed");
-    else
-      r = batch_round_direct(b, rk4);
+                              hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      // capture unavailable: this batch launches directly from now on
+      b->stream = user;
+      (void)hipGetLastError();
+      b->graphs = false;
+      return batch_round_direct(b, rk4);
+    }
+    int r = batch_round_direct(b, rk4);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
     b->stream = user;
