@@ -369,6 +369,73 @@ class Sim:
             pass
 
 
+_cavity_loss_cls = None
+
+
+def _cavity_loss_function():
+    """torch.autograd.Function over llgc_adjoint (built on first use so that
+    importing this module does not import torch)."""
+    global _cavity_loss_cls
+    if _cavity_loss_cls is not None:
+        return _cavity_loss_cls
+    import torch
+
+    class CavityLoss(torch.autograd.Function):
+        """L = mean over steps n0..n1 of |alpha_n|^2 after RK4 steps from
+        m0 (the photon number of section "Introducing the effect of the
+        cavity") as a function of the Ms map, the Ku map, the coupling field
+        B_rms (3,) and the cavity drive amplitude.  forward runs the
+        discrete adjoint once (llgc_adjoint: forward sweep with checkpoints,
+        reverse sweep) and keeps its gradients; backward scales them by the
+        incoming gradient."""
+
+        @staticmethod
+        def forward(ctx, ms_map, ku_map, brms, cdrive_amp, sim, m0, a0,
+                    n_steps, n0, n1, stride):
+            from . import inputs as I
+            q = I.Problem(**{**sim.prob.__dict__})
+            q.ms_map = ms_map.detach()
+            q.ku1_map = ku_map.detach()
+            q.brms = tuple(float(v) for v in brms.detach().cpu())
+            q.cdrive_amp = float(cdrive_amp.detach())
+            sim.set_params(q)
+            sim.set_state(m0, 0.0, a0)
+            g = sim.adjoint(n_steps, q.dt, n0, n1, stride)
+            ctx.save_for_backward(
+                g["g_ms"].reshape(ms_map.shape).to(ms_map.device,
+                                                   ms_map.dtype),
+                g["g_ku"].reshape(ku_map.shape).to(ku_map.device,
+                                                   ku_map.dtype),
+                torch.as_tensor(g["g_brms"], dtype=brms.dtype,
+                                device=brms.device),
+                torch.as_tensor(g["g_eps0"], dtype=cdrive_amp.dtype,
+                                device=cdrive_amp.device))
+            return torch.tensor(g["loss"], dtype=torch.float64,
+                                device=ms_map.device)
+
+        @staticmethod
+        def backward(ctx, gl):
+            gms, gku, gb, ge = ctx.saved_tensors
+            return (gms * gl.to(gms.dtype), gku * gl.to(gku.dtype),
+                    gb * gl.to(gb.dtype), ge * gl.to(ge.dtype),
+                    None, None, None, None, None, None, None)
+
+    _cavity_loss_cls = CavityLoss
+    return CavityLoss
+
+
+def cavity_loss(sim, m0, ms_map, ku_map, brms, cdrive_amp, n_steps, n0, n1,
+                a0=0j, stride=0):
+    """Differentiable windowed photon number (see CavityLoss).  `sim` is an
+    RK4 context whose problem supplies everything else (its params and
+    state are overwritten); `ms_map`, `ku_map` are tensors shaped
+    (nz, ny, nx), `brms` a (3,) tensor in T, `cdrive_amp` a 0-d tensor;
+    any of them may require grad.  Returns a 0-d float64 tensor."""
+    return _cavity_loss_function().apply(
+        ms_map, ku_map, brms, cdrive_amp, sim, m0, complex(a0), int(n_steps),
+        int(n0), int(n1), int(stride))
+
+
 class Batch:
     """Many problems of different sizes advanced together (llgc_batch_*).
     `sims[k]` is instance k, a `Sim` owned by the batch (set_state,
