@@ -7,8 +7,10 @@ cavity drive amplitude are compared with
   * the exact gradient of the oracle's discrete map (float64 reverse-mode
     autograd of oracle/adjoint.py, itself pinned to oracle/llg.py and to
     central differences), per cell;
-  * central finite differences of the FP64 oracle along seeded random
+  * central finite differences of the FP64 oracle along 20 seeded random
     directions (relative 1e-3).
+The oracle-gradient comparison runs on a 32x12x2 grid and on a 32x32x1
+copy of the adjoint workload's setting.
 Tolerances: FP32 forward and reverse sweeps against FP64; the per-cell maps
 to 1e-3 of their largest entry.
 """
@@ -46,10 +48,11 @@ def _problem(nx=32, ny=12, nz=2):
     return p, m0
 
 
-def test_adjoint_matches_oracle_gradient(torch):
+@pytest.mark.parametrize("grid", [(32, 12, 2), (32, 32, 1)])
+def test_adjoint_matches_oracle_gradient(torch, grid):
     from oracle.adjoint import gradient
     from paper_2410_00966_amd.llgc import Sim
-    p, m0 = _problem()
+    p, m0 = _problem(*grid)
     n, win = 60, (41, 60)
     print("adjoint vs oracle", p.shape, flush=True)
     ref = gradient(p, m0.astype(np.float64), 0j, p.dt, n, win,
@@ -100,7 +103,7 @@ def test_adjoint_directional_derivatives_match_fd(torch):
     ms0 = np.asarray(p.ms_map, dtype=np.float64)
     ku0 = np.asarray(p.ku1_map, dtype=np.float64)
     b0, e0 = p.brms[1], p.cdrive_amp
-    for d in range(4):
+    for d in range(20):                     # 20 seeded directions
         dm = rng.normal(size=p.shape)
         dk = rng.normal(size=p.shape)
         db, de = rng.normal(), rng.normal()
