@@ -25,7 +25,9 @@ numpy float64, in the order the paper states the problem.
     step; time-dependent terms evaluated at the stage times.
   * The integrated-out (memory-kernel) form of the cavity field, Eqs.
     (bcav)-(gammafinal), and the paper's rectangle-rule recursion,
-    Eqs. (Sdiscrete)-(gammadiscretefinal), are provided for cross-checks.
+    Eqs. (Sdiscrete)-(gammadiscretefinal), are provided for cross-checks,
+    and an RK4 integrator of m driven by that recursion (the paper's own
+    scheme: run_rk4_memory).
 
 Readings where the paper is silent: gamma = 1.7595e11 rad/(s T); open
 (Neumann) exchange boundaries; zero padding 2n per axis; DP45 error norm
@@ -245,6 +247,55 @@ class CavityLLG:
                 rec.append(self.record(t, m, a))
         return m, a, t, np.array(rec)
 
+    def run_rk4_memory(self, m0, a0, dt, nsteps, record_every=0):
+        """Fixed-step RK4 of m with the cavity integrated out, as the paper
+        does it (section "Adapting the memory term"): the cavity field
+        B_rms Gamma_n is held over step n (t_n -> t_{n+1}, t_n = n dt, t_0 =
+        0 at the reset), Gamma_n from the rectangle-rule recursion
+        Eqs. (Sdiscrete), (Cdiscrete), (gammadiscretefinal) on the coupling
+        sums F_n of the step-start states (S_0 = C_0 = 0):
+          S_n = S_{n-1} + e^{kappa t_n} sin(wc t_n) F_n dt
+          C_n = C_{n-1} + e^{kappa t_n} cos(wc t_n) F_n dt
+          Gamma_n = e^{-kappa t_n} [cos(wc t_n) (x0 - 2 V_c S_n / hbar)
+                                    - sin(wc t_n) (p0 - 2 V_c C_n / hbar)].
+        The cavity has no drive here (the paper drives the magnet).  Records
+        (t, <m>, Re a, Im a) use the amplitude the sums S_n, C_n give at
+        t_{n+1}, a = e^{-(i wc + kappa) t} (a0 + i (V_c/hbar)(C_n + i S_n))
+        (so that 2 Re a = Gamma before the term of F_{n+1} is added)."""
+        p = self.p
+        if p.cdrive_kind != DRIVE_NONE:
+            raise ValueError("the memory form takes no cavity drive")
+        m = np.asarray(m0, dtype=np.float64).copy()
+        a0 = complex(a0)
+        x0, p0 = 2.0 * a0.real, -2.0 * a0.imag
+        vh = self.vc / p.hbar
+        S = C = 0.0
+
+        def amp(t):
+            return np.exp(-(1j * p.wc + p.kappa) * t) * (
+                a0 + 1j * vh * (C + 1j * S))
+
+        rec = [self.record(0.0, m, a0)] if record_every else []
+        for n in range(nsteps):
+            tn = n * dt
+            if n > 0:
+                S, C = memory_sums(p, S, C, tn, self.coupling_sum(m), dt)
+            gam = memory_gamma_value(p, vh, S, C, tn, x0, p0)
+            # the field B_rms (a + a*) with a = Gamma_n / 2 held fixed
+            ah = 0.5 * gam
+
+            def f(mm, tt):
+                return self.torque(mm, self.effective_field(mm, ah, tt))
+
+            k1 = f(m, tn)
+            k2 = f(m + 0.5 * dt * k1, tn + 0.5 * dt)
+            k3 = f(m + 0.5 * dt * k2, tn + 0.5 * dt)
+            k4 = f(m + dt * k3, tn + dt)
+            m = normalise(m + dt / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4))
+            if record_every and (n + 1) % record_every == 0:
+                rec.append(self.record((n + 1) * dt, m, amp((n + 1) * dt)))
+        return m, amp(nsteps * dt), nsteps * dt, np.array(rec)
+
     def run_dp45(self, m0, a0, t_end, tol, dt0, record_every=0, t0=0.0,
                  dt_min=1e-20, dt_max=1e-10, max_attempts=10 ** 7):
         """Adaptive Dormand-Prince from t0 to t_end (last step truncated to
@@ -341,6 +392,22 @@ def alpha_a_posteriori(ts, Fs, prob, a0):
         out[n] = a0 * np.exp(-(prob.kappa + 1j * prob.wc) * t) + \
             1j * vc / prob.hbar * integral
     return out
+
+
+def memory_sums(prob, S, C, t, F, dt):
+    """One rectangle-rule term of Eqs. (Sdiscrete), (Cdiscrete):
+    S += e^{kappa t} sin(wc t) F dt, C += e^{kappa t} cos(wc t) F dt."""
+    e = math.exp(prob.kappa * t)
+    return (S + e * math.sin(prob.wc * t) * F * dt,
+            C + e * math.cos(prob.wc * t) * F * dt)
+
+
+def memory_gamma_value(prob, vh, S, C, t, x0, p0):
+    """Eq. (gammadiscretefinal) with vh = V_c / hbar:
+    Gamma = e^{-kappa t} [cos(wc t)(x0 - 2 vh S) - sin(wc t)(p0 - 2 vh C)]."""
+    ek = math.exp(-prob.kappa * t)
+    return ek * (math.cos(prob.wc * t) * (x0 - 2.0 * vh * S)
+                 - math.sin(prob.wc * t) * (p0 - 2.0 * vh * C))
 
 
 def memory_gamma_recursive(ts, Fs, prob, x0, p0):

@@ -1,7 +1,8 @@
 """Plant plausible mistakes in the oracle (on the CPU, by monkeypatching) and
 check that the pins catch each one: a wrong coupling sign, a dropped damping
 prefactor, a periodic instead of open exchange boundary, a transposed
-demag-tensor component and a wrong Dormand-Prince weight."""
+demag-tensor component, a wrong Dormand-Prince weight, and in the memory
+form's recursion swapped sin/cos, a flipped sign and a dropped e^{kappa t}."""
 import math
 
 import numpy as np
@@ -67,3 +68,37 @@ def test_wrong_dp_weight_breaks_order(monkeypatch):
     monkeypatch.setattr(L, "DP_B5", b5)
     with pytest.raises(AssertionError):
         T.test_dp45_local_error_order_five()
+
+
+def _memory_pin():
+    import test_oracle_memory as TM
+    TM.test_coupled_memory_form_converges_at_first_order()
+
+
+def test_memory_recursion_swapped_sin_cos(monkeypatch):
+    def sums(prob, S, C, t, F, dt):
+        e = math.exp(prob.kappa * t)
+        return (S + e * math.cos(prob.wc * t) * F * dt,
+                C + e * math.sin(prob.wc * t) * F * dt)
+    monkeypatch.setattr(L, "memory_sums", sums)
+    with pytest.raises(AssertionError):
+        _memory_pin()
+
+
+def test_memory_gamma_flipped_sign(monkeypatch):
+    def gamma(prob, vh, S, C, t, x0, p0):
+        ek = math.exp(-prob.kappa * t)
+        return ek * (math.cos(prob.wc * t) * (x0 + 2.0 * vh * S)
+                     - math.sin(prob.wc * t) * (p0 + 2.0 * vh * C))
+    monkeypatch.setattr(L, "memory_gamma_value", gamma)
+    with pytest.raises(AssertionError):
+        _memory_pin()
+
+
+def test_memory_sums_dropped_growth_factor(monkeypatch):
+    def sums(prob, S, C, t, F, dt):
+        return (S + math.sin(prob.wc * t) * F * dt,
+                C + math.cos(prob.wc * t) * F * dt)
+    monkeypatch.setattr(L, "memory_sums", sums)
+    with pytest.raises(AssertionError):
+        _memory_pin()
