@@ -52,6 +52,18 @@ enum {
 };
 
 enum { LLGC_RK4 = 0, LLGC_DP45 = 1 };
+/* Cavity treatment.  ODE: alpha is part of the integrated state, advanced
+ * by the same Runge-Kutta scheme as m (default).  MEMORY: the paper's own
+ * scheme with the cavity integrated out (section "Adapting the memory
+ * term"): the cavity field B_rms Gamma_n is held over step n and Gamma_n
+ * follows the rectangle-rule recursion Eqs. (Sdiscrete), (Cdiscrete),
+ * (gammadiscretefinal) on the coupling sum of the step-start state, first
+ * order in dt.  Evaluated in the equivalent amplitude form
+ * alpha_n = e^{-(i wc + kappa) dt} alpha_{n-1} + i (V_c/hbar) F_n dt
+ * (alpha_0 from the state; Gamma_n = 2 Re alpha_n), which needs no
+ * e^{kappa t} factors.  RK4 only, no cavity drive; the amplitude reported
+ * after step n is e^{-(i wc + kappa) dt} alpha_n. */
+enum { LLGC_CAVITY_ODE = 0, LLGC_CAVITY_MEMORY = 1 };
 enum { LLGC_DRIVE_NONE = 0, LLGC_DRIVE_SINC = 1, LLGC_DRIVE_CW = 2 };
 
 /* Grid of orthorhombic cells (section "The LLG equation in Mumax3").
@@ -93,6 +105,7 @@ typedef struct {
   double dt;               /* s: fixed step, or first trial step         */
   double tol;              /* DP45 error tolerance on |m5-m4|           */
   double dt_min, dt_max;   /* s, DP45 bounds (<= 0: 1e-20 and 1e-10)    */
+  int32_t cavity_mode;     /* LLGC_CAVITY_ODE or LLGC_CAVITY_MEMORY      */
 } llgc_params;
 
 typedef struct {

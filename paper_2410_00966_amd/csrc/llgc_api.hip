@@ -663,6 +663,7 @@ void fill_prm(llgc_ctx* c) {
   P.gpref = (float)(-gamma / (1.0 + p.alpha * p.alpha));
   P.alpha = (float)p.alpha;
   P.method = p.method;
+  P.cmode = p.cavity_mode;
   P.tol = p.tol;
   P.dt_min = p.dt_min > 0 ? p.dt_min : 1e-20;
   P.dt_max = p.dt_max > 0 ? p.dt_max : 1e-10;
@@ -1133,6 +1134,13 @@ int llgc_set_params(llgc_ctx* c, const llgc_params* p) {
   if (p->method == LLGC_DP45 && !(p->tol > 0))
     return fail(c, LLGC_E_ARG, "tol must be > 0");
   if (!(p->kappa >= 0)) return fail(c, LLGC_E_ARG, "kappa must be >= 0");
+  if (p->cavity_mode != LLGC_CAVITY_ODE &&
+      p->cavity_mode != LLGC_CAVITY_MEMORY)
+    return fail(c, LLGC_E_ARG, "unknown cavity mode %d", p->cavity_mode);
+  if (p->cavity_mode == LLGC_CAVITY_MEMORY &&
+      (p->method != LLGC_RK4 || p->cdrive_kind != 0))
+    return fail(c, LLGC_E_UNSUPPORTED,
+                "the memory recursion runs with RK4 and no cavity drive");
   c->prm = *p;
   const size_t nb = sizeof(float) * c->N;
   if (p->ms_map) {
@@ -1189,6 +1197,7 @@ int llgc_set_state(llgc_ctx* c, const float* m, double t, double are,
   h.done = 0;
   h.status = 0;
   h.prev_rej = 0;
+  h.mem_n = 0;
   if (c->have_params) h.dt = c->prm.dt;
   if (int r = ctl_write(c, c->ctl, &h)) return r;
   c->have_state = true;
@@ -1220,6 +1229,7 @@ int llgc_reset_cavity(llgc_ctx* c, double x0, double p0) {
   h.a_im = -0.5 * p0;
   h.as_re[1] = h.a_re;
   h.as_im[1] = h.a_im;
+  h.mem_n = 0;
   if (int r = ctl_write(c, c->ctl, &h)) return r;
   c->need_init = true;
   return LLGC_OK;
@@ -1595,6 +1605,8 @@ extern "C" int llgc_adjoint(llgc_ctx* c, int64_t n_steps, double dt,
     return fail(c, LLGC_E_ARG, "bad step count, window or dt");
   if (c->Px < 64)
     return fail(c, LLGC_E_UNSUPPORTED, "adjoint needs padded nx >= 64");
+  if (c->prm.cavity_mode != LLGC_CAVITY_ODE)
+    return fail(c, LLGC_E_UNSUPPORTED, "adjoint of the cavity ODE form only");
   if (stride <= 0) stride = (int64_t)std::ceil(std::sqrt((double)n_steps));
   const int64_t S = stride;
   const int64_t nseg = (n_steps + S - 1) / S;

@@ -26,6 +26,7 @@ struct Ctl {
   // end-of-step amplitude, 5 complex per step) and the windowed loss
   // sum_{n0 <= n <= n1} |alpha_n|^2 over accepted RK4 steps n (1-based)
   double* ahist;
+  long long mem_n;   // memory recursion: steps since the state was set
   long long loss_n0, loss_n1;
   double loss_acc;
 };
@@ -57,6 +58,7 @@ struct Prm {
   float gpref;                  // -gamma / (1 + alpha^2)
   float alpha;
   int method;                   // 0 RK4, 1 DP45
+  int cmode;                    // 0 cavity ODE, 1 memory recursion
   double tol, dt_min, dt_max;
 };
 

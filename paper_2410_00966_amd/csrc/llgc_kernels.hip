@@ -213,6 +213,28 @@ __device__ inline double max_partials(const double* p, unsigned int n,
 __device__ __forceinline__ void cavity_stage(const Prm& P, Ctl* c, int s,
                                              double F) {
   const double dt = c->dt;
+  if (P.cmode == 1) {
+    // integrated-out cavity (RK4): at the step start alpha_n = alpha^-_n +
+    // i (V_c/hbar) F_n dt (no term at the first step after the state was
+    // set), held over the four stages; alpha^-_{n+1} = e^{-(i wc+kappa) dt}
+    // alpha_n is committed as the end-of-step amplitude
+    c->ka_re[s] = 0.0;
+    c->ka_im[s] = 0.0;
+    c->F_last = F;
+    if (s == 1) {
+      const double ar = c->as_re[1];
+      const double ai = c->as_im[1] + (c->mem_n > 0 ? dt * P.vc_hbar * F : 0.0);
+      for (int q = 1; q <= 4; ++q) {
+        c->as_re[q] = ar;
+        c->as_im[q] = ai;
+      }
+      const double e = exp(-P.kappa * dt);
+      const double cw = cos(P.wc * dt), sw = sin(P.wc * dt);
+      c->anext_re = e * (ar * cw + ai * sw);
+      c->anext_im = e * (ai * cw - ar * sw);
+    }
+    return;
+  }
   const double ts = c->t + stage_c(P, s) * dt;
   const double eps = P.camp * drive_shape(P.ckind, P.cw, ts);
   const double ar = c->as_re[s], ai = c->as_im[s];
@@ -1350,6 +1372,7 @@ __device__ __forceinline__ void finish_step_body(
     c->t = c->t + c->dt;
     c->a_re = c->anext_re;
     c->a_im = c->anext_im;
+    c->mem_n += 1;
     c->as_re[1] = c->a_re;
     c->as_im[1] = c->a_im;
     if (c->ahist) {

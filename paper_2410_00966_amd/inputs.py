@@ -24,6 +24,7 @@ HBAR = 1.05457182e-34      # J s
 MU0 = 4e-7 * math.pi       # T m / A
 
 DRIVE_NONE, DRIVE_SINC, DRIVE_CW = 0, 1, 2
+CAVITY_ODE, CAVITY_MEMORY = 0, 1
 METHOD_RK4, METHOD_DP45 = 0, 1
 
 
@@ -65,6 +66,9 @@ class Problem:
     tol: float = 1e-6
     dt_min: float = 1e-20
     dt_max: float = 1e-10
+    # cavity treatment: CAVITY_ODE (alpha integrated with m) or
+    # CAVITY_MEMORY (the paper's integrated-out recursion; RK4 only)
+    cavity_mode: int = 0
     # optional per-cell maps, float32 arrays of shape (nz, ny, nx)
     ms_map: Optional[np.ndarray] = None
     ku1_map: Optional[np.ndarray] = None

@@ -61,7 +61,7 @@ class Params(ctypes.Structure):
         ("mu0", ctypes.c_double),
         ("method", ctypes.c_int32), ("dt", ctypes.c_double),
         ("tol", ctypes.c_double), ("dt_min", ctypes.c_double),
-        ("dt_max", ctypes.c_double),
+        ("dt_max", ctypes.c_double), ("cavity_mode", ctypes.c_int32),
     ]
 
 
@@ -160,6 +160,7 @@ def make_params(prob, ms_map=None, ku_map=None) -> Params:
     p.cdrive_w = prob.cdrive_w
     p.gamma, p.hbar, p.mu0 = prob.gamma, prob.hbar, prob.mu0
     p.method = prob.method
+    p.cavity_mode = getattr(prob, "cavity_mode", 0)
     p.dt, p.tol = prob.dt, prob.tol
     p.dt_min, p.dt_max = prob.dt_min, prob.dt_max
     return p
