@@ -92,6 +92,16 @@ class CavityLLG:
         self.ku = prob.ku_array()
         self.vc = prob.dx * prob.dy * prob.dz
         self.u = np.asarray(prob.anis_u, dtype=np.float64)
+        # vacuum field of the mode per cell, (3, nz, ny, nx): the map when
+        # one is given (section "Workflow in Mumax3-cQED": B_rms may vary in
+        # space), else the uniform vector everywhere
+        bmap = getattr(prob, "brms_map", None)
+        if bmap is not None:
+            self.brms_cells = np.asarray(bmap, dtype=np.float64).reshape(
+                (3,) + self.shape)
+        else:
+            self.brms_cells = np.asarray(prob.brms, dtype=np.float64).reshape(
+                3, 1, 1, 1) * np.ones((1,) + self.shape)
         self.brms = np.asarray(prob.brms, dtype=np.float64)
         self.nfull = None
         self.kf = None
@@ -147,17 +157,16 @@ class CavityLLG:
         return _demag.demag_field_fft(M, self.kf, self.p.mu0)
 
     def cavity_field(self, a):
-        """B_cav = B_rms (alpha + alpha^*)."""
-        return (self.brms * 2.0 * a.real).reshape(3, 1, 1, 1) * np.ones(
-            (1,) + self.shape)
+        """B_cav,i = B_rms,i (alpha + alpha^*)."""
+        return self.brms_cells * (2.0 * a.real)
 
     def effective_field(self, m, a, t):
         return (self.zeeman(t) + self.exchange(m) + self.anisotropy(m)
                 + self.demag(m) + self.cavity_field(a))
 
     def coupling_sum(self, m):
-        """F = sum_i Ms_i m_i . B_rms  (A m^-1 T)."""
-        return float((self.ms * np.einsum("c,czyx->zyx", self.brms, m)).sum())
+        """F = sum_i Ms_i m_i . B_rms,i  (A m^-1 T)."""
+        return float((self.ms * (self.brms_cells * m).sum(axis=0)).sum())
 
     # -------------------------------------------------------------- dynamics
     def torque(self, m, B):

@@ -72,6 +72,9 @@ class Problem:
     # optional per-cell maps, float32 arrays of shape (nz, ny, nx)
     ms_map: Optional[np.ndarray] = None
     ku1_map: Optional[np.ndarray] = None
+    # optional vacuum field of the mode per cell, float32 (3, nz, ny, nx) in
+    # T; replaces the uniform brms when given
+    brms_map: Optional[np.ndarray] = None
 
     @property
     def shape(self):
