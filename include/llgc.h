@@ -106,6 +106,11 @@ typedef struct {
   double tol;              /* DP45 error tolerance on |m5-m4|           */
   double dt_min, dt_max;   /* s, DP45 bounds (<= 0: 1e-20 and 1e-10)    */
   int32_t cavity_mode;     /* LLGC_CAVITY_ODE or LLGC_CAVITY_MEMORY      */
+  const float *brms_map;   /* T, vacuum field of the mode per cell, 3 N
+                              float32 as [c][z][y][x] (device; copied), or
+                              NULL for the uniform brms.  Section "Workflow
+                              in Mumax3-cQED": B_rms may vary in space.
+                              Not with llgc_adjoint. */
 } llgc_params;
 
 typedef struct {

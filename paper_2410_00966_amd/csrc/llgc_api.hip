@@ -79,6 +79,7 @@ struct llgc_ctx {
   Ctl* ctl = nullptr;
   Ctl* ctl_eval = nullptr;
   float *ms_map = nullptr, *ku_map = nullptr;
+  float* brms_map = nullptr;   // 3 N floats
   size_t npartials = 0;
   // host state
   llgc_params prm{};
@@ -400,6 +401,15 @@ int rhs_stage(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
               const Epi& E, int mode) {
   int r;
   if ((r = launch_xfwd(c, ys, ctl, stage, mode))) return r;
+  if (c->P.brms_map) {
+    // coupling partial sums with the per-cell B_rms (replace the forward
+    // pass's uniform-B_rms sums, tile for tile)
+    Timed tm(c, "k_coupling_map");
+    const int R = fwd_rows(c);
+    hipLaunchKernelGGL(k_coupling_map<kT>, xgrid(c, R), dim3(kT), 0,
+                       c->stream, c->P, ys, ctl, c->partials, R);
+    if ((r = check_launch(c, "k_coupling_map"))) return r;
+  }
   if ((r = launch_yspec(c, ctl, stage, mode))) return r;
   if ((r = launch_xfield(c, ys, ctl, stage, E))) return r;
   if (E.kind == 2 || E.kind == 3) {
@@ -639,6 +649,7 @@ void fill_prm(llgc_ctx* c) {
   P.idz2 = (float)(1.0 / (c->dz * c->dz));
   P.ms = (float)p.ms;
   P.ms_map = c->ms_map;
+  P.brms_map = c->brms_map;
   P.aex2 = (float)(2.0 * p.aex);
   P.ku2 = (float)(2.0 * p.ku1);
   P.ku_map = c->ku_map;
@@ -1108,6 +1119,7 @@ int llgc_destroy(llgc_ctx* c) {
   hipFree(c->ctl);
   hipFree(c->ctl_eval);
   hipFree(c->ms_map);
+  hipFree(c->brms_map);
   hipFree(c->ku_map);
   delete c;
   return LLGC_OK;
@@ -1158,6 +1170,14 @@ int llgc_set_params(llgc_ctx* c, const llgc_params* p) {
   } else if (c->ku_map) {
     HIPCHK(c, hipFree(c->ku_map));
     c->ku_map = nullptr;
+  }
+  if (p->brms_map) {
+    if (!c->brms_map) HIPCHK(c, hipMalloc(&c->brms_map, 3 * nb));
+    HIPCHK(c, hipMemcpyAsync(c->brms_map, p->brms_map, 3 * nb,
+                             hipMemcpyDeviceToDevice, c->stream));
+  } else if (c->brms_map) {
+    HIPCHK(c, hipFree(c->brms_map));
+    c->brms_map = nullptr;
   }
   fill_prm(c);
   const double mu0 = p->mu0 > 0 ? p->mu0 : 4e-7 * M_PI;
@@ -1239,6 +1259,7 @@ int llgc_cavity_enabled(const llgc_ctx* c) {
   if (!c) return LLGC_E_ARG;
   if (!c->have_params) return 0;
   const double* b = c->prm.brms;
+  if (c->brms_map) return 1;
   return (b[0] != 0.0 || b[1] != 0.0 || b[2] != 0.0) ? 1 : 0;
 }
 
@@ -1607,6 +1628,8 @@ extern "C" int llgc_adjoint(llgc_ctx* c, int64_t n_steps, double dt,
     return fail(c, LLGC_E_UNSUPPORTED, "adjoint needs padded nx >= 64");
   if (c->prm.cavity_mode != LLGC_CAVITY_ODE)
     return fail(c, LLGC_E_UNSUPPORTED, "adjoint of the cavity ODE form only");
+  if (c->brms_map)
+    return fail(c, LLGC_E_UNSUPPORTED, "adjoint with a uniform B_rms only");
   if (stride <= 0) stride = (int64_t)std::ceil(std::sqrt((double)n_steps));
   const int64_t S = stride;
   const int64_t nseg = (n_steps + S - 1) / S;
@@ -1692,6 +1715,7 @@ extern "C" int llgc_adjoint(llgc_ctx* c, int64_t n_steps, double dt,
   Prm Pu = c->P;
   Pu.ms = 1.f;
   Pu.ms_map = nullptr;
+  Pu.brms_map = nullptr;
   Pu.brx = Pu.bry = Pu.brz = 0.f;
   Pu.brxd = Pu.bryd = Pu.brzd = 0.0;
   Ctl he{};

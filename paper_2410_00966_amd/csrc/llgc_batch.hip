@@ -84,6 +84,17 @@ __global__ __launch_bounds__(kBXT) void kb_xfield(const BInst* __restrict__ I,
                          B.R, B.E[stage], B.tw, B.logTw, w.y, w.y, lds);
 }
 
+// Coupling sums with a per-cell B_rms map, tile for tile after kb_xfwd
+// (instances without a map return at once).
+__global__ __launch_bounds__(256) void kb_coupling(const BInst* __restrict__ I,
+                                                   const int2* __restrict__ it,
+                                                   int stage) {
+  const int2 w = bitem(it);
+  const BInst& B = I[w.x];
+  if (B.ctl->done || !B.P.brms_map) return;
+  coupling_tile_body<256>(B.P, B.ys[stage], B.partials, B.R, w.y, w.y);
+}
+
 // One workgroup per active instance (`act` lists them).
 __global__ __launch_bounds__(256) void kb_finish_step(
     const BInst* __restrict__ I, const int* __restrict__ act, int kind,

@@ -13,6 +13,7 @@ struct llgc_batch {
   int* act = nullptr;
   int* flags = nullptr;        // [0]: finished count, [1 + k]: done flag k
   int n_x = 0, n_y = 0, n_b = 0, n_act = 0;
+  bool any_map = false;   // some instance has a per-cell B_rms map
   size_t cap_x = 0, cap_y = 0, cap_b = 0;   // work-table capacities
   size_t lds_x = 0, lds_f = 0, lds_y = 0;
   std::string err;
@@ -124,6 +125,9 @@ int batch_tables(llgc_batch* b, const std::vector<char>& active) {
 int batch_stage(llgc_batch* b, int stage) {
   hipLaunchKernelGGL(kb_xfwd, dim3(b->n_x), dim3(kBXT), b->lds_x, b->stream,
                      b->dI, b->it_x, stage);
+  if (b->any_map)
+    hipLaunchKernelGGL(kb_coupling, dim3(b->n_x), dim3(256), 0, b->stream,
+                       b->dI, b->it_x, stage);
   hipLaunchKernelGGL(kb_yspec, dim3(b->n_y), dim3(kBYT), b->lds_y, b->stream,
                      b->dI, b->it_y, stage, 0);
   hipLaunchKernelGGL(kb_xfield, dim3(b->n_x), dim3(kBXT), b->lds_f,
@@ -309,7 +313,11 @@ int llgc_batch_run(llgc_batch* b, int64_t nsteps, double t_end,
     ndone0 += rp[k].done ? 1 : 0;
   }
   std::vector<BInst> hI(n);
-  for (int k = 0; k < n; ++k) hI[k] = make_binst(b->inst[k], rk4);
+  b->any_map = false;
+  for (int k = 0; k < n; ++k) {
+    hI[k] = make_binst(b->inst[k], rk4);
+    if (b->inst[k]->brms_map) b->any_map = true;
+  }
   BHIPCHK(b, hipMemcpyAsync(b->dI, hI.data(), sizeof(BInst) * n,
                             hipMemcpyHostToDevice, b->stream));
   BHIPCHK(b, hipMemcpyAsync(b->flags, &ndone0, sizeof(int),

@@ -51,6 +51,7 @@ struct Prm {
   float fdx, fdy, fdz;          // field drive direction
   int demag;
   float brx, bry, brz;          // B_rms
+  const float* brms_map;        // per-cell B_rms [c][cell] or nullptr
   double brxd, bryd, brzd;
   double wc, kappa, vc_hbar;    // V_c / hbar
   int ckind;

@@ -495,6 +495,40 @@ __global__ __launch_bounds__(T) void k_xfwd3(
   xfwd3_body<T>(P, ys, spec, partials, R, tw, logTw, tile, tile, lds_all);
 }
 
+// ========================================================== k_coupling_map
+// Partial coupling sums sum Ms_i m_i . B_rms,i over the cells of one x-pass
+// tile (rows y0 .. y0+R-1 of layer z) with the per-cell B_rms map, written
+// to `slot` (they replace the forward pass's uniform-B_rms sums).
+template <int T>
+__device__ __forceinline__ void coupling_tile_body(
+    const Prm& P, const float* __restrict__ ys, double* __restrict__ partials,
+    int R, int tile, int slot) {
+  __shared__ double red[16];
+  const int nx = P.nx, ny = P.ny, nz = P.nz, N = P.ncell;
+  const int z = tile % nz;
+  const int y0 = (tile / nz) * R;
+  const float* bm = P.brms_map;
+  double f[1] = {0.0};
+  for (int e = threadIdx.x; e < R * nx; e += T) {
+    const int y = y0 + e / nx, x = e % nx;
+    if (y >= ny) continue;
+    const int i = (z * ny + y) * nx + x;
+    const double msv = P.ms_map ? (double)P.ms_map[i] : (double)P.ms;
+    f[0] += msv * ((double)ys[i] * bm[i] + (double)ys[N + i] * bm[N + i] +
+                   (double)ys[2 * N + i] * bm[2 * N + i]);
+  }
+  block_sum<1>(f, red);
+  if (threadIdx.x == 0) partials[slot] = f[0];
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void k_coupling_map(
+    Prm P, const float* __restrict__ ys, Ctl* __restrict__ ctl,
+    double* __restrict__ partials, int R) {
+  if (ctl->done) return;
+  coupling_tile_body<T>(P, ys, partials, R, blockIdx.x, blockIdx.x);
+}
+
 // ================================================================ k_xfwd_w
 // Forward x pass with the FFT in registers (Px = 64 * NR): one wavefront per
 // (component, row pair) of an R-row tile.  Lane l, register r loads x =
@@ -1091,6 +1125,7 @@ __device__ __forceinline__ void field_cells(const Prm& P,
               bez = P.bz + fd * P.fdz;
   const float gcav = (float)(2.0 * ctl->as_re[stage]);
   const float bcx = P.brx * gcav, bcy = P.bry * gcav, bcz = P.brz * gcav;
+  const float* bmap = P.brms_map;
   double acc[3] = {0.0, 0.0, 0.0};
   float emax = 0.f;
   const int ncellb = R * nx;
@@ -1108,6 +1143,11 @@ __device__ __forceinline__ void field_cells(const Prm& P,
     const float mx = ys[i], my = ys[N + i], mz = ys[2 * N + i];
     const float msv = P.ms_map ? P.ms_map[i] : P.ms;
     float Bx = bex + bcx, By = bey + bcy, Bz = bez + bcz;
+    if (bmap) {   // per-cell vacuum field of the mode
+      Bx = bex + bmap[i] * gcav;
+      By = bey + bmap[N + i] * gcav;
+      Bz = bez + bmap[2 * N + i] * gcav;
+    }
     if (P.demag) {
       const float3 b = bd(r, x);
       Bx += b.x;

@@ -62,6 +62,7 @@ class Params(ctypes.Structure):
         ("method", ctypes.c_int32), ("dt", ctypes.c_double),
         ("tol", ctypes.c_double), ("dt_min", ctypes.c_double),
         ("dt_max", ctypes.c_double), ("cavity_mode", ctypes.c_int32),
+        ("brms_map", _FP),
     ]
 
 
@@ -137,7 +138,7 @@ def grid_of(prob) -> Grid:
     return Grid(prob.nx, prob.ny, prob.nz, prob.dx, prob.dy, prob.dz)
 
 
-def make_params(prob, ms_map=None, ku_map=None) -> Params:
+def make_params(prob, ms_map=None, ku_map=None, brms_map=None) -> Params:
     """Marshals an inputs.Problem into the C struct (maps: device tensors)."""
     p = Params()
     p.ms = prob.ms
@@ -161,6 +162,7 @@ def make_params(prob, ms_map=None, ku_map=None) -> Params:
     p.gamma, p.hbar, p.mu0 = prob.gamma, prob.hbar, prob.mu0
     p.method = prob.method
     p.cavity_mode = getattr(prob, "cavity_mode", 0)
+    p.brms_map = brms_map.data_ptr() if brms_map is not None else None
     p.dt, p.tol = prob.dt, prob.tol
     p.dt_min, p.dt_max = prob.dt_min, prob.dt_max
     return p
@@ -215,7 +217,9 @@ class Sim:
         self.prob = prob
         msm = self._dev(prob.ms_map) if prob.ms_map is not None else None
         kum = self._dev(prob.ku1_map) if prob.ku1_map is not None else None
-        p = make_params(prob, msm, kum)
+        bm = getattr(prob, "brms_map", None)
+        brm = self._dev(bm).reshape(-1) if bm is not None else None
+        p = make_params(prob, msm, kum, brm)
         self._check(self.L.llgc_set_params(self.h, ctypes.byref(p)),
                     "llgc_set_params")
         self.stream.synchronize()

@@ -1,0 +1,141 @@
+"""GPU tests of the per-cell vacuum field of the mode (brms_map) against the
+FP64 oracle (whose map path is pinned to the uniform case and to independent
+cells): right-hand side element by element, a fixed-step run per cell, a
+batch with and without maps bit for bit against standalone solves, and the
+refusal in the adjoint.  Tolerances as the uniform-B_rms parity tests.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2410_00966_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+def _strip_map(shape, b0, seed):
+    """Field of a strip line along x: strongest over the middle third in y,
+    falling off outside, plus a seeded smooth perturbation (float32)."""
+    nz, ny, nx = shape
+    y = (np.arange(ny) + 0.5) / ny
+    prof = np.exp(-((y - 0.5) / 0.2) ** 2)
+    rng = np.random.default_rng(seed)
+    bm = np.zeros((3,) + shape)
+    bm[0] = b0 * prof[None, :, None]
+    bm[1] = 0.3 * b0 * prof[None, :, None] * np.cos(
+        2 * np.pi * np.arange(nx) / nx)[None, None, :]
+    bm[2] = 0.1 * b0 * rng.standard_normal(shape)
+    return bm.astype(np.float32)
+
+
+def _problem(nx, ny, nz, method=I.METHOD_RK4):
+    p = I.Problem(nx=nx, ny=ny, nz=nz, dx=4e-9, dy=4e-9, dz=4e-9, ms=8e5,
+                  aex=1.3e-11, alpha=0.02, ku1=2e4, anis_u=(0.6, 0.0, 0.8),
+                  bext=(0.01, 0.03, 0.1), method=method, dt=1e-13, tol=1e-6)
+    p.wc = 2 * math.pi * 8e9
+    p.kappa = 1e-3 * p.wc
+    b0 = I.brms_from_g(0.05 * p.wc, p.ms * p.ncells * p.vcell)
+    p.brms_map = _strip_map(p.shape, b0, seed=nx + ny + nz)
+    p.ms_map = I.smooth_map(nx, ny, nz, 7e5, 9e5, 4, 2, seed=nx * ny)
+    return p
+
+
+@pytest.mark.parametrize("grid", [(37, 23, 3), (64, 40, 1), (20, 600, 2)])
+def test_rhs_with_map_matches_oracle(torch, grid):
+    from oracle.llg import CavityLLG
+    from paper_2410_00966_amd.llgc import Sim
+    p = _problem(*grid)
+    rng = np.random.default_rng(sum(grid))
+    m = rng.normal(size=(3,) + p.shape)
+    m = (m / np.sqrt((m * m).sum(0))).astype(np.float32)
+    a, t = 0.6 - 0.3j, 1e-12
+    o = CavityLLG(p)
+    Bref = o.effective_field(m.astype(np.float64), a, t)
+    dref, daref = o.rhs(m.astype(np.float64), a, t)
+    s = Sim(p)
+    assert s.cavity_enabled() == 1
+    dm, B, da = s.eval_rhs(torch.from_numpy(m), a, t)
+    s.close()
+    eB = np.abs(B.cpu().numpy() - Bref).max() / np.abs(Bref).max()
+    ed = np.abs(dm.cpu().numpy() - dref).max() / np.abs(dref).max()
+    _say("map rhs", grid, "field err", eB, "torque err", ed, "da", da, daref)
+    assert eB < 2e-5 and ed < 2e-5
+    assert abs(da - daref) <= 1e-9 * abs(daref)
+
+
+def test_rk4_run_with_map_matches_oracle(torch):
+    from oracle.llg import CavityLLG
+    from paper_2410_00966_amd.llgc import Sim
+    p = _problem(24, 20, 2)
+    m0 = I.tilted_uniform_state(p.shape, 10.0, 1e-3, seed=4101)
+    n, every = 200, 20
+    mref, aref, _, recref = CavityLLG(p).run_rk4(m0.astype(np.float64), 0j,
+                                                 p.dt, n, every)
+    s = Sim(p)
+    s.set_state(torch.from_numpy(m0))
+    rec, _ = s.run(nsteps=n, record_every=every)
+    m, _, a = s.get_state()
+    s.close()
+    dm = np.abs(m.cpu().numpy() - mref).max()
+    scale = max(1.0, np.abs(recref[:, 4:]).max())
+    _say("map rk4 max|dm|", dm, "a", a, aref)
+    assert dm <= 1e-4
+    assert np.abs(rec[:, 4:] - recref[:, 4:]).max() <= 1e-3 * scale
+    assert abs(aref) > 1e-3                 # the map couples
+
+
+def test_batch_with_maps_equals_standalone(torch):
+    from paper_2410_00966_amd.llgc import Batch, Sim
+    probs, m0s = [], []
+    for k, sh in enumerate([(24, 20, 2), (40, 16, 1), (17, 33, 3)]):
+        p = _problem(*sh, method=I.METHOD_DP45)
+        if k == 1:
+            p.brms_map = None
+            p.brms = (2e-3, 0.0, 0.0)
+        probs.append(p)
+        m0s.append(I.tilted_uniform_state(p.shape, 10.0, 1e-3, seed=4200 + k))
+    T = 10e-12
+    b = Batch(probs)
+    for s, m0 in zip(b.sims, m0s):
+        s.set_state(torch.from_numpy(m0))
+    recs, infos, st = b.run(t_end=T, record_every=4, rec_cap=200)
+    outs = [s.get_state() for s in b.sims]
+    b.close()
+    assert (st == 0).all()
+    for k, p in enumerate(probs):
+        s = Sim(p, batch_plan=True)
+        s.set_state(torch.from_numpy(m0s[k]))
+        rec, info = s.run(t_end=T, record_every=4, rec_cap=200)
+        m, t, a = s.get_state()
+        s.close()
+        _say("  inst", k, "accepted", infos[k]["accepted"], info["accepted"])
+        assert infos[k]["accepted"] == info["accepted"]
+        assert torch.equal(outs[k][0], m) and outs[k][2] == a
+        assert np.array_equal(recs[k], rec)
+
+
+def test_adjoint_refuses_map(torch):
+    from paper_2410_00966_amd.llgc import Sim, LLGCError
+    p = _problem(32, 8, 1)
+    s = Sim(p)
+    s.set_state(torch.from_numpy(I.tilted_uniform_state(p.shape, 5.0, 0.0,
+                                                        seed=1)))
+    with pytest.raises(LLGCError) as e:
+        s.adjoint(4, p.dt, 2, 4)
+    assert e.value.code == -7
+    s.close()
