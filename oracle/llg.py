@@ -75,7 +75,9 @@ def drive_shape(kind, w, t):
 
 
 def normalise(m):
-    return m / np.sqrt((m * m).sum(axis=0))
+    """m / |m| per cell; cells outside the geometry (m = 0) stay zero."""
+    n = np.sqrt((m * m).sum(axis=0))
+    return m / np.where(n > 0.0, n, 1.0)
 
 
 class CavityLLG:
@@ -89,6 +91,11 @@ class CavityLLG:
         self.p = prob
         self.shape = (prob.nz, prob.ny, prob.nx)
         self.ms = prob.ms_array()
+        # geometry: cells with Ms = 0 hold no magnetisation (m = 0 there);
+        # exchange ignores them and averages run over the magnetic cells
+        self.inside = self.ms > 0.0
+        self.inv_ms = np.where(self.inside, 1.0 / np.where(self.inside,
+                                                           self.ms, 1.0), 0.0)
         self.ku = prob.ku_array()
         self.vc = prob.dx * prob.dy * prob.dz
         self.u = np.asarray(prob.anis_u, dtype=np.float64)
@@ -127,26 +134,29 @@ class CavityLLG:
         return b.reshape(3, 1, 1, 1) * np.ones((1,) + self.shape)
 
     def exchange(self, m):
-        """B_ex,i = (2A/Ms_i) sum_neighbours (m_j - m_i)/d^2, open boundary."""
+        """B_ex,i = (2A/Ms_i) sum_neighbours (m_j - m_i)/d^2, open boundary:
+        neighbours outside the grid or outside the geometry are omitted."""
         p = self.p
         lap = np.zeros_like(m)
+        ins = self.inside[None]
         for axis, d in ((3, p.dx), (2, p.dy), (1, p.dz)):
             if m.shape[axis] < 2:
                 continue
-            diff = np.diff(m, axis=axis) / (d * d)
             lo = [slice(None)] * 4
             hi = [slice(None)] * 4
             lo[axis] = slice(0, -1)
             hi[axis] = slice(1, None)
+            pair = ins[tuple(lo)] & ins[tuple(hi)]
+            diff = np.where(pair, np.diff(m, axis=axis) / (d * d), 0.0)
             lap[tuple(lo)] += diff
             lap[tuple(hi)] -= diff
-        return 2.0 * p.aex / self.ms * lap
+        return 2.0 * p.aex * self.inv_ms * lap
 
     def anisotropy(self, m):
         """Uniaxial: B_a = (2 Ku/Ms) (u.m) u."""
         um = np.einsum("c,czyx->zyx", self.u, m)
-        return (2.0 * self.ku / self.ms * um)[None] * self.u.reshape(3, 1, 1,
-                                                                      1)
+        return (2.0 * self.ku * self.inv_ms * um)[None] * self.u.reshape(
+            3, 1, 1, 1)
 
     def demag(self, m):
         if self.demag_mode is None:
@@ -239,13 +249,13 @@ class CavityLLG:
 
     # ------------------------------------------------------------------ runs
     def record(self, t, m, a):
-        mm = m.reshape(3, -1).mean(axis=1)
+        mm = m[:, self.inside].mean(axis=1)
         return [t, mm[0], mm[1], mm[2], a.real, a.imag]
 
     def run_rk4(self, m0, a0, dt, nsteps, record_every=0, t0=0.0):
         """Fixed-step RK4.  Records (t, <m>, Re a, Im a) for the initial state
         and after every `record_every`-th step."""
-        m = np.asarray(m0, dtype=np.float64).copy()
+        m = np.asarray(m0, dtype=np.float64) * self.inside[None]
         a = complex(a0)
         t = t0
         rec = [self.record(t, m, a)] if record_every else []
@@ -274,7 +284,7 @@ class CavityLLG:
         p = self.p
         if p.cdrive_kind != DRIVE_NONE:
             raise ValueError("the memory form takes no cavity drive")
-        m = np.asarray(m0, dtype=np.float64).copy()
+        m = np.asarray(m0, dtype=np.float64) * self.inside[None]
         a0 = complex(a0)
         x0, p0 = 2.0 * a0.real, -2.0 * a0.imag
         vh = self.vc / p.hbar
@@ -309,7 +319,7 @@ class CavityLLG:
                  dt_min=1e-20, dt_max=1e-10, max_attempts=10 ** 7):
         """Adaptive Dormand-Prince from t0 to t_end (last step truncated to
         land on t_end).  Returns m, a, t, records, accepted dt list, stats."""
-        m = np.asarray(m0, dtype=np.float64).copy()
+        m = np.asarray(m0, dtype=np.float64) * self.inside[None]
         a = complex(a0)
         t = t0
         k1m, k1a = self.rhs(m, a, t)
@@ -353,7 +363,7 @@ class CavityLLG:
     def run_dp45_replay(self, m0, a0, dts, t0=0.0):
         """Dormand-Prince with a prescribed sequence of accepted step sizes
         (every step accepted, FSAL and renormalisation as in run_dp45)."""
-        m = np.asarray(m0, dtype=np.float64).copy()
+        m = np.asarray(m0, dtype=np.float64) * self.inside[None]
         a = complex(a0)
         t = t0
         k1m, k1a = self.rhs(m, a, t)
