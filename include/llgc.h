@@ -84,7 +84,12 @@ typedef struct {
  * 1.05457182e-34 J s and 4 pi 1e-7 T m/A. */
 typedef struct {
   double ms;               /* A/m, used when ms_map == NULL              */
-  const float *ms_map;
+  const float *ms_map;     /* A/m per cell (device, N float32, copied), or
+                              NULL.  Cells with 0 are outside the geometry:
+                              m = 0 there, exchange omits them as it omits
+                              cells beyond the grid, records average m over
+                              the magnetic cells.  Values must be finite and
+                              >= 0 with one magnetic cell at least. */
   double aex;              /* J/m, exchange stiffness                   */
   double alpha;            /* Gilbert damping                           */
   double ku1;              /* J/m^3, used when ku1_map == NULL          */

@@ -80,6 +80,8 @@ struct llgc_ctx {
   Ctl* ctl_eval = nullptr;
   float *ms_map = nullptr, *ku_map = nullptr;
   float* brms_map = nullptr;   // 3 N floats
+  bool masked = false;         // geometry: some cells have Ms = 0
+  double nmag = 0.0;           // magnetic cells
   size_t npartials = 0;
   // host state
   llgc_params prm{};
@@ -650,6 +652,8 @@ void fill_prm(llgc_ctx* c) {
   P.ms = (float)p.ms;
   P.ms_map = c->ms_map;
   P.brms_map = c->brms_map;
+  P.masked = c->masked ? 1 : 0;
+  P.nmag = c->nmag > 0 ? c->nmag : (double)c->N;
   P.aex2 = (float)(2.0 * p.aex);
   P.ku2 = (float)(2.0 * p.ku1);
   P.ku_map = c->ku_map;
@@ -1156,12 +1160,29 @@ int llgc_set_params(llgc_ctx* c, const llgc_params* p) {
   c->prm = *p;
   const size_t nb = sizeof(float) * c->N;
   if (p->ms_map) {
+    // geometry: cells with Ms = 0 are outside the magnet; values must be
+    // finite and >= 0 with at least one magnetic cell
+    std::vector<float> h(c->N);
+    HIPCHK(c, hipMemcpy(h.data(), p->ms_map, nb, hipMemcpyDeviceToHost));
+    int64_t nm = 0;
+    for (float v : h) {
+      if (!(v >= 0.f) || !std::isfinite(v))
+        return fail(c, LLGC_E_ARG, "ms_map values must be finite and >= 0");
+      nm += v > 0.f ? 1 : 0;
+    }
+    if (nm == 0) return fail(c, LLGC_E_ARG, "ms_map has no magnetic cell");
     if (!c->ms_map) HIPCHK(c, hipMalloc(&c->ms_map, nb));
     HIPCHK(c, hipMemcpyAsync(c->ms_map, p->ms_map, nb,
                              hipMemcpyDeviceToDevice, c->stream));
-  } else if (c->ms_map) {
-    HIPCHK(c, hipFree(c->ms_map));
-    c->ms_map = nullptr;
+    c->masked = nm < c->N;
+    c->nmag = (double)nm;
+  } else {
+    if (c->ms_map) {
+      HIPCHK(c, hipFree(c->ms_map));
+      c->ms_map = nullptr;
+    }
+    c->masked = false;
+    c->nmag = (double)c->N;
   }
   if (p->ku1_map) {
     if (!c->ku_map) HIPCHK(c, hipMalloc(&c->ku_map, nb));
@@ -1180,6 +1201,11 @@ int llgc_set_params(llgc_ctx* c, const llgc_params* p) {
     c->brms_map = nullptr;
   }
   fill_prm(c);
+  if (c->have_state && c->masked) {
+    hipLaunchKernelGGL(k_clear_empty<kT>, dim3(n_pointwise_blocks(c)),
+                       dim3(kT), 0, c->stream, c->P, c->yn);
+    if (int r = check_launch(c, "k_clear_empty")) return r;
+  }
   const double mu0 = p->mu0 > 0 ? p->mu0 : 4e-7 * M_PI;
   if (p->enable_demag && (!c->kernel_built || c->kernel_mu0 != mu0)) {
     if (int r = build_demag_kernel(c, mu0)) return r;
@@ -1206,6 +1232,11 @@ int llgc_set_state(llgc_ctx* c, const float* m, double t, double are,
   if (!m) return fail(c, LLGC_E_ARG, "m is NULL");
   HIPCHK(c, hipMemcpyAsync(c->yn, m, sizeof(float) * 3 * c->N,
                            hipMemcpyDeviceToDevice, c->stream));
+  if (c->have_params && c->masked) {   // no magnetisation outside
+    hipLaunchKernelGGL(k_clear_empty<kT>, dim3(n_pointwise_blocks(c)),
+                       dim3(kT), 0, c->stream, c->P, c->yn);
+    if (int r = check_launch(c, "k_clear_empty")) return r;
+  }
   Ctl h{};
   if (int r = ctl_read(c, &h, c->ctl)) return r;
   h.t = t;
@@ -1630,6 +1661,8 @@ extern "C" int llgc_adjoint(llgc_ctx* c, int64_t n_steps, double dt,
     return fail(c, LLGC_E_UNSUPPORTED, "adjoint of the cavity ODE form only");
   if (c->brms_map)
     return fail(c, LLGC_E_UNSUPPORTED, "adjoint with a uniform B_rms only");
+  if (c->masked)
+    return fail(c, LLGC_E_UNSUPPORTED, "adjoint without empty cells only");
   if (stride <= 0) stride = (int64_t)std::ceil(std::sqrt((double)n_steps));
   const int64_t S = stride;
   const int64_t nseg = (n_steps + S - 1) / S;

@@ -41,6 +41,8 @@ struct Prm {
   float idx2, idy2, idz2;       // 1/d^2 per axis
   float ms;                     // uniform Ms (A/m) when ms_map == nullptr
   const float* ms_map;
+  int masked;                   // ms_map has cells with Ms = 0 (geometry)
+  double nmag;                  // magnetic cells (averages)
   float aex2;                   // 2 A
   float ku2;                    // 2 Ku (J/m^3) when ku_map == nullptr
   const float* ku_map;

@@ -495,6 +495,21 @@ __global__ __launch_bounds__(T) void k_xfwd3(
   xfwd3_body<T>(P, ys, spec, partials, R, tw, logTw, tile, tile, lds_all);
 }
 
+// =========================================================== k_clear_empty
+// m = 0 in the cells outside the geometry (Ms = 0).
+template <int T>
+__global__ __launch_bounds__(T) void k_clear_empty(Prm P,
+                                                   float* __restrict__ m) {
+  const int N = P.ncell;
+  for (int i = blockIdx.x * T + threadIdx.x; i < N; i += gridDim.x * T) {
+    if (!(P.ms_map[i] > 0.f)) {
+      m[i] = 0.f;
+      m[N + i] = 0.f;
+      m[2 * N + i] = 0.f;
+    }
+  }
+}
+
 // ========================================================== k_coupling_map
 // Partial coupling sums sum Ms_i m_i . B_rms,i over the cells of one x-pass
 // tile (rows y0 .. y0+R-1 of layer z) with the per-cell B_rms map, written
@@ -1157,12 +1172,15 @@ __device__ __forceinline__ void field_cells(const Prm& P,
     if (msv > 0.f) {
       // exchange: (2A/Ms) sum over existing neighbours (m_j - m_i)/d^2
       float lx = 0.f, ly = 0.f, lz = 0.f;
-      if (x > 0) { lx += (ys[i - 1] - mx) * P.idx2; ly += (ys[N + i - 1] - my) * P.idx2; lz += (ys[2 * N + i - 1] - mz) * P.idx2; }
-      if (x < nx - 1) { lx += (ys[i + 1] - mx) * P.idx2; ly += (ys[N + i + 1] - my) * P.idx2; lz += (ys[2 * N + i + 1] - mz) * P.idx2; }
-      if (y > 0) { lx += (ys[i - nx] - mx) * P.idy2; ly += (ys[N + i - nx] - my) * P.idy2; lz += (ys[2 * N + i - nx] - mz) * P.idy2; }
-      if (y < ny - 1) { lx += (ys[i + nx] - mx) * P.idy2; ly += (ys[N + i + nx] - my) * P.idy2; lz += (ys[2 * N + i + nx] - mz) * P.idy2; }
-      if (z > 0) { lx += (ys[i - plane] - mx) * P.idz2; ly += (ys[N + i - plane] - my) * P.idz2; lz += (ys[2 * N + i - plane] - mz) * P.idz2; }
-      if (z < nz - 1) { lx += (ys[i + plane] - mx) * P.idz2; ly += (ys[N + i + plane] - my) * P.idz2; lz += (ys[2 * N + i + plane] - mz) * P.idz2; }
+      // neighbours outside the geometry (Ms = 0) are omitted like those
+      // outside the grid
+      const float* g = P.masked ? P.ms_map : nullptr;
+      if (x > 0 && (!g || g[i - 1] > 0.f)) { lx += (ys[i - 1] - mx) * P.idx2; ly += (ys[N + i - 1] - my) * P.idx2; lz += (ys[2 * N + i - 1] - mz) * P.idx2; }
+      if (x < nx - 1 && (!g || g[i + 1] > 0.f)) { lx += (ys[i + 1] - mx) * P.idx2; ly += (ys[N + i + 1] - my) * P.idx2; lz += (ys[2 * N + i + 1] - mz) * P.idx2; }
+      if (y > 0 && (!g || g[i - nx] > 0.f)) { lx += (ys[i - nx] - mx) * P.idy2; ly += (ys[N + i - nx] - my) * P.idy2; lz += (ys[2 * N + i - nx] - mz) * P.idy2; }
+      if (y < ny - 1 && (!g || g[i + nx] > 0.f)) { lx += (ys[i + nx] - mx) * P.idy2; ly += (ys[N + i + nx] - my) * P.idy2; lz += (ys[2 * N + i + nx] - mz) * P.idy2; }
+      if (z > 0 && (!g || g[i - plane] > 0.f)) { lx += (ys[i - plane] - mx) * P.idz2; ly += (ys[N + i - plane] - my) * P.idz2; lz += (ys[2 * N + i - plane] - mz) * P.idz2; }
+      if (z < nz - 1 && (!g || g[i + plane] > 0.f)) { lx += (ys[i + plane] - mx) * P.idz2; ly += (ys[N + i + plane] - my) * P.idz2; lz += (ys[2 * N + i + plane] - mz) * P.idz2; }
       const float ce = P.aex2 / msv;
       Bx += ce * lx; By += ce * ly; Bz += ce * lz;
       // uniaxial anisotropy (2 Ku / Ms) (u.m) u
@@ -1201,7 +1219,7 @@ __device__ __forceinline__ void field_cells(const Prm& P,
     if (E.kind == 2) {
       const float nrm = sqrtf(nxv * nxv + nyv * nyv + nzv * nzv);
       if (E.nout) E.nout[i] = nrm;
-      const float inv = 1.f / nrm;
+      const float inv = nrm > 0.f ? 1.f / nrm : 0.f;   // empty cells stay 0
       nxv *= inv; nyv *= inv; nzv *= inv;
       acc[0] += nxv; acc[1] += nyv; acc[2] += nzv;
     }
@@ -1433,9 +1451,9 @@ __device__ __forceinline__ void finish_step_body(
         c->nrec < c->rec_cap) {
       double* row = rec + 6 * (size_t)c->nrec;
       row[0] = c->t;
-      row[1] = s0 / N;
-      row[2] = s1 / N;
-      row[3] = s2 / N;
+      row[1] = s0 / P.nmag;
+      row[2] = s1 / P.nmag;
+      row[3] = s2 / P.nmag;
       row[4] = c->a_re;
       row[5] = c->a_im;
       c->nrec += 1;
@@ -1535,7 +1553,8 @@ __device__ __forceinline__ void begin_body(
       float* mx = &m[0].x; float* my = &m[1].x; float* mz = &m[2].x;
 #pragma unroll
       for (int l = 0; l < 4; ++l) {
-        const float inv = 1.f / sqrtf(mx[l] * mx[l] + my[l] * my[l] + mz[l] * mz[l]);
+        const float n2 = mx[l] * mx[l] + my[l] * my[l] + mz[l] * mz[l];
+        const float inv = n2 > 0.f ? 1.f / sqrtf(n2) : 0.f;
         mx[l] *= inv; my[l] *= inv; mz[l] *= inv;
         acc[0] += mx[l]; acc[1] += my[l]; acc[2] += mz[l];
       }
@@ -1559,7 +1578,8 @@ __device__ __forceinline__ void begin_body(
     float mx, my, mz, kx, ky, kz;
     if (pend) {
       mx = y7[i]; my = y7[N + i]; mz = y7[2 * N + i];
-      const float inv = 1.f / sqrtf(mx * mx + my * my + mz * mz);
+      const float n2 = mx * mx + my * my + mz * mz;
+      const float inv = n2 > 0.f ? 1.f / sqrtf(n2) : 0.f;
       mx *= inv; my *= inv; mz *= inv;
       yn[i] = mx; yn[N + i] = my; yn[2 * N + i] = mz;
       kx = k7[i]; ky = k7[N + i]; kz = k7[2 * N + i];
@@ -1599,9 +1619,9 @@ __device__ __forceinline__ void begin_body(
   {
     double* row = rec + 6 * (size_t)ctl->nrec;
     row[0] = ctl->t;
-    row[1] = S[0] / N;
-    row[2] = S[1] / N;
-    row[3] = S[2] / N;
+    row[1] = S[0] / P.nmag;
+    row[2] = S[1] / P.nmag;
+    row[3] = S[2] / P.nmag;
     row[4] = ctl->a_re;
     row[5] = ctl->a_im;
     ctl->nrec += 1;
@@ -1648,9 +1668,9 @@ __global__ __launch_bounds__(T) void k_record(
   if (ctl->nrec < ctl->rec_cap) {
     double* row = rec + 6 * (size_t)ctl->nrec;
     row[0] = ctl->t;
-    row[1] = S[0] / N;
-    row[2] = S[1] / N;
-    row[3] = S[2] / N;
+    row[1] = S[0] / P.nmag;
+    row[2] = S[1] / P.nmag;
+    row[3] = S[2] / P.nmag;
     row[4] = ctl->a_re;
     row[5] = ctl->a_im;
     ctl->nrec += 1;
