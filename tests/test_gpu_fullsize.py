@@ -3,7 +3,9 @@ compute in seconds:
   * one right-hand-side evaluation (dm/dt per cell, B_eff per cell, d alpha
     / dt) of the nanowire 512x32x4, the mapped film 256x256x2 and the
     textured film 1024x1024x2, from their initial states with a non-zero
-    cavity amplitude, in the launch configuration the benchmark uses;
+    cavity amplitude, in the launch configuration the benchmark uses, and
+    of a grid at the largest padded lengths (521x519x4: ragged, 2048-point
+    transforms, four layers);
   * the first accepted Dormand-Prince step of the textured film: the GPU's
     step size replayed in the oracle, final state per cell.
 Tolerances as the small-grid parity tests: 2e-5 of the largest magnitude for
@@ -43,8 +45,24 @@ def _oracle(name, p):
     return _ORACLES[name]
 
 
+def _largest_ragged():
+    """The largest padded transforms the library accepts (2048 points along
+    x and y) with ragged sides (521 x 519 cells: odd rows, partial tiles)
+    and the most layers (nz = 4: the ky-parity split spectral pass),
+    textured like the film.  (The full 1023 x 1021 x 4 grid runs the same
+    kernels; its FP64 tensor takes minutes to form.)"""
+    p = I.Problem(nx=521, ny=519, nz=4, dx=4e-9, dy=4e-9, dz=4e-9,
+                  ms=8.0e5, aex=1.3e-11, alpha=0.02, ku1=1e4,
+                  anis_u=(0.0, 0.6, 0.8), bext=(0.02, 0.0, 0.01))
+    p.wc = 2.0 * 3.141592653589793 * 4.0e9
+    p.kappa = 1e-3 * p.wc
+    p.brms = (1e-4, 2e-4, 0.0)
+    m0 = I.film_texture(p.nx, p.ny, p.nz, p.dx, p.dy, 48, 10e-9, seed=1007)
+    return p, m0
+
+
 WORKLOADS = {"nanowire": I.c2_nanowire, "mapped_film": I.c5_adjoint,
-             "textured_film": I.c3_film}
+             "textured_film": I.c3_film, "largest_ragged": _largest_ragged}
 
 
 @pytest.mark.parametrize("name", list(WORKLOADS))
