@@ -153,10 +153,12 @@ class CavityLLG:
         return 2.0 * p.aex * self.inv_ms * lap
 
     def anisotropy(self, m):
-        """Uniaxial: B_a = (2 Ku/Ms) (u.m) u."""
+        """Uniaxial, first and second order (energy density
+        -Ku1 (u.m)^2 - Ku2 (u.m)^4): B_a = (2 Ku1 (u.m) + 4 Ku2 (u.m)^3)/Ms u."""
         um = np.einsum("c,czyx->zyx", self.u, m)
-        return (2.0 * self.ku * self.inv_ms * um)[None] * self.u.reshape(
-            3, 1, 1, 1)
+        ku2 = getattr(self.p, "ku2", 0.0)
+        return ((2.0 * self.ku * um + 4.0 * ku2 * um ** 3)
+                * self.inv_ms)[None] * self.u.reshape(3, 1, 1, 1)
 
     def demag(self, m):
         if self.demag_mode is None:
@@ -180,10 +182,14 @@ class CavityLLG:
 
     # -------------------------------------------------------------- dynamics
     def torque(self, m, B):
+        """LL torque; with precession switched off only the damping term
+        (relaxation dynamics)."""
         p = self.p
         mxB = np.cross(m, B, axis=0)
         mxmxB = np.cross(m, mxB, axis=0)
-        return -p.gamma / (1.0 + p.alpha ** 2) * (mxB + p.alpha * mxmxB)
+        prec = 1.0 if getattr(p, "precession", 1) else 0.0
+        return -p.gamma / (1.0 + p.alpha ** 2) * (prec * mxB
+                                                  + p.alpha * mxmxB)
 
     def cavity_rate(self, a, F, t):
         p = self.p
@@ -208,7 +214,8 @@ class CavityLLG:
             if m.shape[axis] >= 2:
                 ex += vc * p.aex * (np.diff(m, axis=axis) ** 2).sum() / (d * d)
         um = np.einsum("c,czyx->zyx", self.u, m)
-        ea = -vc * (self.ku * um * um).sum()
+        ea = -vc * (self.ku * um * um).sum() - vc * (
+            getattr(p, "ku2", 0.0) * (self.inside * um ** 4)).sum()
         ed = -0.5 * vc * (self.ms * (m * self.demag(m)).sum(axis=0)).sum()
         ec = -vc * 2.0 * a.real * self.coupling_sum(m) + \
             p.hbar * p.wc * abs(a) ** 2

@@ -69,6 +69,10 @@ class Problem:
     # cavity treatment: CAVITY_ODE (alpha integrated with m) or
     # CAVITY_MEMORY (the paper's integrated-out recursion; RK4 only)
     cavity_mode: int = 0
+    # second-order uniaxial anisotropy (J/m^3, same axis as ku1) and the
+    # precession switch (0: damping term only, relaxation dynamics)
+    ku2: float = 0.0
+    precession: int = 1
     # optional per-cell maps, float32 arrays of shape (nz, ny, nx)
     ms_map: Optional[np.ndarray] = None
     ku1_map: Optional[np.ndarray] = None
