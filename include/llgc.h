@@ -116,6 +116,13 @@ typedef struct {
                               NULL for the uniform brms.  Section "Workflow
                               in Mumax3-cQED": B_rms may vary in space.
                               Not with llgc_adjoint. */
+  double ku2;              /* J/m^3, second-order uniaxial anisotropy on
+                              anis_u: energy density -Ku2 (u.m)^4, field
+                              (4 Ku2/Ms)(u.m)^3 u.  Not with llgc_adjoint. */
+  int32_t no_precession;   /* 1: torque -gamma alpha/(1+alpha^2) m x (m x B)
+                              only (relaxation dynamics, as Mumax3's
+                              relax); 0: full LL torque.  Not with
+                              llgc_adjoint. */
 } llgc_params;
 
 typedef struct {

@@ -679,6 +679,8 @@ void fill_prm(llgc_ctx* c) {
   P.alpha = (float)p.alpha;
   P.method = p.method;
   P.cmode = p.cavity_mode;
+  P.ku4 = (float)(4.0 * p.ku2);
+  P.prec = p.no_precession ? 0.f : 1.f;
   P.tol = p.tol;
   P.dt_min = p.dt_min > 0 ? p.dt_min : 1e-20;
   P.dt_max = p.dt_max > 0 ? p.dt_max : 1e-10;
@@ -1663,6 +1665,9 @@ extern "C" int llgc_adjoint(llgc_ctx* c, int64_t n_steps, double dt,
     return fail(c, LLGC_E_UNSUPPORTED, "adjoint with a uniform B_rms only");
   if (c->masked)
     return fail(c, LLGC_E_UNSUPPORTED, "adjoint without empty cells only");
+  if (c->prm.ku2 != 0.0 || c->prm.no_precession)
+    return fail(c, LLGC_E_UNSUPPORTED,
+                "adjoint without Ku2 and with precession only");
   if (stride <= 0) stride = (int64_t)std::ceil(std::sqrt((double)n_steps));
   const int64_t S = stride;
   const int64_t nseg = (n_steps + S - 1) / S;

@@ -59,6 +59,8 @@ struct Prm {
   int ckind;
   double camp, cw;
   float gpref;                  // -gamma / (1 + alpha^2)
+  float ku4;                    // 4 Ku2 (J/m^3)
+  float prec;                   // 1: precession term on, 0: off
   float alpha;
   int method;                   // 0 RK4, 1 DP45
   int cmode;                    // 0 cavity ODE, 1 memory recursion

@@ -1185,7 +1185,8 @@ __device__ __forceinline__ void field_cells(const Prm& P,
       Bx += ce * lx; By += ce * ly; Bz += ce * lz;
       // uniaxial anisotropy (2 Ku / Ms) (u.m) u
       const float kuv = P.ku_map ? 2.f * P.ku_map[i] : P.ku2;
-      const float ca = kuv / msv * (P.ux * mx + P.uy * my + P.uz * mz);
+      const float um = P.ux * mx + P.uy * my + P.uz * mz;
+      const float ca = (kuv * um + P.ku4 * um * um * um) / msv;
       Bx += ca * P.ux; By += ca * P.uy; Bz += ca * P.uz;
     }
     // LL torque: -gamma/(1+a^2) [ m x B + a m x (m x B) ]
@@ -1195,9 +1196,9 @@ __device__ __forceinline__ void field_cells(const Prm& P,
     const float qx = my * pz - mz * py;
     const float qy = mz * px - mx * pz;
     const float qz = mx * py - my * px;
-    const float kx = P.gpref * (px + P.alpha * qx);
-    const float ky = P.gpref * (py + P.alpha * qy);
-    const float kz = P.gpref * (pz + P.alpha * qz);
+    const float kx = P.gpref * (P.prec * px + P.alpha * qx);
+    const float ky = P.gpref * (P.prec * py + P.alpha * qy);
+    const float kz = P.gpref * (P.prec * pz + P.alpha * qz);
     if (E.kout) { E.kout[i] = kx; E.kout[N + i] = ky; E.kout[2 * N + i] = kz; }
     if (E.bout) { E.bout[i] = Bx; E.bout[N + i] = By; E.bout[2 * N + i] = Bz; }
     if (E.kind == 0) continue;

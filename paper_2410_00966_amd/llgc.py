@@ -62,7 +62,8 @@ class Params(ctypes.Structure):
         ("method", ctypes.c_int32), ("dt", ctypes.c_double),
         ("tol", ctypes.c_double), ("dt_min", ctypes.c_double),
         ("dt_max", ctypes.c_double), ("cavity_mode", ctypes.c_int32),
-        ("brms_map", _FP),
+        ("brms_map", _FP), ("ku2", ctypes.c_double),
+        ("no_precession", ctypes.c_int32),
     ]
 
 
@@ -163,6 +164,8 @@ def make_params(prob, ms_map=None, ku_map=None, brms_map=None) -> Params:
     p.method = prob.method
     p.cavity_mode = getattr(prob, "cavity_mode", 0)
     p.brms_map = brms_map.data_ptr() if brms_map is not None else None
+    p.ku2 = getattr(prob, "ku2", 0.0)
+    p.no_precession = 0 if getattr(prob, "precession", 1) else 1
     p.dt, p.tol = prob.dt, prob.tol
     p.dt_min, p.dt_max = prob.dt_min, prob.dt_max
     return p
