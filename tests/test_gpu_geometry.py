@@ -129,3 +129,30 @@ def test_geometry_argument_checks(torch):
         s.adjoint(4, p.dt, 2, 4)
     assert e.value.code == -7
     s.close()
+
+
+def test_disc_dp45_matches_oracle_adaptive_run(torch):
+    """Adaptive run on the disc with a per-cell B_rms: the same tolerance
+    lands both on t_end with close step counts and per-cell agreement."""
+    from oracle.llg import CavityLLG
+    from paper_2410_00966_amd.llgc import Sim
+    p, m0 = _disc(32)
+    p.method, p.tol, p.dt = I.METHOD_DP45, 1e-6, 1e-14
+    b = np.zeros((3,) + p.shape, np.float32)
+    b[0] = np.asarray(p.brms[0]) * (np.asarray(p.ms_map) > 0)
+    p.brms_map = b
+    T = 15e-12
+    s = Sim(p)
+    s.set_state(torch.from_numpy(m0))
+    _, info = s.run(t_end=T)
+    m, t, a = s.get_state()
+    s.close()
+    mref, aref, tref, _, _, st = CavityLLG(p).run_dp45(
+        m0.astype(np.float64), 0j, T, p.tol, p.dt)
+    dm = np.abs(m.cpu().numpy() - mref).max()
+    _say("disc dp45 accepted", info["accepted"], st["accepted"], "max|dm|",
+         dm, "a", a, aref)
+    assert t == pytest.approx(T, rel=1e-12)
+    assert dm < 1e-4
+    assert abs(info["accepted"] - st["accepted"]) <= max(2, st["accepted"] // 50)
+    assert np.abs(m.cpu().numpy()[:, np.asarray(p.ms_map) == 0]).max() == 0

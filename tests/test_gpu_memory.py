@@ -113,3 +113,28 @@ def test_memory_form_refusals(torch):
         s.adjoint(10, p.dt, 5, 10)
     assert e.value.code == -7
     s.close()
+
+
+def test_memory_form_in_a_batch_equals_standalone(torch):
+    from paper_2410_00966_amd.llgc import Batch, Sim
+    probs, m0s = [], []
+    for k, sh in enumerate([(20, 16, 2), (33, 17, 1), (24, 40, 3)]):
+        p, m0 = _film(*sh)
+        p.kappa = (0.01 + 0.01 * k) * p.wc
+        probs.append(p)
+        m0s.append(m0)
+    b = Batch(probs)
+    for s, m0 in zip(b.sims, m0s):
+        s.set_state(torch.from_numpy(m0), 0.0, 0.1 + 0.0j)
+    recs, infos, st = b.run(nsteps=90, record_every=9, rec_cap=16)
+    outs = [s.get_state() for s in b.sims]
+    b.close()
+    assert (st == 0).all()
+    for k, p in enumerate(probs):
+        s = Sim(p, batch_plan=True)
+        s.set_state(torch.from_numpy(m0s[k]), 0.0, 0.1 + 0.0j)
+        rec, _ = s.run(nsteps=90, record_every=9, rec_cap=16)
+        m, t, a = s.get_state()
+        s.close()
+        assert torch.equal(outs[k][0], m) and outs[k][2] == a
+        assert np.array_equal(recs[k], rec)
