@@ -681,6 +681,8 @@ void fill_prm(llgc_ctx* c) {
   P.cmode = p.cavity_mode;
   P.ku4 = (float)(4.0 * p.ku2);
   P.prec = p.no_precession ? 0.f : 1.f;
+  P.plain = (!c->masked && !c->brms_map && p.ku2 == 0.0 &&
+             !p.no_precession) ? 1 : 0;
   P.tol = p.tol;
   P.dt_min = p.dt_min > 0 ? p.dt_min : 1e-20;
   P.dt_max = p.dt_max > 0 ? p.dt_max : 1e-10;

@@ -61,6 +61,7 @@ struct Prm {
   float gpref;                  // -gamma / (1 + alpha^2)
   float ku4;                    // 4 Ku2 (J/m^3)
   float prec;                   // 1: precession term on, 0: off
+  int plain;                    // none of: B_rms map, geometry, Ku2, no precession
   float alpha;
   int method;                   // 0 RK4, 1 DP45
   int cmode;                    // 0 cavity ODE, 1 memory recursion

@@ -1120,8 +1120,8 @@ __global__ __launch_bounds__(NR >= 32 ? 512 : 1024) void k_yspec_w(
 // tile (cells (x, y0 + r, z)), given B_demag through `bd(r, x)`; writes the
 // stage outputs and the workgroup's partial sums (RK4 final: <m> sums,
 // DP45 error stage: max error).  Any block size.
-template <class BD>
-__device__ __forceinline__ void field_cells(const Prm& P,
+template <bool GEN, class BD>
+__device__ __forceinline__ void field_cells_t(const Prm& P,
                                             const float* __restrict__ ys,
                                             const Ctl* __restrict__ ctl,
                                             double* __restrict__ partials,
@@ -1140,7 +1140,7 @@ __device__ __forceinline__ void field_cells(const Prm& P,
               bez = P.bz + fd * P.fdz;
   const float gcav = (float)(2.0 * ctl->as_re[stage]);
   const float bcx = P.brx * gcav, bcy = P.bry * gcav, bcz = P.brz * gcav;
-  const float* bmap = P.brms_map;
+  const float* bmap = GEN ? P.brms_map : nullptr;
   double acc[3] = {0.0, 0.0, 0.0};
   float emax = 0.f;
   const int ncellb = R * nx;
@@ -1174,7 +1174,7 @@ __device__ __forceinline__ void field_cells(const Prm& P,
       float lx = 0.f, ly = 0.f, lz = 0.f;
       // neighbours outside the geometry (Ms = 0) are omitted like those
       // outside the grid
-      const float* g = P.masked ? P.ms_map : nullptr;
+      const float* g = (GEN && P.masked) ? P.ms_map : nullptr;
       if (x > 0 && (!g || g[i - 1] > 0.f)) { lx += (ys[i - 1] - mx) * P.idx2; ly += (ys[N + i - 1] - my) * P.idx2; lz += (ys[2 * N + i - 1] - mz) * P.idx2; }
       if (x < nx - 1 && (!g || g[i + 1] > 0.f)) { lx += (ys[i + 1] - mx) * P.idx2; ly += (ys[N + i + 1] - my) * P.idx2; lz += (ys[2 * N + i + 1] - mz) * P.idx2; }
       if (y > 0 && (!g || g[i - nx] > 0.f)) { lx += (ys[i - nx] - mx) * P.idy2; ly += (ys[N + i - nx] - my) * P.idy2; lz += (ys[2 * N + i - nx] - mz) * P.idy2; }
@@ -1186,7 +1186,8 @@ __device__ __forceinline__ void field_cells(const Prm& P,
       // uniaxial anisotropy (2 Ku / Ms) (u.m) u
       const float kuv = P.ku_map ? 2.f * P.ku_map[i] : P.ku2;
       const float um = P.ux * mx + P.uy * my + P.uz * mz;
-      const float ca = (kuv * um + P.ku4 * um * um * um) / msv;
+      const float ca =
+          GEN ? (kuv * um + P.ku4 * um * um * um) / msv : (kuv * um) / msv;
       Bx += ca * P.ux; By += ca * P.uy; Bz += ca * P.uz;
     }
     // LL torque: -gamma/(1+a^2) [ m x B + a m x (m x B) ]
@@ -1196,9 +1197,10 @@ __device__ __forceinline__ void field_cells(const Prm& P,
     const float qx = my * pz - mz * py;
     const float qy = mz * px - mx * pz;
     const float qz = mx * py - my * px;
-    const float kx = P.gpref * (P.prec * px + P.alpha * qx);
-    const float ky = P.gpref * (P.prec * py + P.alpha * qy);
-    const float kz = P.gpref * (P.prec * pz + P.alpha * qz);
+    const float pf = GEN ? P.prec : 1.f;
+    const float kx = P.gpref * (pf * px + P.alpha * qx);
+    const float ky = P.gpref * (pf * py + P.alpha * qy);
+    const float kz = P.gpref * (pf * pz + P.alpha * qz);
     if (E.kout) { E.kout[i] = kx; E.kout[N + i] = ky; E.kout[2 * N + i] = kz; }
     if (E.bout) { E.bout[i] = Bx; E.bout[N + i] = By; E.bout[2 * N + i] = Bz; }
     if (E.kind == 0) continue;
@@ -1238,6 +1240,22 @@ __device__ __forceinline__ void field_cells(const Prm& P,
     emax = block_max(emax, redf);
     if (threadIdx.x == 0) partials[slot] = (double)emax;
   }
+}
+
+
+// The cell loop with the per-cell options (B_rms map, geometry, Ku2,
+// precession switch) compiled in only where a problem uses one of them.
+template <class BD>
+__device__ __forceinline__ void field_cells(const Prm& P,
+                                            const float* __restrict__ ys,
+                                            const Ctl* __restrict__ ctl,
+                                            double* __restrict__ partials,
+                                            int stage, int R, const Epi& E,
+                                            int z, int y0, BD bd, int slot) {
+  if (P.plain)
+    field_cells_t<false>(P, ys, ctl, partials, stage, R, E, z, y0, bd, slot);
+  else
+    field_cells_t<true>(P, ys, ctl, partials, stage, R, E, z, y0, bd, slot);
 }
 
 
