@@ -285,6 +285,9 @@ def c5_adjoint() -> tuple:
     p.brms = (0.0, brms_from_g(g, 8.0e5 * p.ncells * p.vcell), 0.0)
     p.cdrive_kind = DRIVE_CW
     p.cdrive_w = p.wc
+    # resonant CW drive: the free cavity settles at |alpha| = eps0/kappa; the
+    # amplitude gives it a field 2 |B_rms| |alpha| of 1 mT
+    p.cdrive_amp = 1e-3 * p.kappa / (2.0 * p.brms[1])
     m0 = tilted_uniform_state(p.shape, 0.0, 1e-3, seed=1005, axis="x",
                               toward="y")
     return p, m0, dict(steps=50000)

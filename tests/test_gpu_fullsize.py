@@ -107,3 +107,49 @@ def test_full_size_first_dp45_step_of_the_textured_film(torch):
          f"|da| {abs(a - aref):.2e}")
     assert dm < 1e-5
     assert abs(a - aref) < 1e-7 * max(1.0, abs(aref))
+
+
+def test_full_size_adjoint_properties(torch):
+    """The mapped film 256x256x2 (the adjoint workload, its launch
+    configuration), 2000 RK4 steps, loss over the last 400: the adjoint's
+    loss equals the photon number averaged from a plain run's records, and
+    its directional derivatives (Ms map along a smooth seeded direction,
+    drive amplitude) match central differences of the GPU loss (float32
+    state: 2% relative)."""
+    from paper_2410_00966_amd.llgc import Sim
+    p, m0, _ = I.c5_adjoint()
+    n, n0 = 2000, 1601
+    _say("full-size adjoint", p.shape, "steps", n)
+    s = Sim(p)
+    s.set_state(torch.from_numpy(m0))
+    g = s.adjoint(n, p.dt, n0, n)
+    s.set_params(p)
+    s.set_state(torch.from_numpy(m0))
+    rec, _ = s.run(nsteps=n, record_every=1)
+    a2 = rec[n0:n + 1, 4] ** 2 + rec[n0:n + 1, 5] ** 2
+    _say("  loss", g["loss"], "from records", a2.mean())
+    assert g["loss"] == pytest.approx(a2.mean(), rel=1e-9)
+
+    def loss(q):
+        s.set_params(q)
+        s.set_state(torch.from_numpy(m0))
+        return s.adjoint(n, p.dt, n0, n)["loss"]
+
+    d = I.smooth_map(p.nx, p.ny, p.nz, -1.0, 1.0, 4, 3, seed=9001)
+    d = d.astype(np.float64)
+    h = 2e-3 * 8e5
+    qp, qm = I.Problem(**{**p.__dict__}), I.Problem(**{**p.__dict__})
+    qp.ms_map = (np.asarray(p.ms_map, np.float64) + h * d).astype(np.float32)
+    qm.ms_map = (np.asarray(p.ms_map, np.float64) - h * d).astype(np.float32)
+    fd = (loss(qp) - loss(qm)) / (2 * h)
+    ad = float((g["g_ms"].cpu().numpy().astype(np.float64) * d).sum())
+    _say("  d/dMs along d: adjoint", ad, "fd", fd)
+    assert ad == pytest.approx(fd, rel=2e-2)
+    he = 1e-3 * p.cdrive_amp
+    qp, qm = I.Problem(**{**p.__dict__}), I.Problem(**{**p.__dict__})
+    qp.cdrive_amp += he
+    qm.cdrive_amp -= he
+    fe = (loss(qp) - loss(qm)) / (2 * he)
+    _say("  d/deps0: adjoint", g["g_eps0"], "fd", fe)
+    assert g["g_eps0"] == pytest.approx(fe, rel=2e-2)
+    s.close()
