@@ -222,9 +222,12 @@ int llgc_eval_rhs(llgc_ctx *ctx, const float *m_dev, double a_re,
  * is faster depends on the padded lengths, the layer count and how full the
  * GPU is.  With `reps` > 0, times every feasible combination on this
  * context's grid (two rounds of `reps` right-hand-side evaluations of the
- * current state, result discarded), keeps the fastest and records it for
- * the grid shape (nx, ny, nz, demag on/off) in a process-wide table; with
- * `reps` <= 0, applies the recorded choice for this shape if there is one
+ * current state, result discarded), keeps the fastest, then tries halving
+ * and doubling the rows per x-pass tile and the kx columns per spectral
+ * workgroup of that plan one at a time (kept when 2% faster, within the
+ * kernels' register and LDS limits), and records the plan for the grid
+ * shape (nx, ny, nz, demag on/off) in a process-wide table; with
+ * `reps` <= 0, applies the recorded plan for this shape if there is one
  * and otherwise keeps the current plan.  The integrator state is not
  * changed; results of later calls differ from the untuned plan's only by
  * float32 rounding.  `choice` (host, may be NULL) receives the plan kind:

@@ -844,7 +844,38 @@ int time_rhs(llgc_ctx* c, int reps, double* ms) {
 }
 
 // Tuned plan kinds per grid shape (process-wide).
-std::map<std::tuple<int, int, int, int>, int> g_tuned;
+// Plan shape: FFT kind plus rows per x-pass tile and kx columns per
+// spectral workgroup.
+struct PlanShape {
+  int kind, Rf, Ri, Rw, Rwf, W;
+};
+PlanShape plan_get(const llgc_ctx* c) {
+  return PlanShape{plan_kind(c), c->Rf, c->Ri, c->Rw, c->Rwf, c->W};
+}
+void plan_put(llgc_ctx* c, const PlanShape& s) {
+  plan_set_kind(c, s.kind);
+  c->Rf = s.Rf;
+  c->Ri = s.Ri;
+  c->Rw = s.Rw;
+  c->Rwf = s.Rwf;
+  c->W = s.W;
+  const int col = 3 * c->nz * c->Py;
+  c->Ty = 256;
+  while (c->Ty < kTyMax && c->W * col > VPTY * c->Ty) c->Ty *= 2;
+}
+// Register-budget limits of the LDS kernels' tiles (as at creation): rows
+// per forward / field tile, spectral column slots per workgroup.
+void plan_limits(const llgc_ctx* c, int* rf_max, int* ri_max, int* w_max) {
+  const int VPTT = VPT * kTX;
+  *rf_max = 2 * std::max(1, std::min(8, VPTT / c->Px));
+  *ri_max = 2 * std::max(1, std::min(8, VPTT / (3 * c->Px)));
+  const int col = 3 * c->nz * c->Py;
+  *w_max = std::max(1, std::min(VPTY * kTyMax / col,
+                                (int)(kLdsCap / (9 * col))));
+}
+
+// Tuned plan shapes per grid shape (process-wide).
+std::map<std::tuple<int, int, int, int>, PlanShape> g_tuned;
 std::mutex g_tuned_mu;
 
 // ------------------------------------------------------- launch sequences
@@ -1480,8 +1511,8 @@ int llgc_autotune(llgc_ctx* c, int32_t reps, int32_t* choice) {
   if (!c->have_params)
     return fail(c, LLGC_E_STATE, "set params before tuning");
   const auto key = std::make_tuple(c->nx, c->ny, c->nz, c->P.demag ? 1 : 0);
-  const int k0 = plan_kind(c);
-  int best = k0;
+  const PlanShape s0 = plan_get(c);
+  PlanShape best = s0;
   const bool timing = c->timing;
   c->timing = false;                     // keep tuning out of the timers
   struct Restore {
@@ -1489,41 +1520,104 @@ int llgc_autotune(llgc_ctx* c, int32_t reps, int32_t* choice) {
     bool t;
     ~Restore() { c->timing = t; }
   } restore{c, timing};
+  auto undo = [&](int r) {
+    plan_put(c, s0);
+    plan_derive(c);
+    return r;
+  };
   if (reps <= 0) {
     std::lock_guard<std::mutex> lock(g_tuned_mu);
     auto it = g_tuned.find(key);
     if (it != g_tuned.end()) best = it->second;
   } else {
-    // two rounds over the candidate kinds (the first also brings the clocks
-    // up); each kind keeps its faster round
+    // 1) FFT kind of each pass: two rounds over the candidate kinds with
+    // the default shapes (the first round also brings the clocks up); each
+    // kind keeps its faster round
     double tbest[8];
     for (double& v : tbest) v = 1e300;
     for (int round = 0; round < 2; ++round) {
       for (int k = 0; k < 8; ++k) {
         if (!plan_kind_ok(c, k)) continue;
-        plan_set_kind(c, k);
+        PlanShape sk = s0;
+        sk.kind = k;
+        plan_put(c, sk);
         if (plan_derive(c)) continue;             // does not fit this grid
         double ms = 0.0;
-        if (int r = time_rhs(c, reps, &ms)) {
-          plan_set_kind(c, k0);
-          plan_derive(c);
-          return r;
-        }
+        if (int r = time_rhs(c, reps, &ms)) return undo(r);
         tbest[k] = std::min(tbest[k], ms);
       }
     }
+    int kb = s0.kind;
     for (int k = 0; k < 8; ++k)
-      if (tbest[k] < tbest[best]) best = k;
+      if (tbest[k] < tbest[kb]) kb = k;
+    best.kind = kb;
+    // 2) tile shapes of the chosen kind, one parameter at a time: halve or
+    // double the rows of the passes in LDS (2, 4 for the register ones) and
+    // the spectral column slots; a change is kept when 2% faster
+    int rf_max, ri_max, w_max;
+    plan_limits(c, &rf_max, &ri_max, &w_max);
+    const int rcap = c->ny + (c->ny & 1);
+    double tcur = tbest[kb];
+    auto attempt = [&](PlanShape t) -> int {
+      plan_put(c, t);
+      if (plan_derive(c)) return LLGC_OK;
+      double ms = 0.0;
+      if (int r = time_rhs(c, reps, &ms)) return r;
+      if (ms < 0.98 * tcur) {
+        best = t;
+        tcur = ms;
+      }
+      return LLGC_OK;
+    };
+    auto rows = [&](int r, int rmax, int* out) {
+      int n = 0;
+      for (int v : {r / 2, 2 * r}) {
+        v &= ~1;
+        if (v >= 2 && v <= std::min(rmax, std::max(2, rcap)) && v != r)
+          out[n++] = v;
+      }
+      return n;
+    };
+    int cand[2];
+    const PlanShape base = best;
+    if (!(base.kind & 2)) {
+      for (int i = 0, n = rows(base.Rf, rf_max, cand); i < n; ++i) {
+        PlanShape t = best;
+        t.Rf = cand[i];
+        if (int r = attempt(t)) return undo(r);
+      }
+    } else if (sizeof(float2) * 3 * 2 * (size_t)c->Px <= 65536) {
+      // the register forward pass keeps 3 (R/2) rows in LDS: R = 4 only
+      // where that stays within the default 64 KB
+      PlanShape t = best;
+      t.Rwf = base.Rwf == 2 ? 4 : 2;
+      if (int r = attempt(t)) return undo(r);
+    }
+    if (!(base.kind & 4)) {
+      for (int i = 0, n = rows(base.Ri, ri_max, cand); i < n; ++i) {
+        PlanShape t = best;
+        t.Ri = cand[i];
+        if (int r = attempt(t)) return undo(r);
+      }
+    } else {
+      PlanShape t = best;
+      t.Rw = base.Rw == 2 ? 4 : 2;
+      if (int r = attempt(t)) return undo(r);
+    }
+    if (!(base.kind & 1)) {
+      for (int v : {base.W / 2, 2 * base.W}) {
+        if (v < 1 || v > w_max || v == base.W) continue;
+        PlanShape t = best;
+        t.W = v;
+        if (int r = attempt(t)) return undo(r);
+      }
+    }
     std::lock_guard<std::mutex> lock(g_tuned_mu);
     g_tuned[key] = best;
   }
-  plan_set_kind(c, best);
-  if (int r = plan_derive(c)) {
-    plan_set_kind(c, k0);
-    plan_derive(c);
-    return r;
-  }
-  if (choice) *choice = best;
+  plan_put(c, best);
+  if (int r = plan_derive(c)) return undo(r);
+  if (choice) *choice = best.kind;
   c->err.clear();
   return LLGC_OK;
 }
