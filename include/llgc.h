@@ -232,7 +232,8 @@ int llgc_eval_rhs(llgc_ctx *ctx, const float *m_dev, double a_re,
  * changed; results of later calls differ from the untuned plan's only by
  * float32 rounding.  `choice` (host, may be NULL) receives the plan kind:
  * bit 0 register y pass, bit 1 register forward x pass, bit 2 register
- * field x pass.  Not thread-safe against other calls on the same context.
+ * field x pass, bit 3 LDS x passes over the three components of a tile at
+ * once (padded x length >= 64).  Not thread-safe against other calls on the same context.
  * Errors: LLGC_E_ARG (NULL context, or a batch-plan instance, whose plan
  * is fixed), LLGC_E_STATE (no params), LLGC_E_HIP. */
 int llgc_autotune(llgc_ctx *ctx, int32_t reps, int32_t *choice);

@@ -59,6 +59,7 @@ struct llgc_ctx {
   bool use_wy = false;   // register (wavefront) FFT along y
   bool use_wxf = false;  // register (wavefront) FFT in the forward x pass
   bool use_wxi = false;  // register (wavefront) inverse FFT in the field pass
+  bool x3 = false;       // LDS x passes over the 3 components of a tile at once
   bool batch_plan = false;  // fixed plan shared with the batched engine
   bool yhalf = false;    // LDS spectral pass split by ky parity (k_yspec_h)
   int Tyh = 512;         // its workgroup size
@@ -200,7 +201,7 @@ int launch_xfwd(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
 #undef LLGC_FW_ARGS
     return check_launch(c, "k_xfwd_w");
   }
-  if (c->batch_plan) {
+  if (c->batch_plan || c->x3) {
     hipLaunchKernelGGL((k_xfwd3<kTX>), xgrid(c, c->Rf), dim3(kTX),
                        c->P.demag ? c->lds_f : 0, c->stream, c->P, ys,
                        c->spec, ctl, c->partials, c->Rf, c->tw, c->logTw);
@@ -373,7 +374,7 @@ int launch_xfield(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
 #undef LLGC_XW_ARGS
     return check_launch(c, "k_xfield_w");
   }
-  if (c->batch_plan) {
+  if (c->batch_plan || c->x3) {
     hipLaunchKernelGGL((k_xfield_b<kTX>), xgrid(c, c->Ri), dim3(kTX),
                        c->P.demag ? c->lds_i : 0, c->stream, c->P, ys,
                        c->spec, ctl, c->partials, c->rec, stage, c->Ri, E,
@@ -741,7 +742,7 @@ int plan_derive(llgc_ctx* c) {
   if (!c->use_wy && !c->yhalf && W * col > ycap)
     return fail(c, LLGC_E_UNSUPPORTED, "column set exceeds one workgroup");
   const size_t twb = sizeof(float2) * lds_twiddles(c->logTw);  // LDS twiddles
-  c->lds_f = twb + sizeof(float2) * padded_len((size_t)(c->batch_plan ? 3 : 1) *
+  c->lds_f = twb + sizeof(float2) * padded_len((size_t)((c->batch_plan || c->x3) ? 3 : 1) *
                                                 (c->Rf / 2) * c->Px);
   c->lds_i = sizeof(float2) * padded_len_s<6>((size_t)3 * (c->Ri / 2) * c->Px);
   // the spectral pass is specialised on 1024 and 2048 points (yspec_nz)
@@ -797,20 +798,33 @@ int plan_derive(llgc_ctx* c) {
 // A plan kind says which passes keep their FFT in registers: bit 0 the
 // spectral (y) pass, bit 1 the forward x pass, bit 2 the field x pass; rows
 // and columns per workgroup follow each kind as in the default plan.
+// Bit 3: both x passes in LDS over the three components of a tile at once
+// (the batch plan's x kernels; rows per tile sized to fill the workgroup).
 bool plan_kind_ok(const llgc_ctx* c, int k) {
   if ((k & 1) && !(c->Py >= 64 && c->Py <= 2048 &&
                    (c->Py < 2048 || c->nz <= 2)))
     return false;
   if ((k & 6) && !(c->Px >= 64 && c->Px <= 2048)) return false;
+  if ((k & 8) && ((k & 6) || c->Px < 64)) return false;
   return true;
 }
 int plan_kind(const llgc_ctx* c) {
-  return (c->use_wy ? 1 : 0) | (c->use_wxf ? 2 : 0) | (c->use_wxi ? 4 : 0);
+  return (c->use_wy ? 1 : 0) | (c->use_wxf ? 2 : 0) | (c->use_wxi ? 4 : 0) |
+         (c->x3 ? 8 : 0);
 }
 void plan_set_kind(llgc_ctx* c, int k) {
   c->use_wy = (k & 1) != 0;
   c->use_wxf = (k & 2) != 0;
   c->use_wxi = (k & 4) != 0;
+  c->x3 = (k & 8) != 0;
+}
+// Rows per tile of the three-component x passes: 3 (R/2) Px fills
+// VPT * kTX complex values, tiles splitting ny evenly.
+int x3_rows(const llgc_ctx* c) {
+  const int npmax = std::max(1, VPT * kTX / (3 * c->Px));
+  const int pairs = (c->ny + 1) / 2;
+  const int nty = (pairs + npmax - 1) / npmax;
+  return 2 * ((pairs + nty - 1) / nty);
 }
 
 // Mean milliseconds of one right-hand-side evaluation (forward x pass,
@@ -869,6 +883,7 @@ void plan_limits(const llgc_ctx* c, int* rf_max, int* ri_max, int* w_max) {
   const int VPTT = VPT * kTX;
   *rf_max = 2 * std::max(1, std::min(8, VPTT / c->Px));
   *ri_max = 2 * std::max(1, std::min(8, VPTT / (3 * c->Px)));
+  if (c->x3) *rf_max = *ri_max = 2 * std::max(1, VPTT / (3 * c->Px));
   const int col = 3 * c->nz * c->Py;
   *w_max = std::max(1, std::min(VPTY * kTyMax / col,
                                 (int)(kLdsCap / (9 * col))));
@@ -1065,6 +1080,12 @@ int llgc_create_ex(const llgc_grid* g, void* stream, int flags,
   if (const char* s = getenv("LLGC_RW")) c->Rw = (atoi(s) >= 4) ? 4 : 2;
   c->Rwf = 2;
   if (const char* s = getenv("LLGC_RWF")) c->Rwf = (atoi(s) >= 4) ? 4 : 2;
+  if (!bplan && c->Px >= 64 && getenv("LLGC_X3")) {
+    // the three-component x passes (plan kind bit 3)
+    c->use_wxf = c->use_wxi = false;
+    c->x3 = true;
+    c->Rf = c->Ri = x3_rows(c);
+  }
   if (bplan) {
     // the fixed plan of every batched instance (no tuning overrides):
     // register FFTs along x, the LDS spectral pass with kBatchTy threads
@@ -1533,13 +1554,17 @@ int llgc_autotune(llgc_ctx* c, int32_t reps, int32_t* choice) {
     // 1) FFT kind of each pass: two rounds over the candidate kinds with
     // the default shapes (the first round also brings the clocks up); each
     // kind keeps its faster round
-    double tbest[8];
+    double tbest[16];
     for (double& v : tbest) v = 1e300;
     for (int round = 0; round < 2; ++round) {
-      for (int k = 0; k < 8; ++k) {
+      for (int k = 0; k < 16; ++k) {
         if (!plan_kind_ok(c, k)) continue;
         PlanShape sk = s0;
         sk.kind = k;
+        if ((k & 8) && !(s0.kind & 8)) {
+          plan_set_kind(c, k);
+          sk.Rf = sk.Ri = x3_rows(c);
+        }
         plan_put(c, sk);
         if (plan_derive(c)) continue;             // does not fit this grid
         double ms = 0.0;
@@ -1548,13 +1573,18 @@ int llgc_autotune(llgc_ctx* c, int32_t reps, int32_t* choice) {
       }
     }
     int kb = s0.kind;
-    for (int k = 0; k < 8; ++k)
+    for (int k = 0; k < 16; ++k)
       if (tbest[k] < tbest[kb]) kb = k;
     best.kind = kb;
+    if ((kb & 8) && !(s0.kind & 8)) {
+      plan_set_kind(c, kb);
+      best.Rf = best.Ri = x3_rows(c);
+    }
     // 2) tile shapes of the chosen kind, one parameter at a time: halve or
     // double the rows of the passes in LDS (2, 4 for the register ones) and
     // the spectral column slots; a change is kept when 2% faster
     int rf_max, ri_max, w_max;
+    plan_put(c, best);
     plan_limits(c, &rf_max, &ri_max, &w_max);
     const int rcap = c->ny + (c->ny & 1);
     double tcur = tbest[kb];

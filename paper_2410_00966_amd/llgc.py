@@ -333,7 +333,8 @@ class Sim:
         """Times the register/LDS FFT plan kinds on this grid and keeps the
         fastest (reps <= 0: reuse the kind recorded for this grid shape).
         Returns the kind: bit 0 register y pass, bit 1 register forward x
-        pass, bit 2 register field x pass."""
+        pass, bit 2 register field x pass, bit 3 three-component LDS x
+        passes."""
         k = ctypes.c_int32(-1)
         self._check(self.L.llgc_autotune(self.h, int(reps), ctypes.byref(k)),
                     "llgc_autotune")

@@ -62,7 +62,7 @@ def test_tuned_plan_meets_oracle(torch, grid):
     s.set_state(torch.from_numpy(m))
     kind = s.autotune(reps=5)
     _say("grid", grid, "tuned kind", kind)
-    assert 0 <= kind < 8
+    assert 0 <= kind < 16
     o = CavityLLG(p)
     a, t = 0.3 - 0.1j, 1e-12
     dm_ref, da_ref = o.rhs(m.astype(np.float64), a, t)
@@ -95,4 +95,37 @@ def test_batch_plan_refuses_tuning(torch):
     with pytest.raises(LLGCError) as e:
         s.autotune(reps=3)
     assert e.value.code == -1
+    s.close()
+
+
+@pytest.mark.parametrize("grid", [(41, 33, 2), (101, 70, 1), (301, 40, 4)])
+def test_three_component_x_passes_meet_oracle(torch, grid):
+    """Plan kind bit 3 forced at creation (LLGC_X3): RHS and an RK4 run
+    against the oracle.  (Shapes no other test tunes: autotune(reps=0)
+    would apply a recorded plan.)"""
+    import os
+    from oracle.llg import CavityLLG
+    from paper_2410_00966_amd.llgc import Sim
+    p = _problem(*grid)
+    os.environ["LLGC_X3"] = "1"
+    try:
+        s = Sim(p)
+    finally:
+        os.environ.pop("LLGC_X3", None)
+    assert s.autotune(reps=0) & 8
+    m = _random_m(p.shape, seed=sum(grid) + 1)
+    o = CavityLLG(p)
+    a, t = 0.3 - 0.1j, 1e-12
+    dm_ref, da_ref = o.rhs(m.astype(np.float64), a, t)
+    dm, _, da = s.eval_rhs(torch.from_numpy(m), a, t)
+    err = np.abs(dm.cpu().numpy() - dm_ref).max() / np.abs(dm_ref).max()
+    _say("x3", grid, "rhs rel err", err)
+    assert err < 2e-5
+    assert abs(da - da_ref) <= 1e-9 * abs(da_ref)
+    m0 = I.tilted_uniform_state(p.shape, 10.0, 0.02, seed=sum(grid))
+    s.set_state(torch.from_numpy(m0), 0.0, 0j)
+    s.run(nsteps=40)
+    mg, _, _ = s.get_state()
+    mref, _, _, _ = o.run_rk4(m0.astype(np.float64), 0j, p.dt, 40)
+    assert np.abs(mg.cpu().numpy() - mref).max() <= 1e-4
     s.close()
