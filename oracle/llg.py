@@ -20,6 +20,16 @@ numpy float64, in the order the paper states the problem.
     S_i = -Ms_i V_c m_i / gamma (moment mu = -gamma S, M = mu/V_c),
         d alpha/dt = -(i wc + kappa) alpha + i (V_c/hbar) sum_i Ms_i m_i.B_rms
                      - i eps(t)            (eps: optional cavity drive).
+  * Several cavity modes (section "Ferromagnetic materials in a cavity":
+    a multimode cavity is the sum of its modes): each mode k has its own
+    vacuum field B_rms,k (uniform or per cell), frequency, loss and drive;
+    the cavity field is sum_k B_rms,k (alpha_k + alpha_k^*) and each
+    amplitude obeys the single-mode equation with its own coupling sum
+    F_k = sum_i Ms_i m_i . B_rms,k,i.
+  * A field drive shaped in space: B_ext += amp f(t) b(r), the form the
+    paper's example script uses with the mode's field map as b(r) and a
+    sinc pulse as f(t) (appendix "Micromagnetic simulations with
+    Mumax3-cQED").
   * Time integration: classic RK4 (fixed step) or Dormand-Prince 5(4) with
     FSAL on the joint state (m, alpha); m renormalised after every accepted
     step; time-dependent terms evaluated at the stage times.
@@ -33,7 +43,8 @@ Readings where the paper is silent: gamma = 1.7595e11 rad/(s T); open
 (Neumann) exchange boundaries; zero padding 2n per axis; DP45 error norm
 max(max_i |m5-m4|_2, |a5-a4|/max(1,|a5|)) with controller
 dt <- dt*clamp(0.9 (tol/err)^(1/5), 0.2, 5), no growth right after a
-rejection; sinc(0) = 1.
+rejection; sinc(0) = 1.  Several modes: the amplitude part of the DP45
+error is the 2-norm over the modes, |a5-a4|_2 / max(1, |a5|_2).
 """
 from __future__ import annotations
 
@@ -110,6 +121,29 @@ class CavityLLG:
             self.brms_cells = np.asarray(prob.brms, dtype=np.float64).reshape(
                 3, 1, 1, 1) * np.ones((1,) + self.shape)
         self.brms = np.asarray(prob.brms, dtype=np.float64)
+        # multimode cavity: amplitudes are a complex array over the modes
+        self.multi = getattr(prob, "modes", None) is not None
+        if self.multi:
+            modes = list(prob.modes)
+            if not 1 <= len(modes) <= 8:
+                raise ValueError("1..8 modes")
+            cells = []
+            for md in modes:
+                if md.brms_map is not None:
+                    cells.append(np.asarray(md.brms_map, dtype=np.float64)
+                                 .reshape((3,) + self.shape))
+                else:
+                    cells.append(np.asarray(md.brms, dtype=np.float64)
+                                 .reshape(3, 1, 1, 1)
+                                 * np.ones((1,) + self.shape))
+            self.modes = modes
+            self.mode_cells = np.stack(cells)            # (M, 3, nz, ny, nx)
+            self.mode_wc = np.array([md.wc for md in modes], dtype=float)
+            self.mode_kappa = np.array([md.kappa for md in modes],
+                                       dtype=float)
+        fmap = getattr(prob, "fdrive_map", None)
+        self.fdrive_cells = None if fmap is None else np.asarray(
+            fmap, dtype=np.float64).reshape((3,) + self.shape)
         self.nfull = None
         self.kf = None
         self.demag_mode = None
@@ -127,9 +161,14 @@ class CavityLLG:
 
     # ---------------------------------------------------------------- fields
     def zeeman(self, t):
+        """Static field plus the drive amp f(t) times its direction, or
+        times its per-cell shape when a drive map is given."""
         p = self.p
         b = np.asarray(p.bext, dtype=np.float64)
         f = drive_shape(p.fdrive_kind, p.fdrive_w, t)
+        if self.fdrive_cells is not None:
+            return (b.reshape(3, 1, 1, 1) * np.ones((1,) + self.shape)
+                    + p.fdrive_amp * f * self.fdrive_cells)
         b = b + p.fdrive_amp * f * np.asarray(p.fdrive_dir, dtype=np.float64)
         return b.reshape(3, 1, 1, 1) * np.ones((1,) + self.shape)
 
@@ -169,7 +208,10 @@ class CavityLLG:
         return _demag.demag_field_fft(M, self.kf, self.p.mu0)
 
     def cavity_field(self, a):
-        """B_cav,i = B_rms,i (alpha + alpha^*)."""
+        """B_cav,i = B_rms,i (alpha + alpha^*); several modes: the sum of
+        B_rms,k,i (alpha_k + alpha_k^*) over the modes."""
+        if self.multi:
+            return np.tensordot(2.0 * np.real(a), self.mode_cells, axes=1)
         return self.brms_cells * (2.0 * a.real)
 
     def effective_field(self, m, a, t):
@@ -177,7 +219,11 @@ class CavityLLG:
                 + self.demag(m) + self.cavity_field(a))
 
     def coupling_sum(self, m):
-        """F = sum_i Ms_i m_i . B_rms,i  (A m^-1 T)."""
+        """F = sum_i Ms_i m_i . B_rms,i  (A m^-1 T); several modes: the
+        array of F_k = sum_i Ms_i m_i . B_rms,k,i."""
+        if self.multi:
+            return np.array([float((self.ms * (bk * m).sum(axis=0)).sum())
+                             for bk in self.mode_cells])
         return float((self.ms * (self.brms_cells * m).sum(axis=0)).sum())
 
     # -------------------------------------------------------------- dynamics
@@ -193,9 +239,36 @@ class CavityLLG:
 
     def cavity_rate(self, a, F, t):
         p = self.p
+        if self.multi:
+            eps = np.array([md.cdrive_amp * drive_shape(md.cdrive_kind,
+                                                        md.cdrive_w, t)
+                            for md in self.modes])
+            return (-(1j * self.mode_wc + self.mode_kappa) * a
+                    + 1j * (self.vc / p.hbar) * F - 1j * eps)
         eps = p.cdrive_amp * drive_shape(p.cdrive_kind, p.cdrive_w, t)
         return (-(1j * p.wc + p.kappa) * a + 1j * (self.vc / p.hbar) * F
                 - 1j * eps)
+
+    def amplitude(self, a0):
+        """The cavity state as the integrators hold it: a complex number, or
+        a complex array over the modes."""
+        if self.multi:
+            a = np.asarray(a0, dtype=complex).reshape(-1)
+            if a.size == 1 and len(self.modes) > 1:
+                a = np.full(len(self.modes), a[0])
+            return a.copy()
+        return complex(a0)
+
+    def initial_amplitude(self):
+        """alpha_0 = (x0 - i p0)/2 of each mode."""
+        if self.multi:
+            return np.array([0.5 * (md.x0 - 1j * md.p0) for md in self.modes])
+        return 0.5 * (self.p.x0 - 1j * self.p.p0)
+
+    @staticmethod
+    def anorm(a):
+        """|a|, or the 2-norm over the modes."""
+        return float(np.sqrt(np.sum(np.abs(a) ** 2)))
 
     def rhs(self, m, a, t):
         self.nevals += 1
@@ -217,8 +290,12 @@ class CavityLLG:
         ea = -vc * (self.ku * um * um).sum() - vc * (
             getattr(p, "ku2", 0.0) * (self.inside * um ** 4)).sum()
         ed = -0.5 * vc * (self.ms * (m * self.demag(m)).sum(axis=0)).sum()
-        ec = -vc * 2.0 * a.real * self.coupling_sum(m) + \
-            p.hbar * p.wc * abs(a) ** 2
+        if self.multi:
+            ec = float(np.sum(-vc * 2.0 * np.real(a) * self.coupling_sum(m)
+                              + p.hbar * self.mode_wc * np.abs(a) ** 2))
+        else:
+            ec = -vc * 2.0 * a.real * self.coupling_sum(m) + \
+                p.hbar * p.wc * abs(a) ** 2
         return float(ez + ex + ea + ed + ec)
 
     # ----------------------------------------------------------- integrators
@@ -250,20 +327,24 @@ class CavityLLG:
         e = DP_B5 - DP_B4
         errm_vec = h * sum(e[j] * km[j] for j in range(7) if e[j] != 0.0)
         errm = float(np.sqrt((errm_vec ** 2).sum(axis=0)).max())
-        erra = abs(h * sum(e[j] * ka[j] for j in range(7))) / max(1.0,
-                                                                   abs(a5))
+        erra = self.anorm(h * sum(e[j] * ka[j] for j in range(7))) / max(
+            1.0, self.anorm(a5))
         return m5, a5, max(errm, erra), km[6], ka[6]
 
     # ------------------------------------------------------------------ runs
     def record(self, t, m, a):
+        """t, <m> over the magnetic cells, then Re and Im of each mode."""
         mm = m[:, self.inside].mean(axis=1)
-        return [t, mm[0], mm[1], mm[2], a.real, a.imag]
+        row = [t, mm[0], mm[1], mm[2]]
+        for ak in np.atleast_1d(a):
+            row += [ak.real, ak.imag]
+        return row
 
     def run_rk4(self, m0, a0, dt, nsteps, record_every=0, t0=0.0):
         """Fixed-step RK4.  Records (t, <m>, Re a, Im a) for the initial state
         and after every `record_every`-th step."""
         m = np.asarray(m0, dtype=np.float64) * self.inside[None]
-        a = complex(a0)
+        a = self.amplitude(a0)
         t = t0
         rec = [self.record(t, m, a)] if record_every else []
         for n in range(1, nsteps + 1):
@@ -291,6 +372,8 @@ class CavityLLG:
         p = self.p
         if p.cdrive_kind != DRIVE_NONE:
             raise ValueError("the memory form takes no cavity drive")
+        if self.multi:
+            raise ValueError("the memory form is written for one mode")
         m = np.asarray(m0, dtype=np.float64) * self.inside[None]
         a0 = complex(a0)
         x0, p0 = 2.0 * a0.real, -2.0 * a0.imag
@@ -327,7 +410,7 @@ class CavityLLG:
         """Adaptive Dormand-Prince from t0 to t_end (last step truncated to
         land on t_end).  Returns m, a, t, records, accepted dt list, stats."""
         m = np.asarray(m0, dtype=np.float64) * self.inside[None]
-        a = complex(a0)
+        a = self.amplitude(a0)
         t = t0
         k1m, k1a = self.rhs(m, a, t)
         dt = dt0
@@ -371,7 +454,7 @@ class CavityLLG:
         """Dormand-Prince with a prescribed sequence of accepted step sizes
         (every step accepted, FSAL and renormalisation as in run_dp45)."""
         m = np.asarray(m0, dtype=np.float64) * self.inside[None]
-        a = complex(a0)
+        a = self.amplitude(a0)
         t = t0
         k1m, k1a = self.rhs(m, a, t)
         for h in dts:

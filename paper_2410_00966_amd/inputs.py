@@ -26,6 +26,24 @@ MU0 = 4e-7 * math.pi       # T m / A
 DRIVE_NONE, DRIVE_SINC, DRIVE_CW = 0, 1, 2
 CAVITY_ODE, CAVITY_MEMORY = 0, 1
 METHOD_RK4, METHOD_DP45 = 0, 1
+MAX_MODES = 8
+
+
+@dataclasses.dataclass
+class Mode:
+    """One mode of a multimode cavity: its vacuum field (uniform vector, or
+    a per-cell map of shape (3, nz, ny, nx) float32 that replaces it),
+    frequency and loss (rad/s), initial amplitude alpha_0 = (x0 - i p0)/2,
+    and its own drive d(alpha_k)/dt -= i cdrive_amp f(t)."""
+    brms: tuple = (0.0, 0.0, 0.0)
+    wc: float = 0.0
+    kappa: float = 0.0
+    x0: float = 0.0
+    p0: float = 0.0
+    cdrive_kind: int = DRIVE_NONE
+    cdrive_amp: float = 0.0
+    cdrive_w: float = 0.0
+    brms_map: Optional[np.ndarray] = None
 
 
 @dataclasses.dataclass
@@ -43,7 +61,9 @@ class Problem:
     ku1: float = 0.0
     anis_u: tuple = (0.0, 0.0, 1.0)
     bext: tuple = (0.0, 0.0, 0.0)
-    # field drive: B_ext(t) = bext + fdrive_amp * f(t) * fdrive_dir
+    # field drive: B_ext(t) = bext + fdrive_amp * f(t) * fdrive_dir, or
+    # with a per-cell shape fdrive_map (3, nz, ny, nx) float32 in place of
+    # fdrive_dir: bext + fdrive_amp * f(t) * fdrive_map[:, cell]
     fdrive_kind: int = DRIVE_NONE
     fdrive_amp: float = 0.0
     fdrive_w: float = 0.0
@@ -79,6 +99,10 @@ class Problem:
     # optional vacuum field of the mode per cell, float32 (3, nz, ny, nx) in
     # T; replaces the uniform brms when given
     brms_map: Optional[np.ndarray] = None
+    fdrive_map: Optional[np.ndarray] = None
+    # multimode cavity: a list of Mode (1..MAX_MODES); when given, it
+    # replaces the single mode of brms/brms_map/wc/kappa/x0/p0/cdrive_*
+    modes: Optional[list] = None
 
     @property
     def shape(self):
@@ -263,9 +287,13 @@ def c2_nanowire() -> tuple:
     p.brms = (0.0, b, 0.0)
     p.cdrive_kind = DRIVE_SINC
     p.cdrive_w = 2.0 * math.pi * 20e9
-    # a sinc pulse of cut-off w delivers |alpha| ~ pi eps0 / (2 w) to a
-    # resonator below the cut-off
-    p.cdrive_amp = 1e-3 / (2.0 * b) * 2.0 * p.cdrive_w / math.pi
+    # a sinc pulse eps0 sinc(w t) leaves a lossless resonator below the
+    # cut-off (wc < w) with |alpha| = (eps0/w) |pi/2 + (i/2) ln((w+wc)/(w-wc))|
+    # (the t -> infinity limit of the sine/cosine-integral closed form);
+    # eps0 is set so that 2 |B_rms| |alpha| = 1 mT
+    w, wc = p.cdrive_w, p.wc
+    gain = math.hypot(0.5 * math.pi, 0.5 * math.log((w + wc) / (w - wc))) / w
+    p.cdrive_amp = 1e-3 / (2.0 * b) / gain
     m0 = tilted_uniform_state(p.shape, 0.0, 1e-3, seed=1002, axis="x",
                               toward="y")
     return p, m0, dict(t_end=10e-9)
@@ -285,9 +313,11 @@ def c5_adjoint() -> tuple:
     p.brms = (0.0, brms_from_g(g, 8.0e5 * p.ncells * p.vcell), 0.0)
     p.cdrive_kind = DRIVE_CW
     p.cdrive_w = p.wc
-    # resonant CW drive: the free cavity settles at |alpha| = eps0/kappa; the
-    # amplitude gives it a field 2 |B_rms| |alpha| of 1 mT
-    p.cdrive_amp = 1e-3 * p.kappa / (2.0 * p.brms[1])
+    # resonant CW drive eps0 cos(wc t): of its two counter-rotating halves
+    # only e^{-i wc t} is resonant, so the free cavity settles at
+    # |alpha| = eps0/(2 kappa); the amplitude gives it a field
+    # 2 |B_rms| |alpha| of 1 mT
+    p.cdrive_amp = 1e-3 * p.kappa / p.brms[1]
     m0 = tilted_uniform_state(p.shape, 0.0, 1e-3, seed=1005, axis="x",
                               toward="y")
     return p, m0, dict(steps=50000)

@@ -102,3 +102,69 @@ def test_memory_sums_dropped_growth_factor(monkeypatch):
     monkeypatch.setattr(L, "memory_sums", sums)
     with pytest.raises(AssertionError):
         _memory_pin()
+
+
+def _sinc_pin():
+    import test_oracle_drive as TD
+    TD.test_sinc_cavity_drive_closed_form(0.5)
+
+
+def test_normalised_sinc_breaks_drive_pin(monkeypatch):
+    def shape(kind, w, t):
+        if kind == L.DRIVE_SINC:
+            x = math.pi * w * t
+            return 1.0 if x == 0.0 else math.sin(x) / x
+        return 0.0 if kind == L.DRIVE_NONE else math.cos(w * t)
+    monkeypatch.setattr(L, "drive_shape", shape)
+    with pytest.raises(AssertionError):
+        _sinc_pin()
+
+
+def test_sinc_zero_at_origin_breaks_drive_pin(monkeypatch):
+    def shape(kind, w, t):
+        if kind == L.DRIVE_SINC:
+            x = w * t
+            return 0.0 if x == 0.0 else math.sin(x) / x
+        return 0.0 if kind == L.DRIVE_NONE else math.cos(w * t)
+    monkeypatch.setattr(L, "drive_shape", shape)
+    with pytest.raises(AssertionError):
+        _sinc_pin()
+
+
+def test_ignored_drive_map_breaks_linear_response(monkeypatch):
+    orig = L.CavityLLG.__init__
+
+    def init(self, prob, demag="auto"):
+        orig(self, prob, demag)
+        if self.fdrive_cells is not None:   # drive along the first cell's
+            self.fdrive_cells = self.fdrive_cells[:, :1, :1, :1] * np.ones(
+                (1,) + self.shape)
+    monkeypatch.setattr(L.CavityLLG, "__init__", init)
+    import test_oracle_drive as TD
+    with pytest.raises(AssertionError):
+        TD.test_field_drive_map_linear_response()
+
+
+def test_first_mode_only_field_breaks_multimode(monkeypatch):
+    orig = L.CavityLLG.cavity_field
+
+    def field(self, a):
+        if self.multi:
+            return self.mode_cells[0] * (2.0 * np.real(a[0]))
+        return orig(self, a)
+    monkeypatch.setattr(L.CavityLLG, "cavity_field", field)
+    import test_oracle_multimode as TM
+    with pytest.raises(AssertionError):
+        TM.test_degenerate_modes_act_as_one_bright_mode()
+
+
+def test_shared_coupling_sum_breaks_multimode_polaritons(monkeypatch):
+    orig = L.CavityLLG.coupling_sum
+
+    def coupling(self, m):
+        F = orig(self, m)
+        return np.full_like(F, F[0]) if self.multi else F
+    monkeypatch.setattr(L.CavityLLG, "coupling_sum", coupling)
+    import test_oracle_multimode as TM
+    with pytest.raises(AssertionError):
+        TM.test_multimode_polaritons((1.0, 1.6), (0.1, 0.2))
