@@ -91,24 +91,40 @@ def counted_traffic(kernel):
     return _counter_line("traffic_bytes_per_launch", kernel)
 
 
-def cpu_baseline(prob, m0, dt):
-    """The oracle on the same workload and state: one Dormand-Prince attempt
-    (the six right-hand-side evaluations of an accepted FSAL step, at the
-    step size the GPU run settled on) timed on the host; tensor, FFT-kernel
-    set-up and the carried-over first stage are outside the timing."""
-    from oracle.llg import CavityLLG
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(prob, m0, dt, nsteps=3):
+    """The oracle on the same workload and state: `nsteps` Dormand-Prince
+    steps (six right-hand-side evaluations each, FSAL, at the step size the
+    GPU run settled on) timed on the host; tensor and FFT-kernel set-up and
+    the first stage of the first step are outside the timing.  numpy's FFT
+    and elementwise kernels run on one thread."""
+    from oracle.llg import CavityLLG, normalise
     o = CavityLLG(prob, demag="fft")
     m = m0.astype(np.float64)
-    k1m, k1a = o.rhs(m, 0j, 0.0)
+    a = 0j
+    km, ka = o.rhs(m, a, 0.0)
+    t = 0.0
     t0 = time.perf_counter()
-    o.dp45_attempt(m, 0j, 0.0, dt, k1m, k1a)
+    for _ in range(nsteps):
+        m5, a5, _, km, ka = o.dp45_attempt(m, a, t, dt, km, ka)
+        m, a, t = normalise(m5), a5, t + dt
     el = time.perf_counter() - t0
-    return dict(value=prob.ncells / el, unit="cell-steps/s",
+    return dict(value=prob.ncells * nsteps / el, unit="cell-steps/s",
                 cores=1, kind="oracle",
-                sample=("one Dormand-Prince step (6 right-hand-side "
-                        "evaluations, numpy float64, one thread) of the "
-                        f"relaxed {prob.nx}x{prob.ny}x{prob.nz} film at "
-                        f"dt = {dt:.3g} s: {el:.1f} s"))
+                nproc=os.cpu_count(), cpu_model=_cpu_model(),
+                sample=(f"{nsteps} Dormand-Prince steps ({6 * nsteps} "
+                        "right-hand-side evaluations, numpy float64, one "
+                        f"thread) of the relaxed {prob.nx}x{prob.ny}x"
+                        f"{prob.nz} film at dt = {dt:.3g} s: {el:.1f} s"))
 
 
 def bench_batched(torch, t_end, n_plain):
@@ -238,13 +254,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--relax-ns", type=float, default=0.5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-timing", action="store_true",
                     help="skip per-kernel events (for profiler runs)")
     ap.add_argument("--time-all", action="store_true",
                     help="event every kernel in the timed region (default: "
                          "only the dominant one)")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--batch-t-end", type=float, default=10e-12)
+    ap.add_argument("--batch-t-end", type=float, default=2e-9)
     ap.add_argument("--batch-plain", type=int, default=32)
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default plan (profiling runs: no tuning "
@@ -252,7 +269,7 @@ def main():
     ap.add_argument("--no-wire", action="store_true")
     ap.add_argument("--wire-steps", type=int, default=400)
     ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--adjoint-steps", type=int, default=5000)
+    ap.add_argument("--adjoint-steps", type=int, default=50000)
     ap.add_argument("--only", choices=("film", "adjoint", "batched"),
                     help="run one leg alone (for profiler runs)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -368,6 +385,9 @@ def main():
     if not args.no_timing:
         kt = sim.kernel_times()
         ms, n = kt[dom]
+        # a run capped at K accepted steps queues only the attempts it can
+        # still use, so every stage-kernel launch of the timed region does
+        # work when no attempt is rejected: launches == right-hand sides
         per_launch_s = ms * 1e-3 / n
         byts = kernel_bytes(plan, prob, "dp45", dom)
         achieved = byts / per_launch_s / 1e9
@@ -381,6 +401,7 @@ def main():
             "valu_issue_frac": _counter_line("valu_issue_frac_per_launch",
                                              dom),
             "bytes_per_launch": byts, "avg_launch_us": per_launch_s * 1e6,
+            "launches": n, "rhs_evals": info["rhs_evals"],
         }
         # per-kernel table from the warm-up (all kernels timed there).
         # Model bytes per step count the launches that did work: one per
@@ -413,7 +434,8 @@ def main():
                                        args.batch_plain)
     if not args.no_cpu_baseline:
         m_host = m_relaxed.cpu().numpy()
-        out["cpu_baseline"] = cpu_baseline(prob, m_host, info["dt"])
+        out["cpu_baseline"] = cpu_baseline(prob, m_host, info["dt"],
+                                           args.cpu_steps)
     print(json.dumps(out))
 
 

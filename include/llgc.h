@@ -130,8 +130,11 @@ typedef struct {
   double t, dt, last_err;
 } llgc_run_info;
 
-/* Creates a context for one grid.  `hip_stream` is a hipStream_t (NULL =
- * the default stream).  Allocates every device buffer the grid needs and
+/* Creates a context for one grid of finite-difference cells, the
+ * discretisation the paper inherits from Mumax3 (section "The LLG equation
+ * in Mumax3"; the script's SetGridSize / SetCellSize of appendix
+ * "Micromagnetic simulations with Mumax3-cQED").  `hip_stream` is a
+ * hipStream_t (NULL = the default stream).  Allocates every device buffer the grid needs and
  * plans the padded FFT sizes; no parameters or state are set yet.
  * Errors: LLGC_E_ARG (bad sizes, out == NULL), LLGC_E_UNSUPPORTED (nz > 4
  * or padded sizes beyond the on-chip FFT limits), LLGC_E_OOM, LLGC_E_HIP. */
@@ -141,10 +144,13 @@ int llgc_create(const llgc_grid *grid, void *hip_stream, llgc_ctx **out);
 enum { LLGC_PLAN_BATCH = 1 };
 
 /* As llgc_create, with plan flags.  LLGC_PLAN_BATCH selects the fixed plan
- * that every instance of a batch (llgc_batch_create) uses: register FFTs
- * on padded lengths of at least 64 points, 4-row x tiles.  A context
- * created with it performs bit for bit the same arithmetic as the same
- * problem run inside a batch.  It needs 2 <= nx, ny <= 128.
+ * that every instance of a batch (llgc_batch_create) uses: padded lengths
+ * of at least 64 points, LDS Stockham FFTs in every pass, x passes that
+ * transform the three components of a tile of rows at once (rows per tile
+ * chosen so one 512-thread workgroup is full) and a spectral pass with a
+ * fixed workgroup size.  A context created with it performs bit for bit
+ * the same arithmetic as the same problem run inside a batch (the sweeps
+ * of section "Benchmark").  It needs 2 <= nx, ny <= 128.
  * Errors: as llgc_create; LLGC_E_ARG for unknown flags;
  * LLGC_E_UNSUPPORTED outside the batched size range. */
 int llgc_create_ex(const llgc_grid *grid, void *hip_stream, int32_t flags,
@@ -157,21 +163,31 @@ int llgc_destroy(llgc_ctx *ctx);
  * next call).  Never NULL. */
 const char *llgc_last_error(const llgc_ctx *ctx);
 
-/* Copies parameters and maps; (re)builds the demag kernel when the cell
- * geometry requires it (first call); resets the cavity amplitude to
+/* Sets the material, field, cavity and integrator parameters: the
+ * quantities of Eq. (llg) and its effective field (section "The LLG
+ * equation in Mumax3") and the cavity additions B_rms, Wc, Kappa, X0, P0,
+ * HBAR of section "Workflow in Mumax3-cQED".  Copies parameters and maps;
+ * (re)builds the demag kernel when the cell geometry requires it (first
+ * call); resets the cavity amplitude to
  * alpha_0 = (x0 - i p0)/2 and t to 0 only if no state was set before.
  * Errors: LLGC_E_ARG (non-positive ms without map, negative alpha, unknown
  * method or drive kind, dt <= 0), LLGC_E_HIP. */
 int llgc_set_params(llgc_ctx *ctx, const llgc_params *p);
 
-/* Sets m (device pointer, 3*N float32 SoA, copied), the time t and the
- * cavity amplitude alpha = a_re + i a_im.  The vectors are used as given
+/* Sets the joint state of Eqs. (eqmotionspinclasical)/(eqmotionaclasical):
+ * m (device pointer, 3*N float32 SoA, copied; the reduced magnetisation of
+ * Eq. (llg), one unit vector per cell), the time t and the cavity amplitude
+ * alpha = a_re + i a_im.  The vectors are used as given
  * (callers normalise).  Errors: LLGC_E_ARG (m == NULL). */
 int llgc_set_state(llgc_ctx *ctx, const float *m_dev, double t, double a_re,
                    double a_im);
 
-/* Copies m into `m_dev` (device, 3*N float32; may be NULL) and returns t
- * and alpha (host pointers, may be NULL).  Synchronises the stream. */
+/* Reads the joint state back: the outputs the paper's runs record, the
+ * magnetisation (section "Workflow in Mumax3-cQED") and the cavity
+ * amplitude whose modulus squared is the photon number (section
+ * "Introducing the effect of the cavity").  Copies m into `m_dev` (device,
+ * 3*N float32; may be NULL) and returns t and alpha (host pointers, may be
+ * NULL).  Synchronises the stream. */
 int llgc_get_state(llgc_ctx *ctx, float *m_dev, double *t, double *a_re_im);
 
 /* ResetMemoryTerm analogue (paper, script additions): declares the current
@@ -181,7 +197,12 @@ int llgc_reset_cavity(llgc_ctx *ctx, double x0, double p0);
 /* CavityFeatureStatus analogue: 1 if |B_rms| > 0, else 0 (or an error). */
 int llgc_cavity_enabled(const llgc_ctx *ctx);
 
-/* Integrates the joint (m, alpha) system.
+/* Integrates the joint (m, alpha) system of Eq. (llg) with the cavity
+ * field and Eq. (eqmotionaclasical) with loss, the script's Run(t) of
+ * appendix "Micromagnetic simulations with Mumax3-cQED", with one of the
+ * ODE integrators the paper keeps unchanged from Mumax3 (section "Adapting
+ * the memory term for efficient computation"): classic RK4 or
+ * Dormand-Prince 5(4).
  * RK4: `nsteps` fixed steps of params.dt (t_end ignored if nsteps > 0;
  *      otherwise nsteps = round((t_end - t)/dt)).
  * DP45: adaptive steps until t == t_end (the last step is truncated to land
@@ -192,7 +213,10 @@ int llgc_cavity_enabled(const llgc_ctx *ctx);
  * `rec_cap` rows; `n_rec` receives the count.  `info` may be NULL.
  * Errors: LLGC_E_STATE (no params/state), LLGC_E_DT_UNDERFLOW,
  * LLGC_E_NONFINITE (adaptive error non-finite until underflow), LLGC_E_HIP.
- * On a DP45 failure the state is the last accepted one.
+ * On any failure (LLGC_E_NONFINITE, LLGC_E_DT_UNDERFLOW) m, t and alpha
+ * are those of the last accepted step: RK4 writes each new state into a
+ * scratch register and commits it once the step is known to be finite;
+ * DP45 commits only accepted attempts.
  * Launches: the kernels of a chunk (8 DP45 attempts, or one RK4 step) are
  * captured once into a HIP graph on a private stream and replayed on the
  * context's stream; the graph is captured again after anything passed by
@@ -203,7 +227,9 @@ int llgc_run(llgc_ctx *ctx, int64_t nsteps, double t_end,
              int32_t record_every, double *rec, int64_t rec_cap,
              int64_t *n_rec, llgc_run_info *info);
 
-/* One accepted step (RK4: params.dt; DP45: adaptive, retries inside). */
+/* One accepted step of llgc_run's integration (Eq. (llg) with the cavity,
+ * Eq. (eqmotionaclasical)): RK4 with params.dt, or DP45 adaptive with
+ * retries inside.  Errors and state on failure as llgc_run. */
 int llgc_step(llgc_ctx *ctx, llgc_run_info *info);
 
 /* Evaluates the right-hand side once, for parity checks: given m (device,

@@ -68,6 +68,7 @@ struct llgc_ctx {
   int Rwf = 2;           // rows per tile of the wavefront forward x pass
   size_t lds_f, lds_i, lds_y;
   hipStream_t stream;
+  int device = 0;        // HIP device current at creation
   // device buffers
   float *yn = nullptr, *yb[2] = {nullptr, nullptr}, *kb[7] = {};
   float2* spec = nullptr;
@@ -449,7 +450,14 @@ Epi epi_eval(float* kout, float* bout) {
   return E;
 }
 
-Epi epi_rk4(llgc_ctx* c, int s) {
+// RK4 stage epilogues.  A run keeps y_n intact until a step is known to be
+// finite: stage 4 writes the renormalised new state into the scratch
+// register yb[0]; stage 1 of the next step reads it from there and copies it
+// into y_n (the commit), so a non-finite step leaves y_n at the last
+// accepted state.  The run copies y_n into yb[0] before its first step and
+// the last accepted state back after its last (run_prepare, run_conclude).
+// `inplace`: the adjoint's forward sweeps, which read and write y_n itself.
+Epi epi_rk4(llgc_ctx* c, int s, bool inplace = false) {
   Epi E{};
   E.yn = c->yn;
   if (s < 4) {
@@ -458,6 +466,10 @@ Epi epi_rk4(llgc_ctx* c, int s) {
     E.cself = (s == 3) ? 1.f : 0.5f;
     E.ynext = c->yb[s % 2];        // stage s reads yb[(s+1)%2] (s>1)
     E.kout = c->kb[s - 1];
+    if (s == 1 && !inplace) {
+      E.yn = c->yb[0];
+      E.commit = c->yn;
+    }
   } else {
     E.kind = 2;
     E.np = 3;
@@ -468,10 +480,16 @@ Epi epi_rk4(llgc_ctx* c, int s) {
     E.ca[1] = (float)(1.0 / 3.0);
     E.ca[2] = (float)(1.0 / 3.0);
     E.cself = (float)(1.0 / 6.0);
-    E.ynext = c->yn;
+    E.ynext = inplace ? c->yn : c->yb[0];
     E.kout = nullptr;
   }
   return E;
+}
+
+// Input of RK4 stage s (see epi_rk4).
+const float* rk4_input(const llgc_ctx* c, int s, bool inplace = false) {
+  if (s == 1) return inplace ? c->yn : c->yb[0];
+  return c->yb[(s + 1) % 2];
 }
 
 static const double kDPA[8][7] = {
@@ -899,16 +917,15 @@ constexpr int kDpChunk = 8;   // Dormand-Prince attempts per host check
 // The launches of one chunk, issued on c->stream: kind 0 = kDpChunk
 // Dormand-Prince attempts (stages 2..7, then the next attempt's start),
 // kind 1 = one RK4 step (stages 1..4).
-int chunk_direct(llgc_ctx* c, int kind) {
+int chunk_direct(llgc_ctx* c, int kind, int attempts = kDpChunk) {
   int r = LLGC_OK;
   if (kind == 1) {
     for (int s = 1; s <= 4 && !r; ++s) {
-      const float* ys = (s == 1) ? c->yn : c->yb[(s + 1) % 2];
-      r = rhs_stage(c, ys, c->ctl, s, epi_rk4(c, s), 0);
+      r = rhs_stage(c, rk4_input(c, s), c->ctl, s, epi_rk4(c, s), 0);
     }
     return r;
   }
-  for (int b = 0; b < kDpChunk && !r; ++b) {
+  for (int b = 0; b < attempts && !r; ++b) {
     for (int s = 2; s <= 7 && !r; ++s)
       r = rhs_stage(c, c->yb[s % 2], c->ctl, s, epi_dp(c, s), 0);
     if (!r) r = launch_begin(c);
@@ -925,8 +942,10 @@ std::vector<unsigned char> chunk_signature(const llgc_ctx* c) {
     v.insert(v.end(), b, b + n);
   };
   put(&c->P, sizeof(Prm));
-  const int plan[] = {c->use_wy, c->use_wxf, c->use_wxi, c->yhalf, c->Rf,
-                      c->Ri, c->W, c->Ty, c->Ww, c->Rw, c->Rwf, c->Tyh};
+  const int plan[] = {c->use_wy, c->use_wxf, c->use_wxi, c->yhalf, c->x3,
+                      c->Rf,     c->Ri,      c->W,       c->Ty,    c->Ww,
+                      c->Rw,     c->Rwf,     c->Tyh,     (int)c->lds_f,
+                      (int)c->lds_i, (int)c->lds_y, (int)c->lds_yh};
   put(plan, sizeof(plan));
   put(&c->rec, sizeof(c->rec));
   put(&c->ms_map, sizeof(c->ms_map));
@@ -1018,6 +1037,7 @@ int llgc_create_ex(const llgc_grid* g, void* stream, int flags,
   c->N = g->nx * g->ny * g->nz;
   c->dx = g->dx; c->dy = g->dy; c->dz = g->dz;
   c->stream = (hipStream_t)stream;
+  hipGetDevice(&c->device);
   c->batch_plan = bplan;
   c->graphs = getenv("LLGC_NO_GRAPHS") == nullptr;
   c->Px = g->nx == 1 ? 1 : pow2_ceil(2 * g->nx);
@@ -1407,6 +1427,11 @@ int run_prepare(llgc_ctx* c, int64_t nsteps, double t_end, int32_t rec_every,
     }
   }
   rp->done = h.done != 0;
+  if (rp->rk4 && !rp->done) {
+    // the steps read their base state from the scratch register (epi_rk4)
+    HIPCHK(c, hipMemcpyAsync(c->yb[0], c->yn, sizeof(float) * 3 * c->N,
+                             hipMemcpyDeviceToDevice, c->stream));
+  }
   if (int r = ctl_write(c, c->ctl, &h)) return r;
   if (rp->cap > 0) {
     if (int r = launch_record(c)) return r;
@@ -1434,6 +1459,11 @@ int run_conclude(llgc_ctx* c, const RunPrep& rp, double* rec,
   if (rp.cap > 0 && e.nrec > 0) {
     HIPCHK(c, hipMemcpy(rec, c->rec, sizeof(double) * 6 * e.nrec,
                         hipMemcpyDeviceToHost));
+  }
+  if (rp.rk4 && e.status == ST_OK && e.accepted > 0) {
+    // the last step's state is committed from the scratch register
+    HIPCHK(c, hipMemcpyAsync(c->yn, c->yb[0], sizeof(float) * 3 * c->N,
+                             hipMemcpyDeviceToDevice, c->stream));
   }
   if (n_rec) *n_rec = e.nrec;
   if (info) {
@@ -1475,14 +1505,35 @@ int llgc_run(llgc_ctx* c, int64_t nsteps, double t_end, int32_t rec_every,
   } else if (!rp.done) {
     const int64_t max_attempts = 50000000;
     int64_t attempts = 0;
+    // accepted steps still allowed: when fewer than a chunk remain, only
+    // that many attempts are queued (launches past the end of a run would
+    // exit at once on the done flag and only cost launch time)
+    const int64_t cap = nsteps > 0 ? nsteps : INT64_MAX;
+    int64_t accepted = 0;
     while (!r) {
-      r = run_chunk(c, 0);
-      attempts += kDpChunk;
+      const int64_t rem = cap - accepted;
+      if (rem <= 0) break;
+      if (rem < kDpChunk) {
+        r = chunk_direct(c, 0, (int)rem);
+        attempts += rem;
+      } else {
+        r = run_chunk(c, 0);
+        attempts += kDpChunk;
+      }
       if (r) break;
-      int done = 0;
-      HIPCHK(c, hipMemcpyAsync(&done, &c->ctl->done, sizeof(int),
+      // accepted count and done flag of the control block
+      struct {
+        long long accepted;
+        int done;
+      } chk{};
+      HIPCHK(c, hipMemcpyAsync(&chk.accepted, &c->ctl->accepted,
+                               sizeof(long long), hipMemcpyDeviceToHost,
+                               c->stream));
+      HIPCHK(c, hipMemcpyAsync(&chk.done, &c->ctl->done, sizeof(int),
                                hipMemcpyDeviceToHost, c->stream));
       HIPCHK(c, hipStreamSynchronize(c->stream));
+      accepted = chk.accepted;
+      const int done = chk.done;
       if (done) break;
       if (attempts > max_attempts) {
         r = fail(c, LLGC_E_DT_UNDERFLOW, "attempt limit reached");
@@ -1763,7 +1814,7 @@ int rk4_step_stored(llgc_ctx* c, float* Yk /*4 x 3N*/, float* Bk /*4 x 3N*/,
   HIPCHK(c, hipMemcpyAsync(Yk, c->yn, n3 * 4, hipMemcpyDeviceToDevice,
                            c->stream));
   for (int s = 1; s <= 4 && !r; ++s) {
-    Epi E = epi_rk4(c, s);
+    Epi E = epi_rk4(c, s, true);
     E.bout = Bk + (size_t)(s - 1) * n3;
     if (s < 4) E.ynext = Yk + (size_t)s * n3;
     else E.nout = nk;
@@ -1854,8 +1905,8 @@ extern "C" int llgc_adjoint(llgc_ctx* c, int64_t n_steps, double dt,
     const int64_t Sj = std::min(S, n_steps - j * S);
     for (int64_t k = 0; k < Sj && !r; ++k)
       for (int s = 1; s <= 4 && !r; ++s)
-        r = rhs_stage(c, s == 1 ? c->yn : c->yb[(s + 1) % 2], c->ctl, s,
-                      epi_rk4(c, s), 0);
+        r = rhs_stage(c, rk4_input(c, s, true), c->ctl, s,
+                      epi_rk4(c, s, true), 0);
     if (r) return r;
   }
   Ctl fin{};

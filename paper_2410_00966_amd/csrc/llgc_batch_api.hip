@@ -79,7 +79,7 @@ BInst make_binst(llgc_ctx* c, bool rk4) {
   B.rec = c->rec;
   for (int s = 1; s < kMaxStages; ++s) {
     if (rk4 && s <= 4) {
-      B.ys[s] = (s == 1) ? c->yn : c->yb[(s + 1) % 2];
+      B.ys[s] = rk4_input(c, s);
       B.E[s] = epi_rk4(c, s);
     } else if (!rk4 && s >= 2) {
       B.ys[s] = c->yb[s % 2];

@@ -80,6 +80,9 @@ struct Epi {
   float* kout;         // k_s output (may be null)
   float* bout;         // B_eff output (may be null)
   float* nout;         // RK4 final: |m_hat| before renormalisation (or null)
+  float* commit;       // RK4 stage 1 of a run: the stage input (the state
+                       // the previous step left in a scratch register) is
+                       // copied here, committing it as y_n (or null)
 };
 
 __host__ __device__ inline int ilog2(int v) {

@@ -1156,6 +1156,9 @@ __device__ __forceinline__ void field_cells_t(const Prm& P,
     if (y >= ny) continue;
     const int i = (z * ny + y) * nx + x;
     const float mx = ys[i], my = ys[N + i], mz = ys[2 * N + i];
+    if (E.commit) {
+      E.commit[i] = mx; E.commit[N + i] = my; E.commit[2 * N + i] = mz;
+    }
     const float msv = P.ms_map ? P.ms_map[i] : P.ms;
     float Bx = bex + bcx, By = bey + bcy, Bz = bez + bcz;
     if (bmap) {   // per-cell vacuum field of the mode
@@ -1445,7 +1448,17 @@ __device__ __forceinline__ void finish_step_body(
   if (threadIdx.x != 0) return;
   Ctl* c = ctl;
   if (kind == 2) {
-    // RK4 commit and record
+    // RK4: the new state (in a scratch register) and amplitude are committed
+    // only when finite; otherwise the run stops with y_n, t and alpha those
+    // of the last accepted step
+    const double s0 = S[0], s1 = S[1], s2 = S[2];
+    if (!(isfinite(s0) && isfinite(s1) && isfinite(s2) &&
+          isfinite(c->anext_re) && isfinite(c->anext_im))) {
+      c->status = ST_NONFINITE;
+      c->done = 1;
+      if (ndone) atomicAdd(ndone, 1);
+      return;
+    }
     c->t = c->t + c->dt;
     c->a_re = c->anext_re;
     c->a_im = c->anext_im;
@@ -1461,11 +1474,6 @@ __device__ __forceinline__ void finish_step_body(
     if (c->accepted >= c->loss_n0 && c->accepted <= c->loss_n1)
       c->loss_acc += c->a_re * c->a_re + c->a_im * c->a_im;
     if (c->max_accepted > 0 && c->accepted >= c->max_accepted) c->done = 1;
-    const double s0 = S[0], s1 = S[1], s2 = S[2];
-    if (!(isfinite(s0) && isfinite(s1) && isfinite(s2))) {
-      c->status = ST_NONFINITE;
-      c->done = 1;
-    }
     if (c->rec_every > 0 && (c->accepted % c->rec_every) == 0 &&
         c->nrec < c->rec_cap) {
       double* row = rec + 6 * (size_t)c->nrec;
@@ -1615,7 +1623,9 @@ __device__ __forceinline__ void begin_body(
   }
   if (!pend) return;
   if (!rec_due) {
-    // every block saw pend = 1; clear it from the last one to arrive
+    // every block saw pend = 1; clear it from the last one to arrive, once
+    // every wave of this block is past its read of the flag
+    __syncthreads();
     if (threadIdx.x == 0) {
       const unsigned int prev = atomicAdd(&ctl->cnt_begin, 1u);
       if (prev == nblk - 1) {
