@@ -241,6 +241,25 @@ int llgc_eval_rhs(llgc_ctx *ctx, const float *m_dev, double a_re,
                   double a_im, double t, float *dmdt_dev, float *beff_dev,
                   double *dadt);
 
+/* As llgc_eval_rhs, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the evaluation's control block, partial sums and half
+ * spectrum live in a static device array of the library (16 MiB per
+ * device, held until the process ends) instead of the context's buffers,
+ * and the call allocates nothing.  The context still supplies the
+ * parameters and the demag kernel; the caller passes m, dmdt and beff as
+ * for llgc_eval_rhs.  Calls share the array of their device: calls that
+ * overlap on one GPU (other threads, other streams) race; each call clears
+ * what it reads before use.  The current HIP device must be the one the
+ * context was created on.
+ * Errors: as llgc_eval_rhs; LLGC_E_ARG (another device current);
+ * LLGC_E_UNSUPPORTED when the grid needs more than 16 MiB of scratch
+ * (roughly (nx+1) * ny * nz * 24 bytes with demag; 512 x 512 x 2 fits);
+ * LLGC_E_HIP. */
+int llgc_eval_rhs_noalloc(llgc_ctx *ctx, const float *m_dev, double a_re,
+                          double a_im, double t, float *dmdt_dev,
+                          float *beff_dev, double *dadt);
+
 /* Plan autotuner for the demag convolution of Eq. (llg)'s effective field
  * (section "The LLG equation in Mumax3").  Each of the three FFT passes (y
  * spectral pass, forward x pass, field x pass) can hold its transforms in

@@ -1576,6 +1576,131 @@ int llgc_eval_rhs(llgc_ctx* c, const float* m, double are, double aim,
   return LLGC_OK;
 }
 
+}  // extern "C"
+
+// ------------------------------------------- evaluation without allocation
+// Device memory of llgc_eval_rhs_noalloc: its control block, partial sums
+// and half spectrum live in this file-scope array instead of the context's
+// buffers.  Each device holds one copy for the life of the process; host
+// code reaches it only through the address hipGetSymbolAddress gives for the
+// current device (the array's name is not a device address on the host).
+namespace {
+constexpr size_t kScratchBytes = (size_t)16 << 20;
+}
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, unsigned char*> g_scratch_addr;   // device -> its copy
+
+// Address of the current device's copy, looked up once per device.
+int scratch_addr(llgc_ctx* c, int dev, unsigned char** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it == g_scratch_addr.end()) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(c, LLGC_E_HIP, "hipGetSymbolAddress(scratch): %s",
+                  hipGetErrorString(e));
+    it = g_scratch_addr.emplace(dev, (unsigned char*)p).first;
+  }
+  *out = it->second;
+  return LLGC_OK;
+}
+
+__global__ void k_zero4(float4* __restrict__ p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Bytes of scratch an evaluation on this context needs: control block,
+// partial sums, half spectrum (demag only).
+size_t noalloc_bytes(const llgc_ctx* c, size_t* off_part, size_t* off_spec,
+                     size_t* nspec) {
+  *nspec = c->P.demag ? (size_t)c->Hx * c->nz * 3 * (c->ny + (c->ny & 1))
+                      : 0;
+  *off_part = align256(sizeof(Ctl));
+  *off_spec = *off_part + align256(sizeof(double) * c->npartials);
+  return *off_spec + sizeof(float2) * *nspec;
+}
+
+}  // namespace
+
+extern "C" {
+
+int llgc_eval_rhs_noalloc(llgc_ctx* c, const float* m, double are,
+                          double aim, double t, float* dmdt, float* beff,
+                          double* dadt) {
+  if (!c) return LLGC_E_ARG;
+  if (!c->have_params)
+    return fail(c, LLGC_E_STATE, "set params before evaluating");
+  if (!m || !dmdt) return fail(c, LLGC_E_ARG, "m and dmdt are required");
+  int dev = -1;
+  HIPCHK(c, hipGetDevice(&dev));
+  if (dev != c->device)
+    return fail(c, LLGC_E_ARG, "current device %d is not the context's (%d)",
+                dev, c->device);
+  size_t off_part, off_spec, nspec;
+  const size_t need = noalloc_bytes(c, &off_part, &off_spec, &nspec);
+  if (need > kScratchBytes)
+    return fail(c, LLGC_E_UNSUPPORTED,
+                "evaluation needs %zu bytes of static scratch; the limit is "
+                "%zu (padded grid too large: use llgc_eval_rhs)",
+                need, kScratchBytes);
+  unsigned char* base = nullptr;
+  if (int r = scratch_addr(c, dev, &base)) return r;
+  Ctl* ctl = (Ctl*)base;
+  double* part = (double*)(base + off_part);
+  float2* spec = (float2*)(base + off_spec);
+  Ctl h{};
+  h.t = t;
+  h.dt = 0.0;
+  h.a_re = are;
+  h.a_im = aim;
+  h.as_re[1] = are;
+  h.as_im[1] = aim;
+  h.t_end = 1e300;
+  if (int r = ctl_write(c, ctl, &h)) return r;
+  if (nspec > 0) {
+    // the previous call's spectrum is cleared (the context's own spectrum
+    // starts zeroed at creation)
+    const size_t n4 = nspec / 2;   // nspec is even: rows padded to even
+    hipLaunchKernelGGL(k_zero4, dim3((unsigned)std::min<size_t>(
+                                    2048, (n4 + 255) / 256)),
+                       dim3(256), 0, c->stream, (float4*)spec, n4);
+    if (int r = check_launch(c, "k_zero4")) return r;
+  }
+  // the launches below take the scratch spectrum and partials in place of
+  // the context's; no events (timing off for this call)
+  struct Swap {
+    llgc_ctx* c;
+    float2* spec;
+    double* part;
+    bool timing;
+    ~Swap() {
+      c->spec = spec;
+      c->partials = part;
+      c->timing = timing;
+    }
+  } restore{c, c->spec, c->partials, c->timing};
+  c->spec = spec;
+  c->partials = part;
+  c->timing = false;
+  if (int r = rhs_stage(c, m, ctl, 1, epi_eval(dmdt, beff), 1)) return r;
+  Ctl e{};
+  if (int r = ctl_read(c, &e, ctl)) return r;
+  if (dadt) {
+    dadt[0] = e.rhs_dadt_re;
+    dadt[1] = e.rhs_dadt_im;
+  }
+  return LLGC_OK;
+}
+
 int llgc_autotune(llgc_ctx* c, int32_t reps, int32_t* choice) {
   if (!c) return LLGC_E_ARG;
   if (c->batch_plan)

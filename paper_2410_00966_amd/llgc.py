@@ -29,7 +29,7 @@ EXPORTED = ("llgc_create", "llgc_destroy", "llgc_last_error",
             "llgc_plan_info", "llgc_create_ex", "llgc_batch_create",
             "llgc_batch_destroy", "llgc_batch_last_error",
             "llgc_batch_instance", "llgc_batch_run", "llgc_set_timing_only",
-            "llgc_autotune")
+            "llgc_autotune", "llgc_eval_rhs_noalloc")
 PLAN_BATCH = 1
 
 
@@ -126,6 +126,8 @@ def load():
                             P(RunInfo), P(i32)], ctypes.c_int),
         "llgc_set_timing_only": ([vp, ctypes.c_char_p], ctypes.c_int),
         "llgc_autotune": ([vp, i32, P(i32)], ctypes.c_int),
+        "llgc_eval_rhs_noalloc": ([vp, vp, dbl, dbl, dbl, vp, vp, P(dbl)],
+                                  ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -288,6 +290,20 @@ class Sim:
             B.data_ptr() if B is not None else None, da), "llgc_eval_rhs")
         self.stream.synchronize()
         return dm, B, complex(da[0], da[1])
+
+    def eval_rhs_noalloc(self, m, dm, B=None, a=0j, t=0.0):
+        """llgc_eval_rhs_noalloc: as eval_rhs into caller-provided `dm` (and
+        `B`), with the library's static scratch instead of allocations.
+        Returns d alpha/dt."""
+        md = self._dev(m).reshape(self.shape)
+        da = (ctypes.c_double * 2)()
+        a = complex(a)
+        self._check(self.L.llgc_eval_rhs_noalloc(
+            self.h, md.data_ptr(), a.real, a.imag, float(t), dm.data_ptr(),
+            B.data_ptr() if B is not None else None, da),
+            "llgc_eval_rhs_noalloc")
+        self.stream.synchronize()
+        return complex(da[0], da[1])
 
     def adjoint(self, n_steps, dt, n0, n1, stride=0):
         """Discrete-adjoint gradient of L = mean_{n0<=n<=n1} |alpha_n|^2
