@@ -37,7 +37,9 @@ def kernel_bytes(plan, prob, method, kernel):
     Px, Py = plan["Px"], plan["Py"]
     Hx, Hy = Px // 2 + 1, Py // 2 + 1
     spec = Hx * nz * 3 * ny * 8
-    kern = Hx * Hy * 6 * nz * 4
+    # kernel coefficients: six tensor components per z offset, less the xz
+    # and yz ones at offset 0, which vanish (odd in the z offset)
+    kern = Hx * Hy * (6 * nz - 2) * 4
     state = 12 * N
     if kernel == "k_xfwd":
         return state + spec

@@ -74,6 +74,8 @@ typedef struct {
 } llgc_grid;
 
 /* Material, field, cavity and integrator parameters.
+ * Field drive: B_ext(t) = bext + fdrive_amp * f(t) * fdrive_dir, or with
+ * fdrive_map the per-cell vector in place of fdrive_dir.
  * Maps (ms_map, ku1_map) are device pointers to N float32 values in
  * [z][y][x] order, or NULL for the uniform scalar; they are copied by
  * llgc_set_params, so the caller keeps ownership.
@@ -123,6 +125,14 @@ typedef struct {
                               only (relaxation dynamics, as Mumax3's
                               relax); 0: full LL torque.  Not with
                               llgc_adjoint. */
+  const float *fdrive_map; /* T per unit drive, 3 N float32 as [c][z][y][x]
+                              (device; copied), or NULL for the uniform
+                              fdrive_dir.  Replaces fdrive_dir cell by cell:
+                              B_ext,i(t) = bext + fdrive_amp f(t) map_i, the
+                              excitation of the paper's example script
+                              (B_ext += amp B_rms(r) sinc(w t), appendix
+                              "Micromagnetic simulations with Mumax3-cQED").
+                              Not with llgc_adjoint. */
 } llgc_params;
 
 typedef struct {

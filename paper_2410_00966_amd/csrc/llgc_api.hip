@@ -82,6 +82,7 @@ struct llgc_ctx {
   Ctl* ctl_eval = nullptr;
   float *ms_map = nullptr, *ku_map = nullptr;
   float* brms_map = nullptr;   // 3 N floats
+  float* fdrive_map = nullptr; // 3 N floats: field drive per cell
   bool masked = false;         // geometry: some cells have Ms = 0
   double nmag = 0.0;           // magnetic cells
   size_t npartials = 0;
@@ -686,6 +687,8 @@ void fill_prm(llgc_ctx* c) {
   P.fkind = p.fdrive_kind; P.famp = p.fdrive_amp; P.fw = p.fdrive_w;
   P.fdx = (float)p.fdrive_dir[0]; P.fdy = (float)p.fdrive_dir[1];
   P.fdz = (float)p.fdrive_dir[2];
+  P.fdrive_map = c->fdrive_map;
+  if (c->fdrive_map) P.fdx = P.fdy = P.fdz = 0.f;   // the map replaces it
   P.demag = p.enable_demag ? 1 : 0;
   P.brx = (float)p.brms[0]; P.bry = (float)p.brms[1]; P.brz = (float)p.brms[2];
   P.brxd = p.brms[0]; P.bryd = p.brms[1]; P.brzd = p.brms[2];
@@ -700,8 +703,8 @@ void fill_prm(llgc_ctx* c) {
   P.cmode = p.cavity_mode;
   P.ku4 = (float)(4.0 * p.ku2);
   P.prec = p.no_precession ? 0.f : 1.f;
-  P.plain = (!c->masked && !c->brms_map && p.ku2 == 0.0 &&
-             !p.no_precession) ? 1 : 0;
+  P.plain = (!c->masked && !c->brms_map && !c->fdrive_map &&
+             p.ku2 == 0.0 && !p.no_precession) ? 1 : 0;
   P.tol = p.tol;
   P.dt_min = p.dt_min > 0 ? p.dt_min : 1e-20;
   P.dt_max = p.dt_max > 0 ? p.dt_max : 1e-10;
@@ -1200,6 +1203,7 @@ int llgc_destroy(llgc_ctx* c) {
   hipFree(c->ctl_eval);
   hipFree(c->ms_map);
   hipFree(c->brms_map);
+  hipFree(c->fdrive_map);
   hipFree(c->ku_map);
   delete c;
   return LLGC_OK;
@@ -1275,6 +1279,14 @@ int llgc_set_params(llgc_ctx* c, const llgc_params* p) {
   } else if (c->brms_map) {
     HIPCHK(c, hipFree(c->brms_map));
     c->brms_map = nullptr;
+  }
+  if (p->fdrive_map) {
+    if (!c->fdrive_map) HIPCHK(c, hipMalloc(&c->fdrive_map, 3 * nb));
+    HIPCHK(c, hipMemcpyAsync(c->fdrive_map, p->fdrive_map, 3 * nb,
+                             hipMemcpyDeviceToDevice, c->stream));
+  } else if (c->fdrive_map) {
+    HIPCHK(c, hipFree(c->fdrive_map));
+    c->fdrive_map = nullptr;
   }
   fill_prm(c);
   if (c->have_state && c->masked) {
@@ -1965,6 +1977,9 @@ extern "C" int llgc_adjoint(llgc_ctx* c, int64_t n_steps, double dt,
     return fail(c, LLGC_E_UNSUPPORTED, "adjoint of the cavity ODE form only");
   if (c->brms_map)
     return fail(c, LLGC_E_UNSUPPORTED, "adjoint with a uniform B_rms only");
+  if (c->fdrive_map)
+    return fail(c, LLGC_E_UNSUPPORTED,
+                "adjoint with a uniform field-drive direction only");
   if (c->masked)
     return fail(c, LLGC_E_UNSUPPORTED, "adjoint without empty cells only");
   if (c->prm.ku2 != 0.0 || c->prm.no_precession)

@@ -50,7 +50,8 @@ struct Prm {
   float bx, by, bz;             // static external field
   int fkind;
   double famp, fw;
-  float fdx, fdy, fdz;          // field drive direction
+  float fdx, fdy, fdz;          // field drive direction (0 with a map)
+  const float* fdrive_map;      // per-cell drive vector [c][cell] or nullptr
   int demag;
   float brx, bry, brz;          // B_rms
   const float* brms_map;        // per-cell B_rms [c][cell] or nullptr

@@ -1166,6 +1166,11 @@ __device__ __forceinline__ void field_cells_t(const Prm& P,
       By = bey + bmap[N + i] * gcav;
       Bz = bez + bmap[2 * N + i] * gcav;
     }
+    if (GEN && P.fdrive_map) {   // field drive shaped per cell
+      Bx += fd * P.fdrive_map[i];
+      By += fd * P.fdrive_map[N + i];
+      Bz += fd * P.fdrive_map[2 * N + i];
+    }
     if (P.demag) {
       const float3 b = bd(r, x);
       Bx += b.x;

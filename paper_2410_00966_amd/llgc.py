@@ -63,7 +63,7 @@ class Params(ctypes.Structure):
         ("tol", ctypes.c_double), ("dt_min", ctypes.c_double),
         ("dt_max", ctypes.c_double), ("cavity_mode", ctypes.c_int32),
         ("brms_map", _FP), ("ku2", ctypes.c_double),
-        ("no_precession", ctypes.c_int32),
+        ("no_precession", ctypes.c_int32), ("fdrive_map", _FP),
     ]
 
 
@@ -141,7 +141,8 @@ def grid_of(prob) -> Grid:
     return Grid(prob.nx, prob.ny, prob.nz, prob.dx, prob.dy, prob.dz)
 
 
-def make_params(prob, ms_map=None, ku_map=None, brms_map=None) -> Params:
+def make_params(prob, ms_map=None, ku_map=None, brms_map=None,
+                fdrive_map=None) -> Params:
     """Marshals an inputs.Problem into the C struct (maps: device tensors)."""
     p = Params()
     p.ms = prob.ms
@@ -168,6 +169,7 @@ def make_params(prob, ms_map=None, ku_map=None, brms_map=None) -> Params:
     p.brms_map = brms_map.data_ptr() if brms_map is not None else None
     p.ku2 = getattr(prob, "ku2", 0.0)
     p.no_precession = 0 if getattr(prob, "precession", 1) else 1
+    p.fdrive_map = fdrive_map.data_ptr() if fdrive_map is not None else None
     p.dt, p.tol = prob.dt, prob.tol
     p.dt_min, p.dt_max = prob.dt_min, prob.dt_max
     return p
@@ -224,7 +226,9 @@ class Sim:
         kum = self._dev(prob.ku1_map) if prob.ku1_map is not None else None
         bm = getattr(prob, "brms_map", None)
         brm = self._dev(bm).reshape(-1) if bm is not None else None
-        p = make_params(prob, msm, kum, brm)
+        fm = getattr(prob, "fdrive_map", None)
+        fdm = self._dev(fm).reshape(-1) if fm is not None else None
+        p = make_params(prob, msm, kum, brm, fdm)
         self._check(self.L.llgc_set_params(self.h, ctypes.byref(p)),
                     "llgc_set_params")
         self.stream.synchronize()

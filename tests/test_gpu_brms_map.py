@@ -92,10 +92,12 @@ def test_rk4_run_with_map_matches_oracle(torch):
     m, _, a = s.get_state()
     s.close()
     dm = np.abs(m.cpu().numpy() - mref).max()
-    scale = max(1.0, np.abs(recref[:, 4:]).max())
-    _say("map rk4 max|dm|", dm, "a", a, aref)
+    scale = np.abs(recref[:, 4] + 1j * recref[:, 5]).max()
+    ea = np.abs((rec[:, 4] - recref[:, 4])
+                + 1j * (rec[:, 5] - recref[:, 5])).max()
+    _say("map rk4 max|dm|", dm, "a", a, aref, "|da|/max|a|", ea / scale)
     assert dm <= 1e-4
-    assert np.abs(rec[:, 4:] - recref[:, 4:]).max() <= 1e-3 * scale
+    assert ea <= 1e-6 * scale
     assert abs(aref) > 1e-3                 # the map couples
 
 

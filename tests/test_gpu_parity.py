@@ -146,8 +146,14 @@ def _compare_run(torch, p, m0, nsteps, rec_every, tol_cell, a0=0j):
     assert dm <= tol_cell
     assert rec.shape == recref.shape
     assert np.abs(rec[:, 1:4] - recref[:, 1:4]).max() <= tol_cell
-    scale = max(1.0, np.abs(recref[:, 4:]).max())
-    assert np.abs(rec[:, 4:] - recref[:, 4:]).max() <= 1e-3 * scale
+    # the amplitude is FP64 on both sides but driven through the coupling
+    # sum by the FP32 state, whose per-cell error it follows (measured up to
+    # 2.5e-6 of its largest recorded value over 5000 steps)
+    scale = np.abs(recref[:, 4] + 1j * recref[:, 5]).max()
+    ea = np.abs((rec[:, 4] - recref[:, 4]) + 1j * (rec[:, 5] - recref[:, 5]))
+    _say("  max|da| / max|a|", ea.max() / max(scale, 1e-300))
+    assert ea.max() <= 1e-5 * scale + 1e-15
+    assert abs(a - aref) <= 1e-5 * scale + 1e-15
     s.close()
     return m, mref
 
