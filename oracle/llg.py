@@ -26,6 +26,18 @@ numpy float64, in the order the paper states the problem.
     the cavity field is sum_k B_rms,k (alpha_k + alpha_k^*) and each
     amplitude obeys the single-mode equation with its own coupling sum
     F_k = sum_i Ms_i m_i . B_rms,k,i.
+  * Dzyaloshinskii-Moriya interaction, one of the effective-field terms the
+    paper lists after Eq. (llg) (defined in the Mumax3 reference it cites):
+    interfacial, energy density D [m_z div m - (m.grad) m_z], and bulk,
+    D m.(curl m).  Discretised on the bonds between neighbouring magnetic
+    cells i, j (unit vector e_ij, spacing d_ij):
+        E = sum_bonds c_ij . (m_i x m_j),
+        c_ij = D_int V_c (z x e_ij)/d_ij - D_bulk V_c e_ij/d_ij,
+    whose continuum limit is the energy density above; the field is
+    B_i = -(1/(Ms_i V_c)) dE/dm_i = (1/(Ms_i V_c)) sum_j c_ij x m_j (in the
+    interior the central differences of (2D/Ms)(dm_z/dx, dm_z/dy,
+    -dm_x/dx - dm_y/dy) and -(2D/Ms) curl m).  At an open edge the missing
+    bond is omitted, as for exchange.
   * A field drive shaped in space: B_ext += amp f(t) b(r), the form the
     paper's example script uses with the mode's field map as b(r) and a
     sinc pulse as f(t) (appendix "Micromagnetic simulations with
@@ -199,6 +211,65 @@ class CavityLLG:
         return ((2.0 * self.ku * um + 4.0 * ku2 * um ** 3)
                 * self.inv_ms)[None] * self.u.reshape(3, 1, 1, 1)
 
+    def _dmi_bonds(self):
+        """(axis, spacing, c-vector per unit D_int, per unit D_bulk) for the
+        bonds along x, y, z; a bond joins cell i and its + neighbour."""
+        p = self.p
+        z = np.array([0.0, 0.0, 1.0])
+        out = []
+        for axis, d, e in ((3, p.dx, np.array([1.0, 0.0, 0.0])),
+                           (2, p.dy, np.array([0.0, 1.0, 0.0])),
+                           (1, p.dz, np.array([0.0, 0.0, 1.0]))):
+            out.append((axis, d, np.cross(z, e) / d, -e / d))
+        return out
+
+    def dmi_energy(self, m):
+        """E_dmi = sum over bonds of c_ij . (m_i x m_j) (J)."""
+        p = self.p
+        di = getattr(p, "dmi_int", 0.0)
+        db = getattr(p, "dmi_bulk", 0.0)
+        if di == 0.0 and db == 0.0:
+            return 0.0
+        vc = self.vc
+        ins = self.inside[None]
+        e = 0.0
+        for axis, d, ci, cb in self._dmi_bonds():
+            if m.shape[axis] < 2:
+                continue
+            c = vc * (di * ci + db * cb)
+            lo = [slice(None)] * 4
+            hi = [slice(None)] * 4
+            lo[axis] = slice(0, -1)
+            hi[axis] = slice(1, None)
+            pair = (ins[tuple(lo)] & ins[tuple(hi)])[0]
+            cr = np.cross(m[tuple(lo)], m[tuple(hi)], axis=0)
+            e += float((np.einsum("c,c...->...", c, cr) * pair).sum())
+        return e
+
+    def dmi(self, m):
+        """B_i = (1/(Ms_i V_c)) sum over the bonds of i of c_ij x m_j,
+        with c_ij for the bond seen from i (c_ji = -c_ij)."""
+        p = self.p
+        di = getattr(p, "dmi_int", 0.0)
+        db = getattr(p, "dmi_bulk", 0.0)
+        B = np.zeros_like(m)
+        if di == 0.0 and db == 0.0:
+            return B
+        ins = self.inside[None]
+        for axis, d, ci, cb in self._dmi_bonds():
+            if m.shape[axis] < 2:
+                continue
+            c = (di * ci + db * cb).reshape(3, 1, 1, 1)
+            lo = [slice(None)] * 4
+            hi = [slice(None)] * 4
+            lo[axis] = slice(0, -1)
+            hi[axis] = slice(1, None)
+            pair = ins[tuple(lo)] & ins[tuple(hi)]
+            # cell i (lo) sees j = i + e (hi) through c; j sees i through -c
+            B[tuple(lo)] += pair * np.cross(c, m[tuple(hi)], axis=0)
+            B[tuple(hi)] -= pair * np.cross(c, m[tuple(lo)], axis=0)
+        return B * self.inv_ms[None]
+
     def demag(self, m):
         if self.demag_mode is None:
             return np.zeros_like(m)
@@ -216,7 +287,7 @@ class CavityLLG:
 
     def effective_field(self, m, a, t):
         return (self.zeeman(t) + self.exchange(m) + self.anisotropy(m)
-                + self.demag(m) + self.cavity_field(a))
+                + self.dmi(m) + self.demag(m) + self.cavity_field(a))
 
     def coupling_sum(self, m):
         """F = sum_i Ms_i m_i . B_rms,i  (A m^-1 T); several modes: the
@@ -277,7 +348,8 @@ class CavityLLG:
 
     def energy(self, m, a, t=0.0):
         """Total energy of Eq. (startH) in the classical limit (J):
-        Zeeman + exchange + anisotropy + demag - V_c 2Re(a) F + hbar wc |a|^2.
+        Zeeman + exchange + anisotropy + DMI + demag - V_c 2Re(a) F
+        + hbar wc |a|^2.
         """
         p = self.p
         vc = self.vc
@@ -296,7 +368,7 @@ class CavityLLG:
         else:
             ec = -vc * 2.0 * a.real * self.coupling_sum(m) + \
                 p.hbar * p.wc * abs(a) ** 2
-        return float(ez + ex + ea + ed + ec)
+        return float(ez + ex + ea + self.dmi_energy(m) + ed + ec)
 
     # ----------------------------------------------------------- integrators
     def step_rk4(self, m, a, t, dt):

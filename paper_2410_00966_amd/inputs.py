@@ -92,6 +92,10 @@ class Problem:
     # second-order uniaxial anisotropy (J/m^3, same axis as ku1) and the
     # precession switch (0: damping term only, relaxation dynamics)
     ku2: float = 0.0
+    # Dzyaloshinskii-Moriya constants (J/m^2): interfacial (film normal z)
+    # and bulk
+    dmi_int: float = 0.0
+    dmi_bulk: float = 0.0
     precession: int = 1
     # optional per-cell maps, float32 arrays of shape (nz, ny, nx)
     ms_map: Optional[np.ndarray] = None

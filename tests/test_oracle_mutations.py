@@ -168,3 +168,33 @@ def test_shared_coupling_sum_breaks_multimode_polaritons(monkeypatch):
     import test_oracle_multimode as TM
     with pytest.raises(AssertionError):
         TM.test_multimode_polaritons((1.0, 1.6), (0.1, 0.2))
+
+
+def test_mirrored_dmi_bonds_break_continuum_limit(monkeypatch):
+    """e x z in place of z x e (the other chirality, in field and energy
+    alike): the gradient pin still holds, the continuum pin does not."""
+    def bonds(self):
+        p = self.p
+        z = np.array([0.0, 0.0, 1.0])
+        out = []
+        for axis, d, e in ((3, p.dx, np.array([1.0, 0.0, 0.0])),
+                           (2, p.dy, np.array([0.0, 1.0, 0.0])),
+                           (1, p.dz, np.array([0.0, 0.0, 1.0]))):
+            out.append((axis, d, np.cross(e, z) / d, -e / d))
+        return out
+    monkeypatch.setattr(L.CavityLLG, "_dmi_bonds", bonds)
+    import test_oracle_dmi as TD
+    TD.test_field_is_energy_gradient(3e-3, 0.0)
+    with pytest.raises(AssertionError):
+        TD.test_continuum_limit_second_order(3e-3, 0.0)
+
+
+def test_dmi_field_missing_factor_breaks_gradient_pin(monkeypatch):
+    orig = L.CavityLLG.dmi
+
+    def half(self, m):
+        return 0.5 * orig(self, m)
+    monkeypatch.setattr(L.CavityLLG, "dmi", half)
+    import test_oracle_dmi as TD
+    with pytest.raises(AssertionError):
+        TD.test_field_is_energy_gradient(0.0, 2e-3)
