@@ -133,6 +133,15 @@ typedef struct {
                               (B_ext += amp B_rms(r) sinc(w t), appendix
                               "Micromagnetic simulations with Mumax3-cQED").
                               Not with llgc_adjoint. */
+  double dmi_int, dmi_bulk; /* J/m^2, Dzyaloshinskii-Moriya constants (one
+                              of the effective-field terms listed after
+                              Eq. (llg)): interfacial, energy density
+                              D [m_z div m - (m.grad) m_z] (film normal z),
+                              and bulk, D m.curl m; discretised on the bonds
+                              between magnetic neighbours, E = sum_bonds
+                              c_ij.(m_i x m_j), c_ij = D_int V_c (z x e_ij)
+                              /d - D_bulk V_c e_ij/d, a missing neighbour's
+                              bond omitted.  Not with llgc_adjoint. */
 } llgc_params;
 
 typedef struct {
@@ -149,6 +158,50 @@ typedef struct {
  * Errors: LLGC_E_ARG (bad sizes, out == NULL), LLGC_E_UNSUPPORTED (nz > 4
  * or padded sizes beyond the on-chip FFT limits), LLGC_E_OOM, LLGC_E_HIP. */
 int llgc_create(const llgc_grid *grid, void *hip_stream, llgc_ctx **out);
+
+/* ---------------------------------------------------------------------
+ * Multimode cavity.  The paper simulates one mode at a time and notes that
+ * a cavity of several modes follows by summing them (section
+ * "Ferromagnetic materials in a cavity", subsection "Effects of the parity
+ * of the magnetic mode").  Here each mode k has its own vacuum field
+ * B_rms,k (uniform, or per cell), frequency, loss, initial amplitude and
+ * drive; the cavity field is sum_k B_rms,k (alpha_k + alpha_k^*) in both
+ * torque terms, and every amplitude obeys the single-mode equation
+ *   d alpha_k/dt = -(i wc_k + kappa_k) alpha_k
+ *                  + i (V_c/hbar) sum_i Ms_i m_i . B_rms,k,i - i eps_k(t)
+ * with its own coupling sum.  The DP45 amplitude error is the 2-norm over
+ * the modes relative to max(1, |alpha|_2). */
+#define LLGC_MAX_MODES 8
+typedef struct {
+  double brms[3];          /* T, uniform vacuum field of the mode           */
+  const float *brms_map;   /* T per cell, 3 N float32 [c][z][y][x] (device;
+                              copied), or NULL for brms                     */
+  double wc, kappa;        /* rad/s                                          */
+  double x0, p0;           /* initial 2 Re alpha_k, -2 Im alpha_k            */
+  int32_t cdrive_kind;     /* LLGC_DRIVE_*: d alpha_k/dt -= i amp f(t)      */
+  double cdrive_amp, cdrive_w;
+} llgc_mode;
+
+/* Replaces the single mode of the parameters (the llgc_params fields brms,
+ * brms_map, wc, kappa, x0, p0, cdrive_*) by `n_modes` modes (host array; maps copied); n_modes = 0
+ * returns to the single mode of the parameters.  Sets every amplitude to
+ * (x0_k - i p0_k)/2.  With modes set: records (llgc_run) have 4 + 2 n_modes
+ * columns (t, <m>, then Re, Im of each mode); llgc_set_state keeps the
+ * amplitudes and ignores its a_re, a_im; llgc_get_state returns mode 0's;
+ * llgc_reset_cavity sets each mode to its own x0, p0 (its arguments are
+ * ignored); llgc_eval_rhs uses the current amplitudes and writes 2 doubles
+ * per mode to dadt.  Call after llgc_set_params (which keeps the modes).
+ * Errors: LLGC_E_STATE (no params), LLGC_E_ARG (n_modes outside
+ * 0..LLGC_MAX_MODES, negative kappa, unknown drive), LLGC_E_UNSUPPORTED
+ * (the memory recursion, batch-plan instances; llgc_adjoint refuses a
+ * context with modes), LLGC_E_OOM, LLGC_E_HIP. */
+int llgc_set_modes(llgc_ctx *ctx, int32_t n_modes, const llgc_mode *modes);
+
+/* Amplitudes of the modes: host arrays of 2 n_modes doubles (Re, Im per
+ * mode).  The getter returns n_modes (or an error); both synchronise the
+ * stream.  Errors: LLGC_E_STATE (no modes set), LLGC_E_ARG (NULL). */
+int llgc_set_mode_amplitudes(llgc_ctx *ctx, const double *a_re_im);
+int llgc_get_mode_amplitudes(llgc_ctx *ctx, double *a_re_im);
 
 /* Plan flags of llgc_create_ex. */
 enum { LLGC_PLAN_BATCH = 1 };

@@ -77,12 +77,19 @@ struct llgc_ctx {
   float2* tw = nullptr;
   double* partials = nullptr;
   double* rec = nullptr;
-  int64_t rec_dev_cap = 0;
+  int64_t rec_dev_cap = 0;    // record buffer size in doubles
   Ctl* ctl = nullptr;
   Ctl* ctl_eval = nullptr;
   float *ms_map = nullptr, *ku_map = nullptr;
   float* brms_map = nullptr;   // 3 N floats
   float* fdrive_map = nullptr; // 3 N floats: field drive per cell
+  // multimode cavity (llgc_set_modes): constants on the device, per-mode
+  // maps, per-tile coupling partials; nmodes = 0 for the single mode
+  int nmodes = 0;
+  llgc_mode mode_h[kMaxModes] = {};
+  Modes* modes_dev = nullptr;
+  float* mode_maps = nullptr;   // nmodes * 3 N floats when any mode has one
+  double* mpart = nullptr;      // kMaxModes doubles per x-pass tile
   bool masked = false;         // geometry: some cells have Ms = 0
   double nmag = 0.0;           // magnetic cells
   size_t npartials = 0;
@@ -317,6 +324,7 @@ int launch_yspec(llgc_ctx* c, Ctl* ctl, int stage, int mode) {
     }
     return check_launch(c, "k_yspec_w");
   }
+  if (!c->P.demag && c->P.modes) return LLGC_OK;   // k_finish_modes did it
   if (!c->P.demag) {
     Timed tm(c, "k_finish_stage");
     hipLaunchKernelGGL(k_finish_stage<kT>, dim3(1), dim3(kT), 0, c->stream,
@@ -406,6 +414,19 @@ int rhs_stage(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
               const Epi& E, int mode) {
   int r;
   if ((r = launch_xfwd(c, ys, ctl, stage, mode))) return r;
+  if (c->P.modes) {
+    // multimode cavity: one coupling sum per mode and x-pass tile
+    Timed tm(c, "k_coupling_modes");
+    const int R = fwd_rows(c);
+    hipLaunchKernelGGL(k_coupling_modes<kT>, xgrid(c, R), dim3(kT), 0,
+                       c->stream, c->P, ys, ctl, R);
+    if ((r = check_launch(c, "k_coupling_modes"))) return r;
+    // the modes' stage rates and next amplitudes (the spectral pass then
+    // skips its single-mode finish)
+    hipLaunchKernelGGL(k_finish_modes<64>, dim3(1), dim3(64), 0, c->stream,
+                       c->P, ctl, (int)xgrid(c, R).x, stage, mode);
+    if ((r = check_launch(c, "k_finish_modes"))) return r;
+  }
   if (c->P.brms_map) {
     // coupling partial sums with the per-cell B_rms (replace the forward
     // pass's uniform-B_rms sums, tile for tile)
@@ -551,13 +572,19 @@ int ctl_write(llgc_ctx* c, Ctl* d, const Ctl* h) {
   return LLGC_OK;
 }
 
+// Record rows: t, <m>, then Re, Im of the mode (6 doubles) or of each mode
+// of a multimode cavity (4 + 2 modes).
+int rec_width(const llgc_ctx* c) { return c->nmodes ? 4 + 2 * c->nmodes : 6; }
+
 int ensure_rec(llgc_ctx* c, int64_t cap) {
-  if (cap <= c->rec_dev_cap) return LLGC_OK;
+  const int64_t need = (int64_t)kMaxModes * 2 + 4;   // widest row
+  const int64_t n = std::max<int64_t>(cap, 16) * need;
+  if (std::max<int64_t>(cap, 16) * rec_width(c) <= c->rec_dev_cap)
+    return LLGC_OK;
   if (c->rec) HIPCHK(c, hipFree(c->rec));
   c->rec = nullptr;
-  int64_t n = std::max<int64_t>(cap, 16);
-  if (hipMalloc(&c->rec, sizeof(double) * 6 * n) != hipSuccess)
-    return fail(c, LLGC_E_OOM, "record buffer of %lld rows", (long long)n);
+  if (hipMalloc(&c->rec, sizeof(double) * n) != hipSuccess)
+    return fail(c, LLGC_E_OOM, "record buffer of %lld rows", (long long)cap);
   c->rec_dev_cap = n;
   return LLGC_OK;
 }
@@ -669,6 +696,11 @@ void fill_prm(llgc_ctx* c) {
   P.idx2 = (float)(1.0 / (c->dx * c->dx));
   P.idy2 = (float)(1.0 / (c->dy * c->dy));
   P.idz2 = (float)(1.0 / (c->dz * c->dz));
+  P.idx1 = (float)(1.0 / c->dx);
+  P.idy1 = (float)(1.0 / c->dy);
+  P.idz1 = (float)(1.0 / c->dz);
+  P.dmi_i = (float)p.dmi_int;
+  P.dmi_b = (float)p.dmi_bulk;
   P.ms = (float)p.ms;
   P.ms_map = c->ms_map;
   P.brms_map = c->brms_map;
@@ -704,7 +736,20 @@ void fill_prm(llgc_ctx* c) {
   P.ku4 = (float)(4.0 * p.ku2);
   P.prec = p.no_precession ? 0.f : 1.f;
   P.plain = (!c->masked && !c->brms_map && !c->fdrive_map &&
-             p.ku2 == 0.0 && !p.no_precession) ? 1 : 0;
+             p.ku2 == 0.0 && !p.no_precession && !c->nmodes &&
+             p.dmi_int == 0.0 && p.dmi_bulk == 0.0) ? 1 : 0;
+  P.modes = c->nmodes ? c->modes_dev : nullptr;
+  P.mpart = c->mpart;
+  P.recw = rec_width(c);
+  if (c->nmodes) {
+    // the modes replace the single mode of the parameters
+    P.brms_map = nullptr;
+    P.brx = P.bry = P.brz = 0.f;
+    P.brxd = P.bryd = P.brzd = 0.0;
+    P.wc = P.kappa = 0.0;
+    P.ckind = 0;
+    P.camp = 0.0;
+  }
   P.tol = p.tol;
   P.dt_min = p.dt_min > 0 ? p.dt_min : 1e-20;
   P.dt_max = p.dt_max > 0 ? p.dt_max : 1e-10;
@@ -1204,6 +1249,9 @@ int llgc_destroy(llgc_ctx* c) {
   hipFree(c->ms_map);
   hipFree(c->brms_map);
   hipFree(c->fdrive_map);
+  hipFree(c->modes_dev);
+  hipFree(c->mode_maps);
+  hipFree(c->mpart);
   hipFree(c->ku_map);
   delete c;
   return LLGC_OK;
@@ -1237,6 +1285,9 @@ int llgc_set_params(llgc_ctx* c, const llgc_params* p) {
       (p->method != LLGC_RK4 || p->cdrive_kind != 0))
     return fail(c, LLGC_E_UNSUPPORTED,
                 "the memory recursion runs with RK4 and no cavity drive");
+  if (p->cavity_mode == LLGC_CAVITY_MEMORY && c->nmodes)
+    return fail(c, LLGC_E_UNSUPPORTED,
+                "the memory recursion is written for one mode");
   c->prm = *p;
   const size_t nb = sizeof(float) * c->N;
   if (p->ms_map) {
@@ -1332,6 +1383,10 @@ int llgc_set_state(llgc_ctx* c, const float* m, double t, double are,
   h.a_im = aim;
   h.as_re[1] = are;
   h.as_im[1] = aim;
+  for (int k = 0; k < c->nmodes; ++k) {   // mode amplitudes stay as set
+    h.mas_re[1][k] = h.ma_re[k];
+    h.mas_im[1][k] = h.ma_im[k];
+  }
   h.pending_accept = 0;
   h.done = 0;
   h.status = 0;
@@ -1368,6 +1423,10 @@ int llgc_reset_cavity(llgc_ctx* c, double x0, double p0) {
   h.a_im = -0.5 * p0;
   h.as_re[1] = h.a_re;
   h.as_im[1] = h.a_im;
+  for (int k = 0; k < c->nmodes; ++k) {   // each mode from its own x0, p0
+    h.ma_re[k] = h.mas_re[1][k] = 0.5 * c->mode_h[k].x0;
+    h.ma_im[k] = h.mas_im[1][k] = -0.5 * c->mode_h[k].p0;
+  }
   h.mem_n = 0;
   if (int r = ctl_write(c, c->ctl, &h)) return r;
   c->need_init = true;
@@ -1378,8 +1437,121 @@ int llgc_cavity_enabled(const llgc_ctx* c) {
   if (!c) return LLGC_E_ARG;
   if (!c->have_params) return 0;
   const double* b = c->prm.brms;
+  if (c->nmodes) {
+    for (int k = 0; k < c->nmodes; ++k) {
+      const double* q = c->mode_h[k].brms;
+      if (c->mode_h[k].brms_map || q[0] != 0.0 || q[1] != 0.0 || q[2] != 0.0)
+        return 1;
+    }
+    return 0;
+  }
   if (c->brms_map) return 1;
   return (b[0] != 0.0 || b[1] != 0.0 || b[2] != 0.0) ? 1 : 0;
+}
+
+int llgc_set_modes(llgc_ctx* c, int32_t n, const llgc_mode* modes) {
+  if (!c) return LLGC_E_ARG;
+  if (!c->have_params)
+    return fail(c, LLGC_E_STATE, "set params before the modes");
+  if (n < 0 || n > kMaxModes || (n > 0 && !modes))
+    return fail(c, LLGC_E_ARG, "0..%d modes", kMaxModes);
+  if (n > 0 && c->prm.cavity_mode != LLGC_CAVITY_ODE)
+    return fail(c, LLGC_E_UNSUPPORTED,
+                "the memory recursion is written for one mode");
+  if (n > 0 && c->batch_plan)
+    return fail(c, LLGC_E_UNSUPPORTED,
+                "batched instances have a single cavity mode");
+  bool any_map = false;
+  for (int k = 0; k < n; ++k) {
+    const llgc_mode& q = modes[k];
+    if (!(q.kappa >= 0) || q.cdrive_kind < 0 || q.cdrive_kind > 2)
+      return fail(c, LLGC_E_ARG, "mode %d: kappa >= 0, known drive kind", k);
+    any_map = any_map || q.brms_map;
+  }
+  const size_t n3 = (size_t)3 * c->N;
+  if (n > 0) {
+    if (!c->modes_dev) HIPCHK(c, hipMalloc(&c->modes_dev, sizeof(Modes)));
+    if (!c->mpart)
+      HIPCHK(c, hipMalloc(&c->mpart, sizeof(double) * kMaxModes *
+                                         c->npartials));
+  }
+  if (c->mode_maps) {
+    HIPCHK(c, hipFree(c->mode_maps));
+    c->mode_maps = nullptr;
+  }
+  Modes h{};
+  h.n = n;
+  if (any_map) {
+    // the maps of the modes that have one, one 3 N block each
+    int nmap = 0;
+    for (int k = 0; k < n; ++k) nmap += modes[k].brms_map ? 1 : 0;
+    HIPCHK(c, hipMalloc(&c->mode_maps, sizeof(float) * n3 * nmap));
+    for (int k = 0, j = 0; k < n; ++k) {
+      if (!modes[k].brms_map) continue;
+      float* dst = c->mode_maps + n3 * j++;
+      HIPCHK(c, hipMemcpyAsync(dst, modes[k].brms_map, sizeof(float) * n3,
+                               hipMemcpyDeviceToDevice, c->stream));
+      h.map[k] = dst;
+    }
+    h.any_map = 1;
+  }
+  for (int k = 0; k < n; ++k) {
+    const llgc_mode& q = modes[k];
+    for (int j = 0; j < 3; ++j) h.br[k][j] = q.brms[j];
+    h.wc[k] = q.wc;
+    h.kappa[k] = q.kappa;
+    h.ckind[k] = q.cdrive_kind;
+    h.camp[k] = q.cdrive_amp;
+    h.cw[k] = q.cdrive_w;
+    c->mode_h[k] = q;
+    c->mode_h[k].brms_map = nullptr;   // borrowed only for this call
+  }
+  if (n > 0)
+    HIPCHK(c, hipMemcpyAsync(c->modes_dev, &h, sizeof(Modes),
+                             hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->nmodes = n;
+  fill_prm(c);
+  // amplitudes start at (x0 - i p0)/2 of each mode
+  Ctl q{};
+  if (int r = ctl_read(c, &q, c->ctl)) return r;
+  for (int k = 0; k < kMaxModes; ++k) {
+    const double ar = k < n ? 0.5 * modes[k].x0 : 0.0;
+    const double ai = k < n ? -0.5 * modes[k].p0 : 0.0;
+    q.ma_re[k] = q.mas_re[1][k] = ar;
+    q.ma_im[k] = q.mas_im[1][k] = ai;
+  }
+  if (int r = ctl_write(c, c->ctl, &q)) return r;
+  c->need_init = true;
+  return LLGC_OK;
+}
+
+int llgc_set_mode_amplitudes(llgc_ctx* c, const double* a) {
+  if (!c) return LLGC_E_ARG;
+  if (!c->nmodes) return fail(c, LLGC_E_STATE, "no multimode cavity set");
+  if (!a) return fail(c, LLGC_E_ARG, "amplitudes are NULL");
+  Ctl q{};
+  if (int r = ctl_read(c, &q, c->ctl)) return r;
+  for (int k = 0; k < c->nmodes; ++k) {
+    q.ma_re[k] = q.mas_re[1][k] = a[2 * k];
+    q.ma_im[k] = q.mas_im[1][k] = a[2 * k + 1];
+  }
+  if (int r = ctl_write(c, c->ctl, &q)) return r;
+  c->need_init = true;
+  return LLGC_OK;
+}
+
+int llgc_get_mode_amplitudes(llgc_ctx* c, double* a) {
+  if (!c) return LLGC_E_ARG;
+  if (!c->nmodes) return fail(c, LLGC_E_STATE, "no multimode cavity set");
+  if (!a) return fail(c, LLGC_E_ARG, "amplitudes are NULL");
+  Ctl q{};
+  if (int r = ctl_read(c, &q, c->ctl)) return r;
+  for (int k = 0; k < c->nmodes; ++k) {
+    a[2 * k] = q.ma_re[k];
+    a[2 * k + 1] = q.ma_im[k];
+  }
+  return c->nmodes;
 }
 
 }  // extern "C" (reopened below)
@@ -1436,6 +1608,10 @@ int run_prepare(llgc_ctx* c, int64_t nsteps, double t_end, int32_t rec_every,
       // current dt may differ from the one y2 was formed with
       h.as_re[2] = h.a_re + h.dt * 0.2 * h.ka_re[1];
       h.as_im[2] = h.a_im + h.dt * 0.2 * h.ka_im[1];
+      for (int k = 0; k < c->nmodes; ++k) {
+        h.mas_re[2][k] = h.ma_re[k] + h.dt * 0.2 * h.mka_re[1][k];
+        h.mas_im[2][k] = h.ma_im[k] + h.dt * 0.2 * h.mka_im[1][k];
+      }
     }
   }
   rp->done = h.done != 0;
@@ -1469,7 +1645,8 @@ int run_conclude(llgc_ctx* c, const RunPrep& rp, double* rec,
   const int64_t evals = rp.rk4 ? 4 * e.accepted
                                : 6 * (e.accepted + e.rejected) + rp.evals;
   if (rp.cap > 0 && e.nrec > 0) {
-    HIPCHK(c, hipMemcpy(rec, c->rec, sizeof(double) * 6 * e.nrec,
+    HIPCHK(c, hipMemcpy(rec, c->rec,
+                        sizeof(double) * rec_width(c) * e.nrec,
                         hipMemcpyDeviceToHost));
   }
   if (rp.rk4 && e.status == ST_OK && e.accepted > 0) {
@@ -1562,6 +1739,49 @@ int llgc_step(llgc_ctx* c, llgc_run_info* info) {
   return llgc_run(c, 1, 1e300, 0, nullptr, 0, nullptr, info);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Control block of a right-hand-side evaluation: time and amplitude given;
+// with a multimode cavity the amplitudes are the context's current ones.
+int eval_ctl(llgc_ctx* c, double t, double are, double aim, Ctl* h) {
+  if (c->nmodes) {
+    Ctl cur{};
+    if (int r = ctl_read(c, &cur, c->ctl)) return r;
+    for (int k = 0; k < c->nmodes; ++k) {
+      h->mas_re[1][k] = h->ma_re[k] = cur.ma_re[k];
+      h->mas_im[1][k] = h->ma_im[k] = cur.ma_im[k];
+    }
+  }
+  h->t = t;
+  h->dt = 0.0;
+  h->a_re = are;
+  h->a_im = aim;
+  h->as_re[1] = are;
+  h->as_im[1] = aim;
+  h->t_end = 1e300;
+  return LLGC_OK;
+}
+
+// d alpha/dt of the evaluation: 2 doubles, or 2 per mode.
+void eval_rates(const llgc_ctx* c, const Ctl& e, double* dadt) {
+  if (!dadt) return;
+  if (c->nmodes) {
+    for (int k = 0; k < c->nmodes; ++k) {
+      dadt[2 * k] = e.mka_re[1][k];
+      dadt[2 * k + 1] = e.mka_im[1][k];
+    }
+    return;
+  }
+  dadt[0] = e.rhs_dadt_re;
+  dadt[1] = e.rhs_dadt_im;
+}
+
+}  // namespace
+
+extern "C" {
+
 int llgc_eval_rhs(llgc_ctx* c, const float* m, double are, double aim,
                   double t, float* dmdt, float* beff, double* dadt) {
   if (!c) return LLGC_E_ARG;
@@ -1569,22 +1789,13 @@ int llgc_eval_rhs(llgc_ctx* c, const float* m, double are, double aim,
     return fail(c, LLGC_E_STATE, "set params before evaluating");
   if (!m || !dmdt) return fail(c, LLGC_E_ARG, "m and dmdt are required");
   Ctl h{};
-  h.t = t;
-  h.dt = 0.0;
-  h.a_re = are;
-  h.a_im = aim;
-  h.as_re[1] = are;
-  h.as_im[1] = aim;
-  h.t_end = 1e300;
+  if (int r = eval_ctl(c, t, are, aim, &h)) return r;
   if (int r = ctl_write(c, c->ctl_eval, &h)) return r;
   if (int r = rhs_stage(c, m, c->ctl_eval, 1, epi_eval(dmdt, beff), 1))
     return r;
   Ctl e{};
   if (int r = ctl_read(c, &e, c->ctl_eval)) return r;
-  if (dadt) {
-    dadt[0] = e.rhs_dadt_re;
-    dadt[1] = e.rhs_dadt_im;
-  }
+  eval_rates(c, e, dadt);
   return LLGC_OK;
 }
 
@@ -1670,13 +1881,7 @@ int llgc_eval_rhs_noalloc(llgc_ctx* c, const float* m, double are,
   double* part = (double*)(base + off_part);
   float2* spec = (float2*)(base + off_spec);
   Ctl h{};
-  h.t = t;
-  h.dt = 0.0;
-  h.a_re = are;
-  h.a_im = aim;
-  h.as_re[1] = are;
-  h.as_im[1] = aim;
-  h.t_end = 1e300;
+  if (int r = eval_ctl(c, t, are, aim, &h)) return r;
   if (int r = ctl_write(c, ctl, &h)) return r;
   if (nspec > 0) {
     // the previous call's spectrum is cleared (the context's own spectrum
@@ -1706,10 +1911,7 @@ int llgc_eval_rhs_noalloc(llgc_ctx* c, const float* m, double are,
   if (int r = rhs_stage(c, m, ctl, 1, epi_eval(dmdt, beff), 1)) return r;
   Ctl e{};
   if (int r = ctl_read(c, &e, ctl)) return r;
-  if (dadt) {
-    dadt[0] = e.rhs_dadt_re;
-    dadt[1] = e.rhs_dadt_im;
-  }
+  eval_rates(c, e, dadt);
   return LLGC_OK;
 }
 
@@ -1980,6 +2182,10 @@ extern "C" int llgc_adjoint(llgc_ctx* c, int64_t n_steps, double dt,
   if (c->fdrive_map)
     return fail(c, LLGC_E_UNSUPPORTED,
                 "adjoint with a uniform field-drive direction only");
+  if (c->nmodes)
+    return fail(c, LLGC_E_UNSUPPORTED, "adjoint with a single cavity mode");
+  if (c->prm.dmi_int != 0.0 || c->prm.dmi_bulk != 0.0)
+    return fail(c, LLGC_E_UNSUPPORTED, "adjoint without DMI");
   if (c->masked)
     return fail(c, LLGC_E_UNSUPPORTED, "adjoint without empty cells only");
   if (c->prm.ku2 != 0.0 || c->prm.no_precession)

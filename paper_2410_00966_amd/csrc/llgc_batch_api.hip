@@ -296,6 +296,9 @@ int llgc_batch_run(llgc_batch* b, int64_t nsteps, double t_end,
                    "before running", k);
     if (c->prm.method != b->inst[0]->prm.method)
       return bfail(b, LLGC_E_ARG, "instances use different methods");
+    if (c->nmodes)
+      return bfail(b, LLGC_E_UNSUPPORTED,
+                   "instance %d: batched instances have one cavity mode", k);
   }
   if (n_rec)
     for (int k = 0; k < n; ++k) n_rec[k] = 0;

@@ -6,6 +6,21 @@
 namespace llgc {
 
 constexpr int kMaxStages = 8;
+constexpr int kMaxModes = 8;   // modes of a multimode cavity
+
+// Constants of a multimode cavity (device memory owned by the context):
+// each mode k has its own vacuum field (uniform vector, or a per-cell map),
+// frequency, loss and drive.
+struct Modes {
+  int n;                          // 1..kMaxModes
+  double br[kMaxModes][3];        // uniform B_rms of each mode (T)
+  double wc[kMaxModes], kappa[kMaxModes];
+  int ckind[kMaxModes];
+  double camp[kMaxModes], cw[kMaxModes];
+  const float* map[kMaxModes];    // per-cell field [c][cell] of mode k, or
+                                  // nullptr for its uniform br[k]
+  int any_map;                    // some mode has a map
+};
 
 // Device-resident integrator control block.  Everything that decides the
 // next step (time, step size, cavity amplitude and stage values, accept /
@@ -29,6 +44,12 @@ struct Ctl {
   long long mem_n;   // memory recursion: steps since the state was set
   long long loss_n0, loss_n1;
   double loss_acc;
+  // multimode cavity (Prm::modes set): these replace the single-mode
+  // amplitude fields above, one entry per mode
+  double ma_re[kMaxModes], ma_im[kMaxModes];            // at t
+  double mas_re[kMaxStages][kMaxModes], mas_im[kMaxStages][kMaxModes];
+  double mka_re[kMaxStages][kMaxModes], mka_im[kMaxStages][kMaxModes];
+  double manext_re[kMaxModes], manext_im[kMaxModes];    // RK4 end of step
 };
 
 enum { ST_OK = 0, ST_UNDERFLOW = 1, ST_NONFINITE = 2 };
@@ -62,11 +83,16 @@ struct Prm {
   float gpref;                  // -gamma / (1 + alpha^2)
   float ku4;                    // 4 Ku2 (J/m^3)
   float prec;                   // 1: precession term on, 0: off
+  float dmi_i, dmi_b;           // DMI constants (J/m^2): interfacial, bulk
+  float idx1, idy1, idz1;       // 1/d per axis
   int plain;                    // none of: B_rms map, geometry, Ku2, no precession
   float alpha;
   int method;                   // 0 RK4, 1 DP45
   int cmode;                    // 0 cavity ODE, 1 memory recursion
   double tol, dt_min, dt_max;
+  const Modes* modes;           // multimode cavity, or nullptr (one mode)
+  double* mpart;                // multimode coupling partials [tile][mode]
+  int recw;                     // record row width: 6, or 4 + 2 modes
 };
 
 // Runge-Kutta epilogue description of one stage of the field kernel.

@@ -194,7 +194,7 @@ __device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
       for (int q = 0; q < (PIN ? R / 2 : R); ++q)
         v[i][q] = s[pidx_s<PS>(base + j + q * Lr)];
       const int k = j & (Ns - 1);
-      if (!TT && k != 0) w1[i] = tw[(k << twshift) & twmask];
+      if (!TT && logNs > 0) w1[i] = tw[(k << twshift) & twmask];
     }
   }
   __syncthreads();
@@ -204,14 +204,17 @@ __device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
     if (b < nbf) {
       const int t = b >> logLr, j = b & (Lr - 1);
       const int k = j & (Ns - 1);
-      if (TT && k != 0) {
+      // Twiddles in every pass after the first (Ns > 1; a uniform branch).
+      // Lanes with k = 0 multiply by exactly 1 + 0i: no per-lane branch,
+      // whose merge would cost a register move per value.
+      if (TT && logNs > 0) {
 #pragma unroll
         for (int q = 1; q < R; ++q) {
           float2 wq = tw[(q - 1) * Ns + k];
           wq.y *= -dir;   // table holds exp(-i ...); inverse conjugates
           v[i][q] = cmul(v[i][q], wq);
         }
-      } else if (k != 0) {
+      } else if (!TT && logNs > 0) {
         float2 w = w1[i];
         w.y *= -dir;   // table holds exp(-i ...); inverse conjugates
         float2 wq = w;

@@ -276,6 +276,84 @@ __device__ __forceinline__ void cavity_stage(const Prm& P, Ctl* c, int s,
   }
 }
 
+// Multimode cavity (section "Ferromagnetic materials in a cavity": each mode
+// of a multimode cavity follows the single-mode equation with its own
+// coupling sum F_k = sum_i Ms_i m_i . B_rms,k,i): the stage rates and next
+// stage amplitudes of every mode, as cavity_stage does for one.  The DP45
+// amplitude error is the 2-norm over the modes relative to
+// max(1, |alpha_5|_2).
+// (Loops over the modes run to kMaxModes with a guard so that the register
+// array F is indexed by constants.)
+__device__ __forceinline__ void cavity_stage_modes(
+    const Prm& P, Ctl* c, int s, const double (&F)[kMaxModes]) {
+  const Modes& M = *P.modes;
+  const double dt = c->dt;
+  const double ts = c->t + stage_c(P, s) * dt;
+#pragma unroll
+  for (int k = 0; k < kMaxModes; ++k) {
+    if (k >= M.n) break;
+    const double eps = M.camp[k] * drive_shape(M.ckind[k], M.cw[k], ts);
+    const double ar = c->mas_re[s][k], ai = c->mas_im[s][k];
+    c->mka_re[s][k] = -M.kappa[k] * ar + M.wc[k] * ai;
+    c->mka_im[s][k] = -M.wc[k] * ar - M.kappa[k] * ai + P.vc_hbar * F[k] - eps;
+  }
+  c->F_last = F[0];
+  if (P.method == 0) {
+    for (int k = 0; k < M.n; ++k) {
+      if (s < 4) {
+        const double h = (s == 3 ? 1.0 : 0.5) * dt;
+        c->mas_re[s + 1][k] = c->ma_re[k] + h * c->mka_re[s][k];
+        c->mas_im[s + 1][k] = c->ma_im[k] + h * c->mka_im[s][k];
+      } else {
+        c->manext_re[k] = c->ma_re[k] + dt / 6.0 *
+            (c->mka_re[1][k] + 2.0 * c->mka_re[2][k] + 2.0 * c->mka_re[3][k] +
+             c->mka_re[4][k]);
+        c->manext_im[k] = c->ma_im[k] + dt / 6.0 *
+            (c->mka_im[1][k] + 2.0 * c->mka_im[2][k] + 2.0 * c->mka_im[3][k] +
+             c->mka_im[4][k]);
+      }
+    }
+    return;
+  }
+  if (s < 7) {
+    for (int k = 0; k < M.n; ++k) {
+      double sr = 0.0, si = 0.0;
+      for (int j = 1; j <= s; ++j) {
+        sr += c_dp_a[s + 1][j - 1] * c->mka_re[j][k];
+        si += c_dp_a[s + 1][j - 1] * c->mka_im[j][k];
+      }
+      c->mas_re[s + 1][k] = c->ma_re[k] + dt * sr;
+      c->mas_im[s + 1][k] = c->ma_im[k] + dt * si;
+    }
+    return;
+  }
+  double e2 = 0.0, a2 = 0.0;
+  for (int k = 0; k < M.n; ++k) {
+    double er = 0.0, ei = 0.0;
+    for (int j = 1; j <= 7; ++j) {
+      er += c_dp_e[j - 1] * c->mka_re[j][k];
+      ei += c_dp_e[j - 1] * c->mka_im[j][k];
+    }
+    e2 += er * er + ei * ei;
+    a2 += c->mas_re[7][k] * c->mas_re[7][k] + c->mas_im[7][k] * c->mas_im[7][k];
+  }
+  c->err_a = dt * sqrt(e2) / fmax(1.0, sqrt(a2));
+}
+
+// Amplitude columns of a record row: Re, Im of the mode, or of each mode.
+__device__ __forceinline__ void record_amplitudes(const Prm& P, const Ctl* c,
+                                                  double* row) {
+  if (P.modes) {
+    for (int k = 0; k < P.modes->n; ++k) {
+      row[4 + 2 * k] = c->ma_re[k];
+      row[5 + 2 * k] = c->ma_im[k];
+    }
+  } else {
+    row[4] = c->a_re;
+    row[5] = c->a_im;
+  }
+}
+
 // ================================================================== k_xfwd
 // 1D grid of ceil(ny/R)*nz tiles (R even, XCD-remapped; the nz layers of one
 // y range are consecutive tiles).  LDS: (R/2) * Px complex.
@@ -544,6 +622,48 @@ __global__ __launch_bounds__(T) void k_coupling_map(
   coupling_tile_body<T>(P, ys, partials, R, blockIdx.x, blockIdx.x);
 }
 
+// ======================================================== k_coupling_modes
+// Multimode cavity: the coupling sums F_k = sum_i Ms_i m_i . B_rms,k,i of
+// every mode over the cells of one x-pass tile (as k_coupling_map), FP64,
+// written to P.mpart[tile * kMaxModes + k].
+template <int T>
+__global__ __launch_bounds__(T) void k_coupling_modes(
+    Prm P, const float* __restrict__ ys, Ctl* __restrict__ ctl, int R) {
+  __shared__ double red[16 * kMaxModes];
+  if (ctl->done) return;
+  const Modes& M = *P.modes;
+  const int nx = P.nx, ny = P.ny, nz = P.nz, N = P.ncell;
+  const int tile = blockIdx.x;
+  const int z = tile % nz;
+  const int y0 = (tile / nz) * R;
+  const int nm = M.n;
+  double f[kMaxModes];
+#pragma unroll
+  for (int k = 0; k < kMaxModes; ++k) f[k] = 0.0;
+  for (int e = threadIdx.x; e < R * nx; e += T) {
+    const int y = y0 + e / nx, x = e % nx;
+    if (y >= ny) continue;
+    const int i = (z * ny + y) * nx + x;
+    const double msv = P.ms_map ? (double)P.ms_map[i] : (double)P.ms;
+    const double mx = msv * ys[i], my = msv * ys[N + i],
+                 mz = msv * ys[2 * N + i];
+#pragma unroll
+    for (int k = 0; k < kMaxModes; ++k) {
+      if (k >= nm) break;
+      if (const float* b = M.map[k]) {
+        f[k] += mx * b[i] + my * b[N + i] + mz * b[2 * N + i];
+      } else {
+        f[k] += mx * M.br[k][0] + my * M.br[k][1] + mz * M.br[k][2];
+      }
+    }
+  }
+  block_sum<kMaxModes>(f, red);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < kMaxModes; ++k)
+      P.mpart[(size_t)tile * kMaxModes + k] = f[k];
+}
+
 // ================================================================ k_xfwd_w
 // Forward x pass with the FFT in registers (Px = 64 * NR): one wavefront per
 // (component, row pair) of an R-row tile.  Lane l, register r loads x =
@@ -665,6 +785,57 @@ __device__ __forceinline__ void finish_cavity(const Prm& P, Ctl* ctl,
   }
 }
 
+// Multimode cavity: the coupling sum of every mode from the tiles' partials
+// (first wavefront, fixed order), then the modes' stage rates and next
+// stage amplitudes.  Runs in its own one-workgroup kernel so that the
+// spectral pass's workgroup 0 keeps only the single-mode finish.
+__device__ __forceinline__ void finish_cavity_modes(const Prm& P, Ctl* ctl,
+                                                    int nblk, int stage,
+                                                    int mode) {
+  if (threadIdx.x >= 64) return;
+  const int nm = P.modes->n;
+  double Fm[kMaxModes];
+#pragma unroll
+  for (int k = 0; k < kMaxModes; ++k) {
+    double v = 0.0;
+    if (k < nm) {   // uniform across the wave
+      for (int b = threadIdx.x; b < nblk; b += 64)
+        v += P.mpart[(size_t)b * kMaxModes + k];
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    }
+    Fm[k] = v;
+  }
+  if (threadIdx.x != 0) return;
+  if (mode == 0) {
+    cavity_stage_modes(P, ctl, stage, Fm);
+  } else {
+    // evaluation: the rates of every mode at the given amplitudes
+    const Modes& M = *P.modes;
+#pragma unroll
+    for (int k = 0; k < kMaxModes; ++k) {
+      if (k >= nm) break;
+      const double eps =
+          M.camp[k] * drive_shape(M.ckind[k], M.cw[k], ctl->t);
+      const double ar = ctl->mas_re[1][k], ai = ctl->mas_im[1][k];
+      ctl->mka_re[1][k] = -M.kappa[k] * ar + M.wc[k] * ai;
+      ctl->mka_im[1][k] =
+          -M.wc[k] * ar - M.kappa[k] * ai + P.vc_hbar * Fm[k] - eps;
+    }
+    ctl->rhs_dadt_re = ctl->mka_re[1][0];
+    ctl->rhs_dadt_im = ctl->mka_im[1][0];
+    ctl->F_last = Fm[0];
+  }
+}
+
+template <int T>
+__global__ __launch_bounds__(T) void k_finish_modes(Prm P,
+                                                    Ctl* __restrict__ ctl,
+                                                    int nblk, int stage,
+                                                    int mode) {
+  if (ctl->done) return;
+  finish_cavity_modes(P, ctl, nblk, stage, mode);
+}
+
 // Stand-alone stage finish (used when there is no spectral pass).
 template <int T>
 __global__ __launch_bounds__(T) void k_finish_stage(
@@ -684,13 +855,10 @@ __global__ __launch_bounds__(T) void k_finish_stage(
 // K[kx][|ky|] (6 components x NZ offsets); sy = -1 on the mirrored half
 // (xy and yz are odd in ky); xz, yz are odd in the z offset.
 template <int NZ>
-__device__ __forceinline__ void kernel_product(const float* __restrict__ Kp,
-                                               float sy,
-                                               const float2 (&M)[3 * NZ],
-                                               float2 (&Hf)[3 * NZ]) {
-  float kk[6 * NZ];
-#pragma unroll
-  for (int q = 0; q < 6 * NZ; ++q) kk[q] = Kp[q];
+__device__ __forceinline__ void kernel_product_k(const float (&kk)[6 * NZ],
+                                                 float sy,
+                                                 const float2 (&M)[3 * NZ],
+                                                 float2 (&Hf)[3 * NZ]) {
 #pragma unroll
   for (int q = 0; q < 3 * NZ; ++q) Hf[q] = make_float2(0.f, 0.f);
 #pragma unroll
@@ -718,6 +886,23 @@ __device__ __forceinline__ void kernel_product(const float* __restrict__ Kp,
   }
 }
 
+template <int NZ>
+__device__ __forceinline__ void kernel_load(const float* __restrict__ Kp,
+                                            float (&kk)[6 * NZ]) {
+#pragma unroll
+  for (int q = 0; q < 6 * NZ; ++q) kk[q] = Kp[q];
+}
+
+template <int NZ>
+__device__ __forceinline__ void kernel_product(const float* __restrict__ Kp,
+                                               float sy,
+                                               const float2 (&M)[3 * NZ],
+                                               float2 (&Hf)[3 * NZ]) {
+  float kk[6 * NZ];
+  kernel_load<NZ>(Kp, kk);
+  kernel_product_k<NZ>(kk, sy, M, Hf);
+}
+
 // Spectral pass of column block `blk` (a workgroup of T threads; LDS
 // `lds_all` as sized by the plan).  LP > 0: log2(Py) fixed at compile time
 // (specialised FFT addressing).
@@ -736,7 +921,7 @@ __device__ __forceinline__ void yspec_l_body(
   if constexpr (TT) fft_tt_build<VPTY, true, LP>(twl, tw, logTw);
   else stage_twiddles(twl, tw, logTw);
   // workgroup 0 also finishes the coupling sum of this stage
-  if (blk == 0) {
+  if (blk == 0 && !P.modes) {
     finish_cavity(P, ctl, partials, nblk_f, stage, mode, red);
     __syncthreads();
   }
@@ -795,49 +980,80 @@ __device__ __forceinline__ void yspec_l_body(
   __syncthreads();
   fft_lds<VPTY, true, LP, true, false, 4, TT>(lds, P.logPy, ncol, twl, logTw,
                                              -1.f);
-  // pointwise product: per (w, ky), all 3*nz values
+  // pointwise product, all 3*nz values at a (w, ky).  A thread takes the
+  // mirrored pair ky = kh, Py - kh (kh in 1 .. Py/2 - 1), which share the
+  // kernel row |ky| = kh (odd-in-ky parts flip), or for kh = 0 the two
+  // self-mirrored rows ky = 0 and Py/2.
   const int Hy = P.Hy;
-  for (int e = threadIdx.x; e < Wb * Py; e += T) {
-    const int w = e >> lpy, ky = e & (Py - 1);
+  // (Py = 1: the single row ky = 0 only)
+  const int Ph = Py >> 1, nkh = Py >= 2 ? Ph : 1;
+  const int lph = Py >= 2 ? lpy - 1 : 0, nself = Py >= 2 ? 2 : 1;
+  for (int e = threadIdx.x; e < Wb * nkh; e += T) {
+    const int w = e >> lph, kh = e & (nkh - 1);
     float2 M[nz3], Hf[nz3];
     if (has_pair && w == 0) {
       // slot 0: split Z = X0 + i XN at (ky, -ky), apply each column's
       // kernel, recombine; the results are real sequences, so
-      // W[-ky] = conj(Y0[ky]) + i conj(YN[ky]).  One thread per pair.
+      // W[-ky] = conj(Y0[ky]) + i conj(YN[ky]).  One pass per mirrored
+      // pair: ky = kh, and for kh = 0 also ky = Py/2.
       // (Y0 is parked in LDS while YN is formed: fewer live registers)
-      if (2 * ky > Py) continue;
-      const int km = (Py - ky) & (Py - 1);
-      float2 XN[nz3];
+#pragma unroll 1
+      for (int r = 0; r < (kh == 0 ? nself : 1); ++r) {
+        const int ky = r == 0 ? kh : Ph;
+        const int km = (Py - ky) & (Py - 1);
+        float2 XN[nz3];
 #pragma unroll
-      for (int q = 0; q < nz3; ++q) {
-        const float2 z = lds[pidx(q * Py + ky)];
-        const float2 zm = lds[pidx(q * Py + km)];
-        M[q] = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
-        XN[q] = make_float2(0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x));
-      }
-      kernel_product<NZ>(K + (size_t)ky * 6 * NZ, 1.f, M, Hf);
+        for (int q = 0; q < nz3; ++q) {
+          const float2 z = lds[pidx(q * Py + ky)];
+          const float2 zm = lds[pidx(q * Py + km)];
+          M[q] = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
+          XN[q] = make_float2(0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x));
+        }
+        kernel_product<NZ>(K + (size_t)ky * 6 * NZ, 1.f, M, Hf);
 #pragma unroll
-      for (int q = 0; q < nz3; ++q) lds[pidx(q * Py + ky)] = Hf[q];
-      kernel_product<NZ>(K + ((size_t)hxn * Hy + ky) * 6 * NZ, 1.f, XN, Hf);
+        for (int q = 0; q < nz3; ++q) lds[pidx(q * Py + ky)] = Hf[q];
+        kernel_product<NZ>(K + ((size_t)hxn * Hy + ky) * 6 * NZ, 1.f, XN,
+                           Hf);
 #pragma unroll
-      for (int q = 0; q < nz3; ++q) {
-        const float2 y0 = lds[pidx(q * Py + ky)];
-        lds[pidx(q * Py + ky)] = make_float2(y0.x - Hf[q].y, y0.y + Hf[q].x);
-        if (km != ky)
-          lds[pidx(q * Py + km)] = make_float2(y0.x + Hf[q].y,
-                                               -y0.y + Hf[q].x);
+        for (int q = 0; q < nz3; ++q) {
+          const float2 y0 = lds[pidx(q * Py + ky)];
+          lds[pidx(q * Py + ky)] = make_float2(y0.x - Hf[q].y, y0.y + Hf[q].x);
+          if (km != ky)
+            lds[pidx(q * Py + km)] = make_float2(y0.x + Hf[q].y,
+                                                 -y0.y + Hf[q].x);
+        }
       }
       continue;
     }
     const int kx = kx0 + w;
-    const bool lo = ky <= (Py >> 1);
-    const int kyi = lo ? ky : Py - ky;
+    const int base = w * nz3 * Py;
+    float kk[6 * NZ];
+    if (kh == 0) {
+      // ky = 0 and ky = Py/2: each its own mirror, even parts only
+#pragma unroll 1
+      for (int r = 0; r < nself; ++r) {
+        const int ky = r * Ph;
+        kernel_load<NZ>(K + ((size_t)kx * Hy + ky) * 6 * NZ, kk);
 #pragma unroll
-    for (int q = 0; q < nz3; ++q) M[q] = lds[pidx((w * nz3 + q) * Py + ky)];
-    kernel_product<NZ>(K + ((size_t)kx * Hy + kyi) * 6 * NZ,
-                       lo ? 1.f : -1.f, M, Hf);   // odd-in-ky parts flip
+        for (int q = 0; q < nz3; ++q) M[q] = lds[pidx(base + q * Py + ky)];
+        kernel_product_k<NZ>(kk, 1.f, M, Hf);
 #pragma unroll
-    for (int q = 0; q < nz3; ++q) lds[pidx((w * nz3 + q) * Py + ky)] = Hf[q];
+        for (int q = 0; q < nz3; ++q) lds[pidx(base + q * Py + ky)] = Hf[q];
+      }
+      continue;
+    }
+    kernel_load<NZ>(K + ((size_t)kx * Hy + kh) * 6 * NZ, kk);
+#pragma unroll
+    for (int q = 0; q < nz3; ++q) M[q] = lds[pidx(base + q * Py + kh)];
+    kernel_product_k<NZ>(kk, 1.f, M, Hf);
+#pragma unroll
+    for (int q = 0; q < nz3; ++q) lds[pidx(base + q * Py + kh)] = Hf[q];
+    const int km = Py - kh;
+#pragma unroll
+    for (int q = 0; q < nz3; ++q) M[q] = lds[pidx(base + q * Py + km)];
+    kernel_product_k<NZ>(kk, -1.f, M, Hf);   // odd-in-ky parts flip
+#pragma unroll
+    for (int q = 0; q < nz3; ++q) lds[pidx(base + q * Py + km)] = Hf[q];
   }
   __syncthreads();
   fft_lds<VPTY, true, LP, false, true, 4, TT>(lds, P.logPy, ncol, twl, logTw,
@@ -910,7 +1126,7 @@ __global__ __launch_bounds__(T, 4) void k_yspec_h(
   float2* twl = lds_all;
   float2* lds = lds_all + lds_twiddles(logTw);
   stage_twiddles(twl, tw, logTw);
-  if (blockIdx.x == 0) {
+  if (blockIdx.x == 0 && !P.modes) {
     finish_cavity(P, ctl, partials, nblk_f, stage, mode, red);
     __syncthreads();
   }
@@ -1071,7 +1287,7 @@ __device__ __forceinline__ void yspec_w_body(
     int logTw, const double* __restrict__ partials, int nblk_f, int stage,
     int mode, int blk, float2* lds) {
   __shared__ double red[16];
-  if (blk == 0) {
+  if (blk == 0 && !P.modes) {
     finish_cavity(P, ctl, partials, nblk_f, stage, mode, red);
     __syncthreads();
   }
@@ -1139,8 +1355,32 @@ __device__ __forceinline__ void field_cells_t(const Prm& P,
   const float bex = P.bx + fd * P.fdx, bey = P.by + fd * P.fdy,
               bez = P.bz + fd * P.fdz;
   const float gcav = (float)(2.0 * ctl->as_re[stage]);
-  const float bcx = P.brx * gcav, bcy = P.bry * gcav, bcz = P.brz * gcav;
+  float bcx = P.brx * gcav, bcy = P.bry * gcav, bcz = P.brz * gcav;
   const float* bmap = GEN ? P.brms_map : nullptr;
+  // multimode cavity: sum_k B_rms,k 2 Re alpha_k (uniform vectors), or per
+  // cell over the modes' maps
+  float gk[kMaxModes];
+  int nmodes = 0;
+  bool mmap = false;
+  if (GEN && P.modes) {
+    const Modes& M = *P.modes;
+    nmodes = M.n;
+    mmap = M.any_map != 0;
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+    for (int k = 0; k < kMaxModes; ++k) {
+      const double g = k < nmodes ? 2.0 * ctl->mas_re[stage][k] : 0.0;
+      gk[k] = (float)g;
+      if (k < nmodes && !M.map[k]) {   // uniform modes: one vector
+        sx += M.br[k][0] * g;
+        sy += M.br[k][1] * g;
+        sz += M.br[k][2] * g;
+      }
+    }
+    bcx = (float)sx;
+    bcy = (float)sy;
+    bcz = (float)sz;
+  }
   double acc[3] = {0.0, 0.0, 0.0};
   float emax = 0.f;
   const int ncellb = R * nx;
@@ -1165,6 +1405,17 @@ __device__ __forceinline__ void field_cells_t(const Prm& P,
       Bx = bex + bmap[i] * gcav;
       By = bey + bmap[N + i] * gcav;
       Bz = bez + bmap[2 * N + i] * gcav;
+    }
+    if (GEN && mmap) {   // per-cell fields of the modes that have maps
+#pragma unroll
+      for (int k = 0; k < kMaxModes; ++k) {
+        if (k >= nmodes) break;
+        if (const float* b = P.modes->map[k]) {
+          Bx += b[i] * gk[k];
+          By += b[N + i] * gk[k];
+          Bz += b[2 * N + i] * gk[k];
+        }
+      }
     }
     if (GEN && P.fdrive_map) {   // field drive shaped per cell
       Bx += fd * P.fdrive_map[i];
@@ -1191,6 +1442,31 @@ __device__ __forceinline__ void field_cells_t(const Prm& P,
       if (z < nz - 1 && (!g || g[i + plane] > 0.f)) { lx += (ys[i + plane] - mx) * P.idz2; ly += (ys[N + i + plane] - my) * P.idz2; lz += (ys[2 * N + i + plane] - mz) * P.idz2; }
       const float ce = P.aex2 / msv;
       Bx += ce * lx; By += ce * ly; Bz += ce * lz;
+      if (GEN && (P.dmi_i != 0.f || P.dmi_b != 0.f)) {
+        // Dzyaloshinskii-Moriya: over the bonds to existing magnetic
+        // neighbours j, B += (1/Ms) sum_j c_ij x m_j with
+        // c_ij = D_int (z x e_ij)/d - D_bulk e_ij/d; per axis the two
+        // neighbours enter as c x (m_{i+e} - m_{i-e}), a missing one omitted
+        float ax = 0.f, ay = 0.f, az = 0.f;   // x bonds
+        float bx = 0.f, by = 0.f, bz = 0.f;   // y bonds
+        float cx = 0.f, cy = 0.f, cz = 0.f;   // z bonds
+        if (x < nx - 1 && (!g || g[i + 1] > 0.f)) { ax += ys[i + 1]; ay += ys[N + i + 1]; az += ys[2 * N + i + 1]; }
+        if (x > 0 && (!g || g[i - 1] > 0.f)) { ax -= ys[i - 1]; ay -= ys[N + i - 1]; az -= ys[2 * N + i - 1]; }
+        if (y < ny - 1 && (!g || g[i + nx] > 0.f)) { bx += ys[i + nx]; by += ys[N + i + nx]; bz += ys[2 * N + i + nx]; }
+        if (y > 0 && (!g || g[i - nx] > 0.f)) { bx -= ys[i - nx]; by -= ys[N + i - nx]; bz -= ys[2 * N + i - nx]; }
+        if (z < nz - 1 && (!g || g[i + plane] > 0.f)) { cx += ys[i + plane]; cy += ys[N + i + plane]; cz += ys[2 * N + i + plane]; }
+        if (z > 0 && (!g || g[i - plane] > 0.f)) { cx -= ys[i - plane]; cy -= ys[N + i - plane]; cz -= ys[2 * N + i - plane]; }
+        const float di = P.dmi_i / msv, db = P.dmi_b / msv;
+        // x bonds: c = (-D_bulk, D_int, 0)/dx
+        const float x0 = -db * P.idx1, x1 = di * P.idx1;
+        Bx += x1 * az; By -= x0 * az; Bz += x0 * ay - x1 * ax;
+        // y bonds: c = (-D_int, -D_bulk, 0)/dy
+        const float y0c = -di * P.idy1, y1c = -db * P.idy1;
+        Bx += y1c * bz; By -= y0c * bz; Bz += y0c * by - y1c * bx;
+        // z bonds: c = (0, 0, -D_bulk)/dz
+        const float z2 = -db * P.idz1;
+        Bx -= z2 * cy; By += z2 * cx;
+      }
       // uniaxial anisotropy (2 Ku / Ms) (u.m) u
       const float kuv = P.ku_map ? 2.f * P.ku_map[i] : P.ku2;
       const float um = P.ux * mx + P.uy * my + P.uz * mz;
@@ -1457,8 +1733,12 @@ __device__ __forceinline__ void finish_step_body(
     // only when finite; otherwise the run stops with y_n, t and alpha those
     // of the last accepted step
     const double s0 = S[0], s1 = S[1], s2 = S[2];
-    if (!(isfinite(s0) && isfinite(s1) && isfinite(s2) &&
-          isfinite(c->anext_re) && isfinite(c->anext_im))) {
+    bool fin = isfinite(s0) && isfinite(s1) && isfinite(s2) &&
+               isfinite(c->anext_re) && isfinite(c->anext_im);
+    if (P.modes)
+      for (int k = 0; k < P.modes->n; ++k)
+        fin = fin && isfinite(c->manext_re[k]) && isfinite(c->manext_im[k]);
+    if (!fin) {
       c->status = ST_NONFINITE;
       c->done = 1;
       if (ndone) atomicAdd(ndone, 1);
@@ -1467,6 +1747,11 @@ __device__ __forceinline__ void finish_step_body(
     c->t = c->t + c->dt;
     c->a_re = c->anext_re;
     c->a_im = c->anext_im;
+    if (P.modes)
+      for (int k = 0; k < P.modes->n; ++k) {
+        c->ma_re[k] = c->mas_re[1][k] = c->manext_re[k];
+        c->ma_im[k] = c->mas_im[1][k] = c->manext_im[k];
+      }
     c->mem_n += 1;
     c->as_re[1] = c->a_re;
     c->as_im[1] = c->a_im;
@@ -1481,13 +1766,12 @@ __device__ __forceinline__ void finish_step_body(
     if (c->max_accepted > 0 && c->accepted >= c->max_accepted) c->done = 1;
     if (c->rec_every > 0 && (c->accepted % c->rec_every) == 0 &&
         c->nrec < c->rec_cap) {
-      double* row = rec + 6 * (size_t)c->nrec;
+      double* row = rec + (size_t)P.recw * c->nrec;
       row[0] = c->t;
       row[1] = s0 / P.nmag;
       row[2] = s1 / P.nmag;
       row[3] = s2 / P.nmag;
-      row[4] = c->a_re;
-      row[5] = c->a_im;
+      record_amplitudes(P, c, row);
       c->nrec += 1;
     }
   } else {
@@ -1506,6 +1790,13 @@ __device__ __forceinline__ void finish_step_body(
       c->as_im[1] = c->a_im;
       c->ka_re[1] = c->ka_re[7];
       c->ka_im[1] = c->ka_im[7];
+      if (P.modes)
+        for (int k = 0; k < P.modes->n; ++k) {
+          c->ma_re[k] = c->mas_re[1][k] = c->mas_re[7][k];
+          c->ma_im[k] = c->mas_im[1][k] = c->mas_im[7][k];
+          c->mka_re[1][k] = c->mka_re[7][k];
+          c->mka_im[1][k] = c->mka_im[7][k];
+        }
       c->accepted += 1;
       c->pending_accept = 1;
       c->prev_rej = 0;
@@ -1529,6 +1820,11 @@ __device__ __forceinline__ void finish_step_body(
     // second stage amplitude of the next attempt
     c->as_re[2] = c->a_re + dtn * c_dp_a[2][0] * c->ka_re[1];
     c->as_im[2] = c->a_im + dtn * c_dp_a[2][0] * c->ka_im[1];
+    if (P.modes)
+      for (int k = 0; k < P.modes->n; ++k) {
+        c->mas_re[2][k] = c->ma_re[k] + dtn * c_dp_a[2][0] * c->mka_re[1][k];
+        c->mas_im[2][k] = c->ma_im[k] + dtn * c_dp_a[2][0] * c->mka_im[1][k];
+      }
   }
   if (ndone && c->done) atomicAdd(ndone, 1);
 }
@@ -1651,13 +1947,12 @@ __device__ __forceinline__ void begin_body(
   sum_partials<3>(partials, nblk, S, red);
   if (threadIdx.x != 0) return;
   {
-    double* row = rec + 6 * (size_t)ctl->nrec;
+    double* row = rec + (size_t)P.recw * ctl->nrec;
     row[0] = ctl->t;
     row[1] = S[0] / P.nmag;
     row[2] = S[1] / P.nmag;
     row[3] = S[2] / P.nmag;
-    row[4] = ctl->a_re;
-    row[5] = ctl->a_im;
+    record_amplitudes(P, ctl, row);
     ctl->nrec += 1;
   }
   ctl->pending_accept = 0;
@@ -1700,13 +1995,12 @@ __global__ __launch_bounds__(T) void k_record(
   sum_partials<3>(partials, gridDim.x, S, red);
   if (threadIdx.x != 0) return;
   if (ctl->nrec < ctl->rec_cap) {
-    double* row = rec + 6 * (size_t)ctl->nrec;
+    double* row = rec + (size_t)P.recw * ctl->nrec;
     row[0] = ctl->t;
     row[1] = S[0] / P.nmag;
     row[2] = S[1] / P.nmag;
     row[3] = S[2] / P.nmag;
-    row[4] = ctl->a_re;
-    row[5] = ctl->a_im;
+    record_amplitudes(P, ctl, row);
     ctl->nrec += 1;
   }
   ctl->cnt_rec = 0;

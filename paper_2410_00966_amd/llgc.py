@@ -29,7 +29,8 @@ EXPORTED = ("llgc_create", "llgc_destroy", "llgc_last_error",
             "llgc_plan_info", "llgc_create_ex", "llgc_batch_create",
             "llgc_batch_destroy", "llgc_batch_last_error",
             "llgc_batch_instance", "llgc_batch_run", "llgc_set_timing_only",
-            "llgc_autotune", "llgc_eval_rhs_noalloc")
+            "llgc_autotune", "llgc_eval_rhs_noalloc", "llgc_set_modes",
+            "llgc_set_mode_amplitudes", "llgc_get_mode_amplitudes")
 PLAN_BATCH = 1
 
 
@@ -64,7 +65,17 @@ class Params(ctypes.Structure):
         ("dt_max", ctypes.c_double), ("cavity_mode", ctypes.c_int32),
         ("brms_map", _FP), ("ku2", ctypes.c_double),
         ("no_precession", ctypes.c_int32), ("fdrive_map", _FP),
+        ("dmi_int", ctypes.c_double), ("dmi_bulk", ctypes.c_double),
     ]
+
+
+class Mode(ctypes.Structure):
+    _fields_ = [("brms", _D3), ("brms_map", _FP),
+                ("wc", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("x0", ctypes.c_double), ("p0", ctypes.c_double),
+                ("cdrive_kind", ctypes.c_int32),
+                ("cdrive_amp", ctypes.c_double),
+                ("cdrive_w", ctypes.c_double)]
 
 
 class RunInfo(ctypes.Structure):
@@ -128,6 +139,9 @@ def load():
         "llgc_autotune": ([vp, i32, P(i32)], ctypes.c_int),
         "llgc_eval_rhs_noalloc": ([vp, vp, dbl, dbl, dbl, vp, vp, P(dbl)],
                                   ctypes.c_int),
+        "llgc_set_modes": ([vp, i32, P(Mode)], ctypes.c_int),
+        "llgc_set_mode_amplitudes": ([vp, P(dbl)], ctypes.c_int),
+        "llgc_get_mode_amplitudes": ([vp, P(dbl)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -170,6 +184,8 @@ def make_params(prob, ms_map=None, ku_map=None, brms_map=None,
     p.ku2 = getattr(prob, "ku2", 0.0)
     p.no_precession = 0 if getattr(prob, "precession", 1) else 1
     p.fdrive_map = fdrive_map.data_ptr() if fdrive_map is not None else None
+    p.dmi_int = getattr(prob, "dmi_int", 0.0)
+    p.dmi_bulk = getattr(prob, "dmi_bulk", 0.0)
     p.dt, p.tol = prob.dt, prob.tol
     p.dt_min, p.dt_max = prob.dt_min, prob.dt_max
     return p
@@ -231,10 +247,58 @@ class Sim:
         p = make_params(prob, msm, kum, brm, fdm)
         self._check(self.L.llgc_set_params(self.h, ctypes.byref(p)),
                     "llgc_set_params")
+        modes = getattr(prob, "modes", None)
+        if modes is not None or getattr(self, "nmodes", 0):
+            self.set_modes(modes or [])
         self.stream.synchronize()
 
+    def set_modes(self, modes):
+        """Multimode cavity (llgc_set_modes): `modes` is a list of
+        inputs.Mode (maps: (3, nz, ny, nx) arrays); [] = the single mode of
+        the parameters.  Amplitudes start at (x0 - i p0)/2 of each mode."""
+        n = len(modes)
+        arr = (Mode * max(n, 1))()
+        keep = []
+        for k, md in enumerate(modes):
+            arr[k].brms = _D3(*md.brms)
+            if md.brms_map is not None:
+                bm = self._dev(md.brms_map).reshape(-1)
+                keep.append(bm)
+                arr[k].brms_map = bm.data_ptr()
+            else:
+                arr[k].brms_map = None
+            arr[k].wc, arr[k].kappa = md.wc, md.kappa
+            arr[k].x0, arr[k].p0 = md.x0, md.p0
+            arr[k].cdrive_kind = md.cdrive_kind
+            arr[k].cdrive_amp = md.cdrive_amp
+            arr[k].cdrive_w = md.cdrive_w
+        self._check(self.L.llgc_set_modes(self.h, n, arr), "llgc_set_modes")
+        self.nmodes = n
+        self.stream.synchronize()
+
+    def mode_amplitudes(self):
+        a = (ctypes.c_double * (2 * self.nmodes))()
+        self._check(self.L.llgc_get_mode_amplitudes(self.h, a),
+                    "llgc_get_mode_amplitudes")
+        return np.array(a[0::2]) + 1j * np.array(a[1::2])
+
+    def set_mode_amplitudes(self, a):
+        a = np.asarray(a, dtype=complex).reshape(-1)
+        if a.size == 1 and self.nmodes > 1:
+            a = np.full(self.nmodes, a[0])
+        buf = (ctypes.c_double * (2 * self.nmodes))()
+        for k in range(self.nmodes):
+            buf[2 * k], buf[2 * k + 1] = a[k].real, a[k].imag
+        self._check(self.L.llgc_set_mode_amplitudes(self.h, buf),
+                    "llgc_set_mode_amplitudes")
+
     def set_state(self, m, t=0.0, a=0j):
+        """m, t and the amplitude (with several modes: one per mode, or one
+        value for all)."""
         md = self._dev(m).reshape(self.shape)
+        if getattr(self, "nmodes", 0):
+            self.set_mode_amplitudes(a)
+            a = 0j
         a = complex(a)
         self._check(self.L.llgc_set_state(self.h, md.data_ptr(), t, a.real,
                                           a.imag), "llgc_set_state")
@@ -249,6 +313,8 @@ class Sim:
                                           ctypes.byref(t), a),
                     "llgc_get_state")
         self.stream.synchronize()
+        if getattr(self, "nmodes", 0):
+            return m, t.value, self.mode_amplitudes()
         return m, t.value, complex(a[0], a[1])
 
     def reset_cavity(self, x0=0.0, p0=0.0):
@@ -263,7 +329,9 @@ class Sim:
         """Returns (records (n, 6) float64, info dict)."""
         if record_every > 0 and rec_cap <= 0:
             rec_cap = (nsteps // record_every + 2) if nsteps else 100000
-        rec = np.zeros((max(rec_cap, 1), 6))
+        width = 4 + 2 * getattr(self, "nmodes", 0) if getattr(
+            self, "nmodes", 0) else 6
+        rec = np.zeros((max(rec_cap, 1), width))
         nrec = ctypes.c_int64()
         info = RunInfo()
         rc = self.L.llgc_run(
@@ -284,15 +352,27 @@ class Sim:
                     t=info.t, dt=info.dt, last_err=info.last_err)
 
     def eval_rhs(self, m, a=0j, t=0.0, want_field=True):
+        """One right-hand side: (dm/dt, B_eff, d alpha/dt).  With several
+        modes `a` (one per mode) is set as the current amplitudes first and
+        d alpha/dt is an array over the modes."""
         md = self._dev(m).reshape(self.shape)
         dm = self.torch.empty_like(md)
         B = self.torch.empty_like(md) if want_field else None
-        da = (ctypes.c_double * 2)()
+        nm = getattr(self, "nmodes", 0)
+        if nm:
+            # the evaluation reads the current amplitudes: set, then restore
+            keep = self.mode_amplitudes()
+            self.set_mode_amplitudes(a)
+            a = 0j
+        da = (ctypes.c_double * max(2, 2 * nm))()
         a = complex(a)
         self._check(self.L.llgc_eval_rhs(
             self.h, md.data_ptr(), a.real, a.imag, float(t), dm.data_ptr(),
             B.data_ptr() if B is not None else None, da), "llgc_eval_rhs")
         self.stream.synchronize()
+        if nm:
+            self.set_mode_amplitudes(keep)
+            return dm, B, np.array(da[0::2]) + 1j * np.array(da[1::2])
         return dm, B, complex(da[0], da[1])
 
     def eval_rhs_noalloc(self, m, dm, B=None, a=0j, t=0.0):
