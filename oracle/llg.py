@@ -522,6 +522,74 @@ class CavityLLG:
         return m, a, t, np.array(rec), np.array(dts), dict(accepted=nacc,
                                                            rejected=nrej)
 
+    def relax(self, m0, torque_tol=0.0, max_steps=100000, block=8):
+        """Energy minimisation by damped dynamics, the relax() the paper's
+        example script calls before it runs (appendix "Micromagnetic
+        simulations with Mumax3-cQED"; the relax of the Mumax3 reference):
+        the precession term off, the cavity decoupled (no cavity field, the
+        amplitude left as it is) and the drives off, Dormand-Prince 5(4)
+        steps (tolerance and first step of the problem) in blocks of
+        `block` accepted steps.  After each block the torque of the current
+        state is taken: the relaxation stops when the largest |dm/dt| falls
+        below `torque_tol` (> 0), when the mean of |dm/dt|^2 over the
+        magnetic cells has not decreased since the previous block, or after
+        `max_steps` accepted steps.  Returns (m, stats)."""
+        import dataclasses
+        p = self.p
+        q = dataclasses.replace(p, precession=0, brms=(0.0, 0.0, 0.0),
+                                brms_map=None, modes=None,
+                                cdrive_kind=DRIVE_NONE, fdrive_kind=DRIVE_NONE,
+                                fdrive_map=None, cavity_mode=0)
+        o = CavityLLG(q, demag=self.demag_mode or "auto")
+        m = np.asarray(m0, dtype=np.float64) * self.inside[None]
+        a, t = 0j, 0.0
+        dt = p.dt
+        tol = p.tol
+        k1m, k1a = o.rhs(m, a, t)
+        prev_rej = False
+        nacc = nrej = nblk = 0
+        prev = None
+        mx = math.inf
+        while True:
+            nb = min(block, max_steps - nacc)
+            if nb <= 0:
+                break
+            done = 0
+            while done < nb:
+                h = dt
+                m5, a5, err, k7m, k7a = o.dp45_attempt(m, a, t, h, k1m, k1a)
+                if not (math.isfinite(err) and np.isfinite(m5).all()):
+                    err = math.inf
+                if err <= tol:
+                    fac = 5.0 if err == 0.0 else min(5.0, max(
+                        0.2, 0.9 * (tol / err) ** 0.2))
+                    if prev_rej:
+                        fac = min(fac, 1.0)
+                    t, m, a = t + h, normalise(m5), a5
+                    k1m, k1a = k7m, k7a
+                    nacc += 1
+                    done += 1
+                    prev_rej = False
+                else:
+                    fac = 0.2 if not math.isfinite(err) else max(
+                        0.2, 0.9 * (tol / err) ** 0.2)
+                    prev_rej = True
+                    nrej += 1
+                dt = min(p.dt_max, h * fac)
+                if dt < p.dt_min:
+                    raise FloatingPointError("time step underflow")
+            nblk += 1
+            tq, _ = o.rhs(m, a, t)
+            n2 = (tq * tq).sum(axis=0)[self.inside]
+            mean2, mx = float(n2.mean()), float(np.sqrt(n2.max()))
+            if torque_tol > 0.0 and mx < torque_tol:
+                break
+            if prev is not None and mean2 >= prev:
+                break
+            prev = mean2
+        return m, dict(accepted=nacc, rejected=nrej, blocks=nblk,
+                       max_torque=mx)
+
     def run_dp45_replay(self, m0, a0, dts, t0=0.0):
         """Dormand-Prince with a prescribed sequence of accepted step sizes
         (every step accepted, FSAL and renormalisation as in run_dp45)."""

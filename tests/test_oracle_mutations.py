@@ -198,3 +198,19 @@ def test_dmi_field_missing_factor_breaks_gradient_pin(monkeypatch):
     import test_oracle_dmi as TD
     with pytest.raises(AssertionError):
         TD.test_field_is_energy_gradient(0.0, 2e-3)
+
+
+def test_relax_dropping_anisotropy_breaks_stoner_wohlfarth(monkeypatch):
+    """A relax whose copy of the problem loses the anisotropy lands at the
+    field direction instead of the Stoner-Wohlfarth angle."""
+    import dataclasses
+    orig = dataclasses.replace
+
+    def replace(obj, **kw):
+        if "precession" in kw:
+            kw["ku1"] = 0.0
+        return orig(obj, **kw)
+    monkeypatch.setattr(dataclasses, "replace", replace)
+    import test_oracle_relax as TR
+    with pytest.raises(AssertionError):
+        TR.test_stoner_wohlfarth_equilibrium(0.05, 68.2, 10.0)
