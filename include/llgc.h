@@ -159,6 +159,23 @@ typedef struct {
  * or padded sizes beyond the on-chip FFT limits), LLGC_E_OOM, LLGC_E_HIP. */
 int llgc_create(const llgc_grid *grid, void *hip_stream, llgc_ctx **out);
 
+/* Energy minimisation by damped dynamics: the relax() the paper's example
+ * script calls before its run (appendix "Micromagnetic simulations with
+ * Mumax3-cQED"; the relax of Mumax3).  With the precession term off, the
+ * cavity decoupled (no cavity field; amplitudes kept) and the drives off,
+ * Dormand-Prince steps (params.tol, or 1e-6) run in blocks of 8 accepted
+ * steps; after each block the torque |dm/dt| of the current state is
+ * evaluated: with `torque_tol` > 0 (rad/s) the relaxation stops once its
+ * maximum is below it; with `torque_tol` <= 0, once the mean of |dm/dt|^2
+ * over the magnetic cells has not decreased since the previous block; in
+ * any case after `max_steps` accepted steps (<= 0: 100000).  m keeps the relaxed state;
+ * t, the cavity amplitudes, the step counters and every parameter are as
+ * before the call.  `max_torque` (host, may be NULL) receives the last
+ * block's largest |dm/dt|; `info` (may be NULL) the relaxation's steps.
+ * Errors: LLGC_E_STATE (no params/state), and as llgc_run. */
+int llgc_relax(llgc_ctx *ctx, double torque_tol, int64_t max_steps,
+               double *max_torque, llgc_run_info *info);
+
 /* ---------------------------------------------------------------------
  * Multimode cavity.  The paper simulates one mode at a time and notes that
  * a cavity of several modes follows by summing them (section

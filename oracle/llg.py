@@ -530,10 +530,11 @@ class CavityLLG:
         amplitude left as it is) and the drives off, Dormand-Prince 5(4)
         steps (tolerance and first step of the problem) in blocks of
         `block` accepted steps.  After each block the torque of the current
-        state is taken: the relaxation stops when the largest |dm/dt| falls
-        below `torque_tol` (> 0), when the mean of |dm/dt|^2 over the
-        magnetic cells has not decreased since the previous block, or after
-        `max_steps` accepted steps.  Returns (m, stats)."""
+        state is taken: with a threshold `torque_tol` > 0 the relaxation
+        stops once the largest |dm/dt| is below it; without one, once the
+        mean of |dm/dt|^2 over the magnetic cells has not decreased since
+        the previous block; in any case after `max_steps` accepted steps.
+        Returns (m, stats)."""
         import dataclasses
         p = self.p
         q = dataclasses.replace(p, precession=0, brms=(0.0, 0.0, 0.0),
@@ -582,9 +583,10 @@ class CavityLLG:
             tq, _ = o.rhs(m, a, t)
             n2 = (tq * tq).sum(axis=0)[self.inside]
             mean2, mx = float(n2.mean()), float(np.sqrt(n2.max()))
-            if torque_tol > 0.0 and mx < torque_tol:
-                break
-            if prev is not None and mean2 >= prev:
+            if torque_tol > 0.0:
+                if mx < torque_tol:
+                    break
+            elif prev is not None and mean2 >= prev:
                 break
             prev = mean2
         return m, dict(accepted=nacc, rejected=nrej, blocks=nblk,

@@ -1449,6 +1449,122 @@ int llgc_cavity_enabled(const llgc_ctx* c) {
   return (b[0] != 0.0 || b[1] != 0.0 || b[2] != 0.0) ? 1 : 0;
 }
 
+int llgc_relax(llgc_ctx* c, double torque_tol, int64_t max_steps,
+               double* max_torque, llgc_run_info* info) {
+  if (!c) return LLGC_E_ARG;
+  if (!c->have_params || !c->have_state)
+    return fail(c, LLGC_E_STATE, "set params and state before relax");
+  if (max_steps <= 0) max_steps = 100000;
+  Ctl h0{};
+  if (int r = ctl_read(c, &h0, c->ctl)) return r;
+  {
+    // the step controller starts afresh; the decoupled cavity is held at
+    // zero (its amplitude is restored afterwards), so it adds nothing to
+    // the step-size control
+    Ctl hs = h0;
+    hs.prev_rej = 0;
+    hs.a_re = hs.a_im = hs.as_re[1] = hs.as_im[1] = 0.0;
+    for (int k = 0; k < kMaxModes; ++k)
+      hs.ma_re[k] = hs.ma_im[k] = hs.mas_re[1][k] = hs.mas_im[1][k] = 0.0;
+    if (int r = ctl_write(c, c->ctl, &hs)) return r;
+  }
+  // relaxation problem: precession off, cavity decoupled, drives off,
+  // Dormand-Prince; everything restored on the way out
+  struct Saved {
+    llgc_ctx* c;
+    llgc_params prm;
+    float *bm, *fm;
+    int nm;
+    ~Saved() {
+      c->prm = prm;
+      c->brms_map = bm;
+      c->fdrive_map = fm;
+      c->nmodes = nm;
+      fill_prm(c);
+      c->need_init = true;
+    }
+  } saved{c, c->prm, c->brms_map, c->fdrive_map, c->nmodes};
+  c->prm.no_precession = 1;
+  c->prm.method = LLGC_DP45;
+  c->prm.brms[0] = c->prm.brms[1] = c->prm.brms[2] = 0.0;
+  c->prm.cdrive_kind = LLGC_DRIVE_NONE;
+  c->prm.fdrive_kind = LLGC_DRIVE_NONE;
+  c->prm.cavity_mode = LLGC_CAVITY_ODE;
+  if (!(c->prm.tol > 0)) c->prm.tol = 1e-6;
+  c->brms_map = nullptr;
+  c->fdrive_map = nullptr;
+  c->nmodes = 0;
+  fill_prm(c);
+  c->need_init = true;
+  const int nblk = n_pointwise_blocks(c);
+  std::vector<double> part(2 * (size_t)nblk);
+  int64_t acc = 0, rej = 0, evals = 0, blocks = 0;
+  double prev = -1.0, mx2 = 0.0, last_err = 0.0, dt = 0.0;
+  int r = LLGC_OK;
+  while (acc < max_steps) {
+    const int64_t nb = std::min<int64_t>(8, max_steps - acc);
+    llgc_run_info bi{};
+    if ((r = llgc_run(c, nb, 1e300, 0, nullptr, 0, nullptr, &bi))) break;
+    acc += bi.accepted;
+    rej += bi.rejected;
+    evals += bi.rhs_evals;
+    last_err = bi.last_err;
+    dt = bi.dt;
+    ++blocks;
+    // torque of the current state (relaxation dynamics) into a k register
+    // that the next attempt recomputes before reading
+    if ((r = llgc_eval_rhs(c, c->yn, 0.0, 0.0, bi.t, c->kb[1], nullptr,
+                           nullptr)))
+      break;
+    hipLaunchKernelGGL(k_torque_stats<kT>, dim3(nblk), dim3(kT), 0,
+                       c->stream, c->P, c->kb[1], c->partials);
+    if ((r = check_launch(c, "k_torque_stats"))) break;
+    HIPCHK(c, hipMemcpyAsync(part.data(), c->partials,
+                             sizeof(double) * part.size(),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double s2 = 0.0;
+    mx2 = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+      s2 += part[2 * b];
+      mx2 = std::max(mx2, part[2 * b + 1]);
+    }
+    const double mean2 = s2 / (c->nmag > 0 ? c->nmag : (double)c->N);
+    if (torque_tol > 0) {
+      if (std::sqrt(mx2) < torque_tol) break;
+    } else if (prev >= 0.0 && mean2 >= prev) {
+      break;
+    }
+    prev = mean2;
+  }
+  // time, amplitudes and step counts as before the relaxation
+  Ctl h{};
+  if (int q = ctl_read(c, &h, c->ctl)) return q;
+  h.t = h0.t;
+  h.dt = h0.dt;
+  h.a_re = h.as_re[1] = h0.a_re;
+  h.a_im = h.as_im[1] = h0.a_im;
+  for (int k = 0; k < kMaxModes; ++k) {
+    h.ma_re[k] = h.mas_re[1][k] = h0.ma_re[k];
+    h.ma_im[k] = h.mas_im[1][k] = h0.ma_im[k];
+  }
+  h.accepted = h0.accepted;
+  h.rejected = h0.rejected;
+  h.mem_n = 0;
+  if (int q = ctl_write(c, c->ctl, &h)) return q;
+  if (max_torque) *max_torque = std::sqrt(mx2);
+  if (info) {
+    info->accepted = acc;
+    info->rejected = rej;
+    info->rhs_evals = evals;
+    info->t = h0.t;
+    info->dt = dt;
+    info->last_err = last_err;
+  }
+  (void)blocks;
+  return r;
+}
+
 int llgc_set_modes(llgc_ctx* c, int32_t n, const llgc_mode* modes) {
   if (!c) return LLGC_E_ARG;
   if (!c->have_params)

@@ -1969,6 +1969,44 @@ __global__ __launch_bounds__(T) void k_begin(
                 gridDim.x);
 }
 
+// ========================================================== k_torque_stats
+// Per-workgroup sum and maximum of |k_i|^2 over the magnetic cells of a
+// 3N-float field k (relax's stopping rule), to part[2 b], part[2 b + 1].
+template <int T>
+__global__ __launch_bounds__(T) void k_torque_stats(
+    Prm P, const float* __restrict__ k, double* __restrict__ part) {
+  __shared__ double red[16];
+  __shared__ double redm[16];
+  const int N = P.ncell;
+  double s2 = 0.0, mx = 0.0;
+  for (int i = blockIdx.x * T + threadIdx.x; i < N; i += gridDim.x * T) {
+    if (P.ms_map && !(P.ms_map[i] > 0.f)) continue;
+    const double a = k[i], b = k[N + i], c = k[2 * N + i];
+    const double n2 = a * a + b * b + c * c;
+    s2 += n2;
+    mx = fmax(mx, n2);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int o = 32; o > 0; o >>= 1) {
+    s2 += __shfl_xor(s2, o, 64);
+    mx = fmax(mx, __shfl_xor(mx, o, 64));
+  }
+  if (lane == 0) {
+    red[w] = s2;
+    redm[w] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int j = 0; j < T / 64; ++j) {
+      a += red[j];
+      b = fmax(b, redm[j]);
+    }
+    part[2 * blockIdx.x] = a;
+    part[2 * blockIdx.x + 1] = b;
+  }
+}
+
 // ================================================================ k_record
 // Average magnetisation of `m` written as one record row (t, <m>, a).
 template <int T>

@@ -30,7 +30,8 @@ EXPORTED = ("llgc_create", "llgc_destroy", "llgc_last_error",
             "llgc_batch_destroy", "llgc_batch_last_error",
             "llgc_batch_instance", "llgc_batch_run", "llgc_set_timing_only",
             "llgc_autotune", "llgc_eval_rhs_noalloc", "llgc_set_modes",
-            "llgc_set_mode_amplitudes", "llgc_get_mode_amplitudes")
+            "llgc_set_mode_amplitudes", "llgc_get_mode_amplitudes",
+            "llgc_relax")
 PLAN_BATCH = 1
 
 
@@ -142,6 +143,7 @@ def load():
         "llgc_set_modes": ([vp, i32, P(Mode)], ctypes.c_int),
         "llgc_set_mode_amplitudes": ([vp, P(dbl)], ctypes.c_int),
         "llgc_get_mode_amplitudes": ([vp, P(dbl)], ctypes.c_int),
+        "llgc_relax": ([vp, dbl, i64, P(dbl), P(RunInfo)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -343,6 +345,18 @@ class Sim:
             accepted=info.accepted, rejected=info.rejected,
             rhs_evals=info.rhs_evals, t=info.t, dt=info.dt,
             last_err=info.last_err)
+
+    def relax(self, torque_tol=0.0, max_steps=0):
+        """llgc_relax: damped-dynamics energy minimisation of m (t, the
+        cavity and the parameters unchanged).  Returns dict(accepted,
+        rejected, rhs_evals, max_torque)."""
+        info = RunInfo()
+        mt = ctypes.c_double()
+        self._check(self.L.llgc_relax(self.h, float(torque_tol),
+                                      int(max_steps), ctypes.byref(mt),
+                                      ctypes.byref(info)), "llgc_relax")
+        return dict(accepted=info.accepted, rejected=info.rejected,
+                    rhs_evals=info.rhs_evals, max_torque=mt.value)
 
     def step(self):
         info = RunInfo()

@@ -73,8 +73,8 @@ def test_textured_film_energy_falls_by_block():
         m, st = o.relax(m, max_steps=8)
         e.append(o.energy(m, 0j))
     assert (np.diff(e) < 0).all()
-    m, st = o.relax(m, torque_tol=1e6, max_steps=20000)
-    assert st["max_torque"] < 1e6 or st["blocks"] >= 2
+    m, st = o.relax(m, max_steps=20000)       # stagnation rule
+    assert st["blocks"] >= 2
     assert o.energy(m, 0j) < e[-1]
 
 
