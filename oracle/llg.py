@@ -38,6 +38,15 @@ numpy float64, in the order the paper states the problem.
     interior the central differences of (2D/Ms)(dm_z/dx, dm_z/dy,
     -dm_x/dx - dm_y/dy) and -(2D/Ms) curl m).  At an open edge the missing
     bond is omitted, as for exchange.
+  * Thermal field, the last effective-field term listed after Eq. (llg)
+    (Brown's fluctuating field): per cell and component a Gaussian of
+    variance 2 alpha kB T / (gamma Ms_i V_c dt), drawn afresh for every
+    time step and held over its Runge-Kutta stages (fixed-step RK4 only).
+    The normals come from the counter-based Philox4x32-10 generator of
+    Salmon et al. (SC'11), key (seed mod 2^32, seed >> 32), counter (cell,
+    step mod 2^32, step >> 32, 0), its four words made uniform as
+    (w + 1/2) 2^-32 and normal by the Box-Muller transform (pairs (u0, u1)
+    and (u2, u3); three of the four normals used).
   * A field drive shaped in space: B_ext += amp f(t) b(r), the form the
     paper's example script uses with the mode's field map as b(r) and a
     sinc pulse as f(t) (appendix "Micromagnetic simulations with
@@ -67,6 +76,34 @@ import numpy as np
 from . import demag as _demag
 
 DRIVE_NONE, DRIVE_SINC, DRIVE_CW = 0, 1, 2
+KB = 1.380649e-23        # J/K
+
+# Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+# easy as 1, 2, 3", SC'11): multipliers and Weyl key increments.
+_PHILOX_M = (0xD2511F53, 0xCD9E8D57)
+_PHILOX_W = (0x9E3779B9, 0xBB67AE85)
+
+
+def philox4x32(ctr, key, rounds=10):
+    """Philox4x32 on arrays: ctr (4, n) of uint32 values (held in uint64),
+    key (k0, k1).  Each round: (hi0, lo0) = M0 c0, (hi1, lo1) = M1 c2 (64-bit
+    products), c <- (hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0); the key is
+    bumped by the Weyl constants between rounds.  Returns (4, n) uint64
+    holding the 32-bit outputs."""
+    mask = np.uint64(0xFFFFFFFF)
+    c = [np.asarray(x, dtype=np.uint64) & mask for x in ctr]
+    k0, k1 = np.uint64(key[0]) & mask, np.uint64(key[1]) & mask
+    for r in range(rounds):
+        p0 = np.uint64(_PHILOX_M[0]) * c[0]
+        p1 = np.uint64(_PHILOX_M[1]) * c[2]
+        hi0, lo0 = p0 >> np.uint64(32), p0 & mask
+        hi1, lo1 = p1 >> np.uint64(32), p1 & mask
+        c = [hi1 ^ c[1] ^ k0, lo1, hi0 ^ c[3] ^ k1, lo0]
+        if r + 1 < rounds:
+            k0 = (k0 + np.uint64(_PHILOX_W[0])) & mask
+            k1 = (k1 + np.uint64(_PHILOX_W[1])) & mask
+    return np.stack(c)
+
 
 # Dormand & Prince (1980) RK5(4)7M tableau.
 DP_C = np.array([0.0, 1 / 5, 3 / 10, 4 / 5, 8 / 9, 1.0, 1.0])
@@ -170,6 +207,9 @@ class CavityLLG:
             if mode == "fft":
                 self.kf = _demag.demag_kernel_fft(self.nfull, self.shape)
         self.nevals = 0
+        self.noise_step = 0        # index of the step the thermal field of
+                                   # the next evaluation belongs to
+        self._dt_noise = prob.dt   # step size in the thermal variance
 
     # ---------------------------------------------------------------- fields
     def zeeman(self, t):
@@ -285,9 +325,36 @@ class CavityLLG:
             return np.tensordot(2.0 * np.real(a), self.mode_cells, axes=1)
         return self.brms_cells * (2.0 * a.real)
 
+    def thermal(self):
+        """Brown's field of step `noise_step` (zero without temperature)."""
+        p = self.p
+        T = getattr(p, "temperature", 0.0)
+        if T <= 0.0:
+            return 0.0
+        n = self.ms.size
+        seed = int(getattr(p, "seed", 0))
+        step = int(self.noise_step)
+        ctr = np.zeros((4, n), dtype=np.uint64)
+        ctr[0] = np.arange(n, dtype=np.uint64)
+        ctr[1] = step & 0xFFFFFFFF
+        ctr[2] = step >> 32
+        w = philox4x32(ctr, (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF))
+        u = (w.astype(np.float64) + 0.5) * 2.0 ** -32
+        r0 = np.sqrt(-2.0 * np.log(u[0]))
+        r1 = np.sqrt(-2.0 * np.log(u[2]))
+        eta = np.stack([r0 * np.cos(2 * math.pi * u[1]),
+                        r0 * np.sin(2 * math.pi * u[1]),
+                        r1 * np.cos(2 * math.pi * u[3])]).reshape(
+                            (3,) + self.shape)
+        sig = np.sqrt(2.0 * p.alpha * KB * T
+                      / (p.gamma * np.where(self.inside, self.ms, 1.0)
+                         * self.vc * self._dt_noise))
+        return eta * (sig * self.inside)[None]
+
     def effective_field(self, m, a, t):
         return (self.zeeman(t) + self.exchange(m) + self.anisotropy(m)
-                + self.dmi(m) + self.demag(m) + self.cavity_field(a))
+                + self.dmi(m) + self.demag(m) + self.cavity_field(a)
+                + self.thermal())
 
     def coupling_sum(self, m):
         """F = sum_i Ms_i m_i . B_rms,i  (A m^-1 T); several modes: the
@@ -419,8 +486,10 @@ class CavityLLG:
         a = self.amplitude(a0)
         t = t0
         rec = [self.record(t, m, a)] if record_every else []
+        self._dt_noise = dt
         for n in range(1, nsteps + 1):
             m, a = self.step_rk4(m, a, t, dt)
+            self.noise_step += 1
             t = t0 + n * dt
             if record_every and n % record_every == 0:
                 rec.append(self.record(t, m, a))
@@ -481,6 +550,8 @@ class CavityLLG:
                  dt_min=1e-20, dt_max=1e-10, max_attempts=10 ** 7):
         """Adaptive Dormand-Prince from t0 to t_end (last step truncated to
         land on t_end).  Returns m, a, t, records, accepted dt list, stats."""
+        if getattr(self.p, "temperature", 0.0) > 0.0:
+            raise ValueError("the thermal field needs fixed steps (RK4)")
         m = np.asarray(m0, dtype=np.float64) * self.inside[None]
         a = self.amplitude(a0)
         t = t0

@@ -22,6 +22,7 @@ import numpy as np
 GAMMA = 1.7595e11          # rad s^-1 T^-1
 HBAR = 1.05457182e-34      # J s
 MU0 = 4e-7 * math.pi       # T m / A
+KB = 1.380649e-23          # J / K (exact, SI 2019)
 
 DRIVE_NONE, DRIVE_SINC, DRIVE_CW = 0, 1, 2
 CAVITY_ODE, CAVITY_MEMORY = 0, 1
@@ -96,6 +97,9 @@ class Problem:
     # and bulk
     dmi_int: float = 0.0
     dmi_bulk: float = 0.0
+    # thermal field (K) and the seed of its counter-based generator
+    temperature: float = 0.0
+    seed: int = 0
     precession: int = 1
     # optional per-cell maps, float32 arrays of shape (nz, ny, nx)
     ms_map: Optional[np.ndarray] = None

@@ -214,3 +214,17 @@ def test_relax_dropping_anisotropy_breaks_stoner_wohlfarth(monkeypatch):
     import test_oracle_relax as TR
     with pytest.raises(AssertionError):
         TR.test_stoner_wohlfarth_equilibrium(0.05, 68.2, 10.0)
+
+
+def test_thermal_variance_with_ll_prefactor_breaks_boltzmann(monkeypatch):
+    """A thermal variance divided by 1 + alpha^2 (gamma of the LL form in
+    place of the gyromagnetic ratio; here alpha = 1, a factor 2) misses the
+    Langevin average."""
+    orig = L.CavityLLG.thermal
+
+    def thermal(self):
+        return orig(self) * math.sqrt(1.0 + self.p.alpha ** 2)
+    monkeypatch.setattr(L.CavityLLG, "thermal", thermal)
+    import test_oracle_thermal as TT
+    with pytest.raises(AssertionError):
+        TT.test_boltzmann_equilibrium_langevin()
