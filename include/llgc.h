@@ -142,6 +142,16 @@ typedef struct {
                               c_ij.(m_i x m_j), c_ij = D_int V_c (z x e_ij)
                               /d - D_bulk V_c e_ij/d, a missing neighbour's
                               bond omitted.  Not with llgc_adjoint. */
+  double temperature;      /* K; > 0 adds Brown's thermal field (the last
+                              effective-field term listed after Eq. (llg)):
+                              per cell and component a Gaussian of variance
+                              2 alpha kB T / (gamma Ms_i V_c dt), drawn
+                              afresh each RK4 step (counted from
+                              llgc_set_state) and held over its stages.
+                              RK4 only (LLGC_E_UNSUPPORTED with DP45); not
+                              with llgc_adjoint; off during llgc_relax. */
+  uint64_t seed;           /* key of the thermal field's Philox4x32-10
+                              generator (counter: cell, step) */
 } llgc_params;
 
 typedef struct {

@@ -701,6 +701,13 @@ void fill_prm(llgc_ctx* c) {
   P.idz1 = (float)(1.0 / c->dz);
   P.dmi_i = (float)p.dmi_int;
   P.dmi_b = (float)p.dmi_bulk;
+  P.therm = p.temperature > 0
+                ? 2.0 * p.alpha * 1.380649e-23 * p.temperature /
+                      ((p.gamma > 0 ? p.gamma : 1.7595e11) * c->dx * c->dy *
+                       c->dz)
+                : 0.0;
+  P.seed_lo = (unsigned int)(p.seed & 0xFFFFFFFFull);
+  P.seed_hi = (unsigned int)(p.seed >> 32);
   P.ms = (float)p.ms;
   P.ms_map = c->ms_map;
   P.brms_map = c->brms_map;
@@ -737,7 +744,8 @@ void fill_prm(llgc_ctx* c) {
   P.prec = p.no_precession ? 0.f : 1.f;
   P.plain = (!c->masked && !c->brms_map && !c->fdrive_map &&
              p.ku2 == 0.0 && !p.no_precession && !c->nmodes &&
-             p.dmi_int == 0.0 && p.dmi_bulk == 0.0) ? 1 : 0;
+             p.dmi_int == 0.0 && p.dmi_bulk == 0.0 &&
+             !(p.temperature > 0)) ? 1 : 0;
   P.modes = c->nmodes ? c->modes_dev : nullptr;
   P.mpart = c->mpart;
   P.recw = rec_width(c);
@@ -1288,6 +1296,10 @@ int llgc_set_params(llgc_ctx* c, const llgc_params* p) {
   if (p->cavity_mode == LLGC_CAVITY_MEMORY && c->nmodes)
     return fail(c, LLGC_E_UNSUPPORTED,
                 "the memory recursion is written for one mode");
+  if (!(p->temperature >= 0)) return fail(c, LLGC_E_ARG, "temperature < 0");
+  if (p->temperature > 0 && p->method != LLGC_RK4)
+    return fail(c, LLGC_E_UNSUPPORTED,
+                "the thermal field needs fixed steps (RK4)");
   c->prm = *p;
   const size_t nb = sizeof(float) * c->N;
   if (p->ms_map) {
@@ -1392,6 +1404,7 @@ int llgc_set_state(llgc_ctx* c, const float* m, double t, double are,
   h.status = 0;
   h.prev_rej = 0;
   h.mem_n = 0;
+  h.noise_n = 0;
   if (c->have_params) h.dt = c->prm.dt;
   if (int r = ctl_write(c, c->ctl, &h)) return r;
   c->have_state = true;
@@ -1490,6 +1503,7 @@ int llgc_relax(llgc_ctx* c, double torque_tol, int64_t max_steps,
   c->prm.cdrive_kind = LLGC_DRIVE_NONE;
   c->prm.fdrive_kind = LLGC_DRIVE_NONE;
   c->prm.cavity_mode = LLGC_CAVITY_ODE;
+  c->prm.temperature = 0.0;   // relax runs cold
   if (!(c->prm.tol > 0)) c->prm.tol = 1e-6;
   c->brms_map = nullptr;
   c->fdrive_map = nullptr;
@@ -1871,7 +1885,7 @@ int eval_ctl(llgc_ctx* c, double t, double are, double aim, Ctl* h) {
     }
   }
   h->t = t;
-  h->dt = 0.0;
+  h->dt = c->prm.dt;   // enters only the thermal field's variance
   h->a_re = are;
   h->a_im = aim;
   h->as_re[1] = are;
@@ -2302,6 +2316,8 @@ extern "C" int llgc_adjoint(llgc_ctx* c, int64_t n_steps, double dt,
     return fail(c, LLGC_E_UNSUPPORTED, "adjoint with a single cavity mode");
   if (c->prm.dmi_int != 0.0 || c->prm.dmi_bulk != 0.0)
     return fail(c, LLGC_E_UNSUPPORTED, "adjoint without DMI");
+  if (c->prm.temperature > 0)
+    return fail(c, LLGC_E_UNSUPPORTED, "adjoint without the thermal field");
   if (c->masked)
     return fail(c, LLGC_E_UNSUPPORTED, "adjoint without empty cells only");
   if (c->prm.ku2 != 0.0 || c->prm.no_precession)

@@ -50,6 +50,7 @@ struct Ctl {
   double mas_re[kMaxStages][kMaxModes], mas_im[kMaxStages][kMaxModes];
   double mka_re[kMaxStages][kMaxModes], mka_im[kMaxStages][kMaxModes];
   double manext_re[kMaxModes], manext_im[kMaxModes];    // RK4 end of step
+  long long noise_n;   // thermal field: index of the current RK4 step
 };
 
 enum { ST_OK = 0, ST_UNDERFLOW = 1, ST_NONFINITE = 2 };
@@ -85,6 +86,8 @@ struct Prm {
   float prec;                   // 1: precession term on, 0: off
   float dmi_i, dmi_b;           // DMI constants (J/m^2): interfacial, bulk
   float idx1, idy1, idz1;       // 1/d per axis
+  double therm;                 // 2 alpha kB T / (gamma V_c); 0: no thermal
+  unsigned int seed_lo, seed_hi;  // key of the thermal generator
   int plain;                    // none of: B_rms map, geometry, Ku2, no precession
   float alpha;
   int method;                   // 0 RK4, 1 DP45

@@ -94,6 +94,40 @@ __device__ inline double stage_c(const Prm& P, int s) {
   return P.method == 0 ? c_rk4_c[s] : c_dp_c[s];
 }
 
+// ----------------------------------------------------------- thermal field
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32 -> 64-bit
+// products with the Weyl-bumped key; counter (cell, step lo, step hi, 0),
+// key (seed lo, seed hi).  The four words become uniforms (w + 1/2) 2^-32
+// and, by Box-Muller on (u0, u1) and (u2, u3), normals, of which three are
+// Brown's field components (FP64, as the oracle draws them).
+__device__ __forceinline__ void thermal_normals(const Prm& P, int cell,
+                                                long long step, double& n0,
+                                                double& n1, double& n2) {
+  unsigned int c0 = (unsigned int)cell, c1 = (unsigned int)step,
+               c2 = (unsigned int)((unsigned long long)step >> 32), c3 = 0u;
+  unsigned int k0 = P.seed_lo, k1 = P.seed_hi;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const unsigned int lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const unsigned int lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const unsigned int d0 = hi1 ^ c1 ^ k0, d2 = hi0 ^ c3 ^ k1;
+    c0 = d0;
+    c1 = lo1;
+    c2 = d2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  const double s = 2.3283064365386963e-10;   // 2^-32
+  const double u0 = ((double)c0 + 0.5) * s, u1 = ((double)c1 + 0.5) * s;
+  const double u2 = ((double)c2 + 0.5) * s, u3 = ((double)c3 + 0.5) * s;
+  const double r0 = sqrt(-2.0 * log(u0)), r1 = sqrt(-2.0 * log(u2));
+  const double tp = 6.283185307179586;
+  n0 = r0 * cos(tp * u1);
+  n1 = r0 * sin(tp * u1);
+  n2 = r1 * cos(tp * u3);
+}
+
 // ------------------------------------------------------------- reductions
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -1473,6 +1507,14 @@ __device__ __forceinline__ void field_cells_t(const Prm& P,
       const float ca =
           GEN ? (kuv * um + P.ku4 * um * um * um) / msv : (kuv * um) / msv;
       Bx += ca * P.ux; By += ca * P.uy; Bz += ca * P.uz;
+      if (GEN && P.therm > 0.0) {
+        // Brown's field of this step, held over its stages: variance
+        // 2 alpha kB T / (gamma Ms V_c dt) per component
+        double n0, n1, n2;
+        thermal_normals(P, i, ctl->noise_n, n0, n1, n2);
+        const double sg = sqrt(P.therm / (ctl->dt * (double)msv));
+        Bx += (float)(sg * n0); By += (float)(sg * n1); Bz += (float)(sg * n2);
+      }
     }
     // LL torque: -gamma/(1+a^2) [ m x B + a m x (m x B) ]
     const float px = my * Bz - mz * By;
@@ -1753,6 +1795,7 @@ __device__ __forceinline__ void finish_step_body(
         c->ma_im[k] = c->mas_im[1][k] = c->manext_im[k];
       }
     c->mem_n += 1;
+    c->noise_n += 1;
     c->as_re[1] = c->a_re;
     c->as_im[1] = c->a_im;
     if (c->ahist) {

@@ -67,6 +67,7 @@ class Params(ctypes.Structure):
         ("brms_map", _FP), ("ku2", ctypes.c_double),
         ("no_precession", ctypes.c_int32), ("fdrive_map", _FP),
         ("dmi_int", ctypes.c_double), ("dmi_bulk", ctypes.c_double),
+        ("temperature", ctypes.c_double), ("seed", ctypes.c_uint64),
     ]
 
 
@@ -188,6 +189,8 @@ def make_params(prob, ms_map=None, ku_map=None, brms_map=None,
     p.fdrive_map = fdrive_map.data_ptr() if fdrive_map is not None else None
     p.dmi_int = getattr(prob, "dmi_int", 0.0)
     p.dmi_bulk = getattr(prob, "dmi_bulk", 0.0)
+    p.temperature = getattr(prob, "temperature", 0.0)
+    p.seed = int(getattr(prob, "seed", 0)) & ((1 << 64) - 1)
     p.dt, p.tol = prob.dt, prob.tol
     p.dt_min, p.dt_max = prob.dt_min, prob.dt_max
     return p
