@@ -497,8 +497,11 @@ __global__ __launch_bounds__(T) void k_xfwd(
     // (y0+2p, y0+2p+1) are adjacent -> one 16-byte store per (kx, p)
     const int H = P.Hx;
     const int totw = np * H;
-    for (int e = threadIdx.x; e < totw; e += T) {
-      const int k = e / np, p = e - k * np;
+    // e = k np + p advanced by T without a division per element
+    const int dk = T / np, dp = T - dk * np;
+    int k = threadIdx.x / np, p = threadIdx.x - k * np;
+    for (int e = threadIdx.x; e < totw;
+         e += T, k += dk, p += dp, (p >= np ? (p -= np, ++k) : 0)) {
       const float2 z1 = lds[pidx(p * Px + k)];
       const float2 z2 = lds[pidx(p * Px + ((Px - k) & (Px - 1)))];
       // A = (Z[k] + conj Z[-k]) / 2 ; B = (Z[k] - conj Z[-k]) / (2i)
@@ -1611,14 +1614,24 @@ __device__ __forceinline__ void xfield_l_body(
     const int per = 3 * np;
     const int tot = per * H;
     constexpr int U = 4;
+    // element e = k per + c np + p (column k, component c, row pair p),
+    // advanced by T per step without an integer division per element
+    const int dk = T / per, dr = T - dk * per;
+    int ki = threadIdx.x / per, ri = threadIdx.x - ki * per;
     for (int e0 = threadIdx.x; e0 < tot; e0 += T * U) {
       float4 v[U];
+      int kk[U], cc[U], pp[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int e = e0 + u * T;
-        const int k = e / per;
-        const int r = e - k * per;
-        const int c = r / np, p = r - c * np;
+        const int k = ki, r = ri;
+        ki += dk;
+        ri += dr;
+        if (ri >= per) { ri -= per; ++ki; }
+        const int c = (r >= np) + (r >= 2 * np), p = r - c * np;
+        kk[u] = k;
+        cc[u] = c;
+        pp[u] = p;
         const int ya = y0 + 2 * p;
         v[u] = (e < tot && ya < ny)
                    ? *(const float4*)(spec +
@@ -1629,9 +1642,7 @@ __device__ __forceinline__ void xfield_l_body(
       for (int u = 0; u < U; ++u) {
         const int e = e0 + u * T;
         if (e >= tot) continue;
-        const int k = e / per;
-        const int r = e - k * per;
-        const int c = r / np, p = r - c * np;
+        const int k = kk[u], c = cc[u], p = pp[u];
         float2 A = make_float2(v[u].x, v[u].y), B = make_float2(v[u].z, v[u].w);
         if (k == 0 || 2 * k == Px) { A.y = 0.f; B.y = 0.f; }
         const int sp = (c * np + p) * Px;
