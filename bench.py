@@ -29,9 +29,11 @@ METRIC = ("cavity-LLG cell-steps/s (fwd; fwd+adjoint; batched vs plain), "
           "% HBM peak")
 
 
-def kernel_bytes(plan, prob, method, kernel):
-    """Algorithmic HBM bytes of one launch of `kernel`, averaged over the
-    launches of one step (every array read or written once)."""
+def kernel_bytes(plan, prob, method, kernel, fused=False):
+    """Algorithmic HBM bytes of one launch of `kernel`, averaged over its
+    launches in one step (every array read or written once).  `fused`: the
+    run fused the forward x pass of stage s+1 into the field pass of stage s
+    (k_xfield_fwd), leaving k_xfield for the last stage only."""
     N = prob.ncells
     nx, ny, nz = prob.nx, prob.ny, prob.nz
     Px, Py = plan["Px"], plan["Py"]
@@ -41,22 +43,28 @@ def kernel_bytes(plan, prob, method, kernel):
     # and yz ones at offset 0, which vanish (odd in the z offset)
     kern = Hx * Hy * (6 * nz - 2) * 4
     state = 12 * N
-    if kernel == "k_xfwd":
+
+    def field(s):
+        """Field pass of stage s: spectrum in, y_s, k_s out, the earlier
+        k's, and (except the last stage) y_n in and y_{s+1} out."""
+        if method == "dp45":
+            prev = {2: 1, 3: 2, 4: 3, 5: 4, 6: 4, 7: 5}[s]
+            return (spec + 2 * state + (0 if s == 7 else 2 * state)
+                    + prev * state)
+        return spec + 2 * state + (2 * state if s < 4 else 4 * state)
+
+    stages = list(range(2, 8)) if method == "dp45" else list(range(1, 5))
+    if kernel in ("k_xfwd", "k_xfwd_fx"):
         return state + spec
     if kernel == "k_yspec":
         return 2 * spec + kern
+    if kernel == "k_xfield_fwd":
+        # the field pass of every stage but the last, plus the next stage's
+        # half spectrum (its input y_{s+1} is this kernel's own output)
+        per = [field(s) + spec for s in stages[:-1]]
+        return sum(per) / len(per)
     if kernel == "k_xfield":
-        if method == "dp45":
-            # stages 2..7: y_s read, k_s write, y_n read + y_{s+1} write
-            # (stages 2-6), previous k's read (1,2,3,4,4 then 5 at stage 7)
-            prev = [1, 2, 3, 4, 4, 5]
-            per = [spec + state + state + (0 if s == 7 else 2 * state)
-                   + prev[s - 2] * state for s in range(2, 8)]
-            return sum(per) / len(per)
-        per = [spec + state + state + 2 * state,           # s = 1..3
-               spec + state + state + 2 * state,
-               spec + state + state + 2 * state,
-               spec + state + 3 * state + 2 * state]      # s = 4
+        per = [field(stages[-1])] if fused else [field(s) for s in stages]
         return sum(per) / len(per)
     if kernel == "k_begin":
         return 5 * state
@@ -349,6 +357,7 @@ def main():
     if not args.no_timing:
         kw = sim.kernel_times(reset=True)
         kw = kw or {"k_yspec": (1.0, 1)}
+        fused = "k_xfield_fwd" in kw
         dom = max(kw, key=lambda k: kw[k][0])
         sim.set_timing(True, only=None if args.time_all else dom)
     torch.cuda.synchronize()
@@ -391,7 +400,7 @@ def main():
         # still use, so every stage-kernel launch of the timed region does
         # work when no attempt is rejected: launches == right-hand sides
         per_launch_s = ms * 1e-3 / n
-        byts = kernel_bytes(plan, prob, "dp45", dom)
+        byts = kernel_bytes(plan, prob, "dp45", dom, fused)
         achieved = byts / per_launch_s / 1e9
         out["roofline"] = {
             "bound": "hbm", "kernel": dom,
@@ -412,12 +421,10 @@ def main():
         # at once on the device flag and move no data).
         wi = winfo or info
         acc = max(1, wi["accepted"])
-        per_att = (wi["accepted"] + wi["rejected"]) / acc
-        counts = {k: (wi["rhs_evals"] / acc
-                      if k in ("k_xfwd", "k_yspec", "k_xfield") else per_att)
-                  for k in kw}
-        sb = sum(kernel_bytes(plan, prob, "dp45", k) * c
-                 for k, c in counts.items())
+        # launches per accepted step as counted in the warm-up (every
+        # launch of a step-capped run does work)
+        sb = sum(kernel_bytes(plan, prob, "dp45", k, fused) * v[1] / acc
+                 for k, v in kw.items())
         out["kernels"] = {k: {"ms": round(v[0], 3), "launches": v[1],
                               "us_per_launch": round(1e3 * v[0] / v[1], 2)}
                           for k, v in kw.items()}

@@ -61,6 +61,9 @@ struct llgc_ctx {
   bool use_wxi = false;  // register (wavefront) inverse FFT in the field pass
   bool x3 = false;       // LDS x passes over the 3 components of a tile at once
   bool batch_plan = false;  // fixed plan shared with the batched engine
+  bool no_fuse = false;     // LLGC_NO_FUSE: separate forward x passes
+  bool force_fuse = false;  // LLGC_FUSE: fused passes on any grid
+  bool fused_run = false;   // launches of a chunk with fused passes
   bool yhalf = false;    // LDS spectral pass split by ky parity (k_yspec_h)
   int Tyh = 512;         // its workgroup size
   size_t lds_yh = 0;     // its LDS bytes
@@ -187,11 +190,46 @@ int n_pointwise_blocks(const llgc_ctx* c) {
 // ------------------------------------------------------------ stage launch
 bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
+// Chunks of the integrator may fuse the forward x pass of stage s+1 into
+// the field pass of stage s (k_xfield_fwd): LDS x passes on a transform
+// length the kernels are specialised for, demag on, single-context plan.
+// The fused passes use the field pass's tiling (Ri rows) for both.  Fusing
+// pays where the grid leaves the GPU part-idle and launches dominate (the
+// 512x32x4 wire: 0.256 -> 0.225 ms per DP45 step; the 256x256x2 film: RK4
+// 9.1e8 -> 1.08e9 cell-steps/s); on a full GPU the separate passes are
+// faster (1024x1024x2: 1.07 ms fused 1.21 ms), so only grids of at most
+// 512 field tiles fuse (LLGC_FUSE forces it on, LLGC_NO_FUSE off).
+bool fusable(const llgc_ctx* c) {
+  if (!(c->P.demag && !c->use_wxf && !c->use_wxi && !c->x3 &&
+        !c->batch_plan && !c->no_fuse && c->logPx >= 8 && c->logPx <= 11))
+    return false;
+  return c->force_fuse || xgrid(c, c->Ri).x <= 512;
+}
+
 // rows per tile of whichever forward x pass runs
-int fwd_rows(const llgc_ctx* c) { return c->use_wxf ? c->Rwf : c->Rf; }
+int fwd_rows(const llgc_ctx* c) {
+  if (c->fused_run) return c->Ri;
+  return c->use_wxf ? c->Rwf : c->Rf;
+}
 
 int launch_xfwd(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
                 int mode) {
+  if (c->fused_run) {
+    // the first stage of a fused chunk: the fused pass's forward body
+    Timed tm(c, "k_xfwd_fx");
+#define LLGC_XFX(LP)                                                        \
+  hipLaunchKernelGGL((k_xfwd_fx<kTX, LP>), xgrid(c, c->Ri), dim3(kTX),       \
+                     c->lds_i, c->stream, c->P, ys, c->spec, ctl,           \
+                     c->partials, c->Ri, c->tw, c->logTw)
+    switch (c->logPx) {
+      case 8: LLGC_XFX(8); break;
+      case 9: LLGC_XFX(9); break;
+      case 10: LLGC_XFX(10); break;
+      default: LLGC_XFX(11); break;
+    }
+#undef LLGC_XFX
+    return check_launch(c, "k_xfwd_fx");
+  }
   Timed tm(c, "k_xfwd");
   if (c->use_wxf) {
     const int R = c->Rwf;
@@ -365,7 +403,23 @@ int launch_yspec(llgc_ctx* c, Ctl* ctl, int stage, int mode) {
 }
 
 int launch_xfield(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
-                  const Epi& E) {
+                  const Epi& E, bool fuse_fwd = false) {
+  if (fuse_fwd) {
+    // field pass of this stage + forward x pass of the next stage input
+    Timed tm(c, "k_xfield_fwd");
+#define LLGC_XFF(LP)                                                        \
+  hipLaunchKernelGGL((k_xfield_fwd<kTX, LP>), xgrid(c, c->Ri), dim3(kTX),    \
+                     c->lds_i, c->stream, c->P, ys, c->spec, ctl,           \
+                     c->partials, c->rec, stage, c->Ri, E, c->tw, c->logTw)
+    switch (c->logPx) {
+      case 8: LLGC_XFF(8); break;
+      case 9: LLGC_XFF(9); break;
+      case 10: LLGC_XFF(10); break;
+      default: LLGC_XFF(11); break;
+    }
+#undef LLGC_XFF
+    return check_launch(c, "k_xfield_fwd");
+  }
   Timed tm(c, "k_xfield");
   if (c->use_wxi) {
     const int R = c->Rw;
@@ -410,10 +464,14 @@ int launch_xfield(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
 // rows per tile of whichever field kernel runs
 int field_rows(const llgc_ctx* c) { return c->use_wxi ? c->Rw : c->Ri; }
 
+// One right-hand side.  In a fused chunk (c->fused_run) the stage's
+// forward x pass was done by the previous stage's field pass unless
+// `first`, and `fuse_next` lets this stage's field pass do the next one's.
 int rhs_stage(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
-              const Epi& E, int mode) {
+              const Epi& E, int mode, bool first = true,
+              bool fuse_next = false) {
   int r;
-  if ((r = launch_xfwd(c, ys, ctl, stage, mode))) return r;
+  if (first && (r = launch_xfwd(c, ys, ctl, stage, mode))) return r;
   if (c->P.modes) {
     // multimode cavity: one coupling sum per mode and x-pass tile
     Timed tm(c, "k_coupling_modes");
@@ -437,7 +495,7 @@ int rhs_stage(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
     if ((r = check_launch(c, "k_coupling_map"))) return r;
   }
   if ((r = launch_yspec(c, ctl, stage, mode))) return r;
-  if ((r = launch_xfield(c, ys, ctl, stage, E))) return r;
+  if ((r = launch_xfield(c, ys, ctl, stage, E, fuse_next))) return r;
   if (E.kind == 2 || E.kind == 3) {
     Timed tm(c, "k_finish_step");
     hipLaunchKernelGGL(k_finish_step<kT>, dim3(1), dim3(kT), 0, c->stream,
@@ -849,6 +907,13 @@ int plan_derive(llgc_ctx* c) {
     for (const void* f : xi)
       raise_lds_limit(f, c->lds_i);
     raise_lds_limit((const void*)k_xfwd3<kTX>, c->lds_f);
+    const void* xff[] = {
+        (const void*)k_xfield_fwd<kTX, 8>, (const void*)k_xfield_fwd<kTX, 9>,
+        (const void*)k_xfield_fwd<kTX, 10>, (const void*)k_xfield_fwd<kTX, 11>,
+        (const void*)k_xfwd_fx<kTX, 8>, (const void*)k_xfwd_fx<kTX, 9>,
+        (const void*)k_xfwd_fx<kTX, 10>, (const void*)k_xfwd_fx<kTX, 11>};
+    for (const void* f : xff)
+      raise_lds_limit(f, c->lds_i);
     raise_lds_limit((const void*)k_xfield_b<kTX>, c->lds_i);
   }
   if (c->yhalf) {
@@ -975,17 +1040,22 @@ constexpr int kDpChunk = 8;   // Dormand-Prince attempts per host check
 // kind 1 = one RK4 step (stages 1..4).
 int chunk_direct(llgc_ctx* c, int kind, int attempts = kDpChunk) {
   int r = LLGC_OK;
+  const bool fz = fusable(c);
+  c->fused_run = fz;
   if (kind == 1) {
     for (int s = 1; s <= 4 && !r; ++s) {
-      r = rhs_stage(c, rk4_input(c, s), c->ctl, s, epi_rk4(c, s), 0);
+      r = rhs_stage(c, rk4_input(c, s), c->ctl, s, epi_rk4(c, s), 0,
+                    !fz || s == 1, fz && s < 4);
     }
-    return r;
+  } else {
+    for (int b = 0; b < attempts && !r; ++b) {
+      for (int s = 2; s <= 7 && !r; ++s)
+        r = rhs_stage(c, c->yb[s % 2], c->ctl, s, epi_dp(c, s), 0,
+                      !fz || s == 2, fz && s < 7);
+      if (!r) r = launch_begin(c);
+    }
   }
-  for (int b = 0; b < attempts && !r; ++b) {
-    for (int s = 2; s <= 7 && !r; ++s)
-      r = rhs_stage(c, c->yb[s % 2], c->ctl, s, epi_dp(c, s), 0);
-    if (!r) r = launch_begin(c);
-  }
+  c->fused_run = false;
   return r;
 }
 
@@ -1094,6 +1164,8 @@ int llgc_create_ex(const llgc_grid* g, void* stream, int flags,
   c->dx = g->dx; c->dy = g->dy; c->dz = g->dz;
   c->stream = (hipStream_t)stream;
   hipGetDevice(&c->device);
+  c->no_fuse = getenv("LLGC_NO_FUSE") != nullptr;
+  c->force_fuse = getenv("LLGC_FUSE") != nullptr;
   c->batch_plan = bplan;
   c->graphs = getenv("LLGC_NO_GRAPHS") == nullptr;
   c->Px = g->nx == 1 ? 1 : pow2_ceil(2 * g->nx);

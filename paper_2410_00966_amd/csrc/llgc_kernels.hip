@@ -1679,6 +1679,121 @@ __global__ __launch_bounds__(T) void k_xfield(
                        xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, lds);
 }
 
+// ============================================= fused field + forward pass
+// Forward x pass of one tile with the transform length fixed (LP = log2 Px)
+// and the three components transformed together: Ms * y for rows y0 ..
+// y0+R-1 of layer z, two rows per complex transform, into LDS laid out as
+// the field pass lays out its inverse (2 padding slots per 64, twiddles from
+// global memory), so the field pass's LDS serves both; then the half
+// spectrum (16-byte stores of row pairs) and the tile's FP64 coupling sum
+// into partials[slot].  The arithmetic is k_xfwd's.
+template <int T, int LP>
+__device__ __forceinline__ void xfwd3_fixed_body(
+    const Prm& P, const float* __restrict__ ys, float2* __restrict__ spec,
+    double* __restrict__ partials, int R, const float2* __restrict__ tw,
+    int logTw, int tile, int slot, float2* lds) {
+  constexpr int PS = 6;
+  constexpr int Px = 1 << LP, xl = Px >> 1, lxl = LP - 1;
+  __shared__ double red[16];
+  const int nz = P.nz;
+  const int z = tile % nz;
+  const int y0 = (tile / nz) * R;
+  const int np = R >> 1;
+  const int nx = P.nx, ny = P.ny, nyp = P.nyp, N = P.ncell;
+  const int plane = nx * ny;
+  const float* msz = P.ms_map ? P.ms_map + (size_t)z * plane : nullptr;
+  const double br[3] = {P.brxd, P.bryd, P.brzd};
+  double facc[1] = {0.0};
+  const int per = np << lxl;   // lower half-rows of one component
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float* yc = ys + (size_t)c * N + (size_t)z * plane;
+    double fc = 0.0;
+    for (int q = threadIdx.x; q < per; q += T) {
+      const int p = q >> lxl, x = q & (xl - 1);
+      float2 v = make_float2(0.f, 0.f);
+      if (x < nx) {
+        const int ya = y0 + 2 * p;
+        if (ya < ny) {
+          const float msv = msz ? msz[ya * nx + x] : P.ms;
+          const float mv = yc[ya * nx + x];
+          v.x = msv * mv;
+          fc += (double)msv * (double)mv;
+        }
+        if (ya + 1 < ny) {
+          const float msv = msz ? msz[(ya + 1) * nx + x] : P.ms;
+          const float mv = yc[(ya + 1) * nx + x];
+          v.y = msv * mv;
+          fc += (double)msv * (double)mv;
+        }
+      }
+      lds[pidx_s<PS>((c * np + p) * Px + x)] = v;
+    }
+    facc[0] += fc * br[c];
+  }
+  __syncthreads();
+  fft_lds<VPT, false, LP, true, false, PS>(lds, LP, 3 * np, tw, logTw, -1.f);
+  constexpr int H = xl + 1;
+  const int totw = np * H;
+  const int dk = T / np, dp = T - dk * np;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    int k = threadIdx.x / np, p = threadIdx.x - k * np;
+    for (int e = threadIdx.x; e < totw;
+         e += T, k += dk, p += dp, (p >= np ? (p -= np, ++k) : 0)) {
+      const int b = (c * np + p) * Px;
+      const float2 z1 = lds[pidx_s<PS>(b + k)];
+      const float2 z2 = lds[pidx_s<PS>(b + ((Px - k) & (Px - 1)))];
+      // A = (Z[k] + conj Z[-k]) / 2 ; B = (Z[k] - conj Z[-k]) / (2i)
+      float4 v = make_float4(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y),
+                             0.5f * (z1.y + z2.y), -0.5f * (z1.x - z2.x));
+      const int ya = y0 + 2 * p;
+      if (ya < ny) {
+        if (ya + 1 >= ny) { v.z = 0.f; v.w = 0.f; }   // keep the pad zero
+        float2* row = spec + ((size_t)(k * nz + z) * 3 + c) * nyp;
+        *(float4*)(row + ya) = v;
+      }
+    }
+  }
+  block_sum<1>(facc, red);
+  if (threadIdx.x == 0) partials[slot] = facc[0];
+}
+
+// Stand-alone forward pass with the fused pass's tiling (the first stage of
+// an attempt, whose input comes from elsewhere).
+template <int T, int LP>
+__global__ __launch_bounds__(T) void k_xfwd_fx(
+    Prm P, const float* __restrict__ ys, float2* __restrict__ spec,
+    Ctl* __restrict__ ctl, double* __restrict__ partials, int R,
+    const float2* __restrict__ tw, int logTw) {
+  extern __shared__ float2 lds[];
+  if (ctl->done) return;
+  xfwd3_fixed_body<T, LP>(P, ys, spec, partials, R, tw, logTw,
+                          xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, lds);
+}
+
+// Field pass of stage s fused with the forward x pass of stage s+1: the
+// tile's next stage input y_{s+1} (written by the field epilogue, read back
+// by the same workgroup after a barrier) is transformed into the half
+// spectrum rows of this tile, which no other tile reads or writes, and the
+// tile's coupling sum for stage s+1 goes to partials[blockIdx.x].  Saves
+// the separate forward launch and its read of y_{s+1} from HBM.
+template <int T, int LP>
+__global__ __launch_bounds__(T) void k_xfield_fwd(
+    Prm P, const float* __restrict__ ys, float2* __restrict__ spec,
+    Ctl* __restrict__ ctl, double* __restrict__ partials,
+    double* __restrict__ rec, int stage, int R, Epi E,
+    const float2* __restrict__ tw, int logTw) {
+  extern __shared__ float2 lds[];
+  if (ctl->done) return;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  xfield_l_body<T, LP>(P, ys, spec, ctl, partials, stage, R, E, tw, logTw,
+                       tile, blockIdx.x, lds);
+  __syncthreads();
+  xfwd3_fixed_body<T, LP>(P, E.ynext, spec, partials, R, tw, logTw, tile,
+                          blockIdx.x, lds);
+}
+
 // The field pass of the batch plan: partial sums indexed by tile (as the
 // batched kernels index them), so that both sum in the same order.
 template <int T>
