@@ -2354,13 +2354,17 @@ int rk4_step_stored(llgc_ctx* c, float* Yk /*4 x 3N*/, float* Bk /*4 x 3N*/,
   int r = 0;
   HIPCHK(c, hipMemcpyAsync(Yk, c->yn, n3 * 4, hipMemcpyDeviceToDevice,
                            c->stream));
+  const bool fz = fusable(c);
+  c->fused_run = fz;
   for (int s = 1; s <= 4 && !r; ++s) {
     Epi E = epi_rk4(c, s, true);
     E.bout = Bk + (size_t)(s - 1) * n3;
     if (s < 4) E.ynext = Yk + (size_t)s * n3;
     else E.nout = nk;
-    r = rhs_stage(c, Yk + (size_t)(s - 1) * n3, c->ctl, s, E, 0);
+    r = rhs_stage(c, Yk + (size_t)(s - 1) * n3, c->ctl, s, E, 0,
+                  !fz || s == 1, fz && s < 4);
   }
+  c->fused_run = false;
   return r;
 }
 
@@ -2453,10 +2457,13 @@ extern "C" int llgc_adjoint(llgc_ctx* c, int64_t n_steps, double dt,
     HIPCHK(c, hipMemcpyAsync(ck + n3 * j, c->yn, n3 * 4,
                              hipMemcpyDeviceToDevice, c->stream));
     const int64_t Sj = std::min(S, n_steps - j * S);
+    const bool fz = fusable(c);
+    c->fused_run = fz;
     for (int64_t k = 0; k < Sj && !r; ++k)
       for (int s = 1; s <= 4 && !r; ++s)
         r = rhs_stage(c, rk4_input(c, s, true), c->ctl, s,
-                      epi_rk4(c, s, true), 0);
+                      epi_rk4(c, s, true), 0, !fz || s == 1, fz && s < 4);
+    c->fused_run = false;
     if (r) return r;
   }
   Ctl fin{};
