@@ -394,8 +394,9 @@ __device__ __forceinline__ void record_amplitudes(const Prm& P, const Ctl* c,
 // mode 0: integrate (cavity stage in the last block); mode 1: evaluate.
 // V4: nx % 4 == 0 and 16-byte aligned planes (vector loads).
 // LP > 0: log2(Px) fixed at compile time (specialised FFT addressing).
+// At most 128 VGPRs (four waves per SIMD): two 512-thread workgroups per CU.
 template <int T, bool V4, int LP = 0>
-__global__ __launch_bounds__(T) void k_xfwd(
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void k_xfwd(
     Prm P, const float* __restrict__ ys, float2* __restrict__ spec,
     Ctl* __restrict__ ctl, double* __restrict__ partials, int stage, int R,
     const float2* __restrict__ tw, int logTw, int mode) {
@@ -1432,11 +1433,53 @@ __device__ __forceinline__ void field_cells_t(const Prm& P,
     const int y = y0 + r;
     if (y >= ny) continue;
     const int i = (z * ny + y) * nx + x;
+    // Every global load of the cell is issued before the first use of any:
+    // a missing neighbour's index falls back to the cell itself (its
+    // difference is then zero and its weight below is 0), and the earlier
+    // k's sit behind uniform guards, so no load waits behind a per-lane
+    // branch or behind another load's use.
+    const bool hn[6] = {x > 0, x < nx - 1, y > 0, y < ny - 1, z > 0,
+                        z < nz - 1};
+    const int off[6] = {-1, 1, -nx, nx, -plane, plane};
+    int jn[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) jn[q] = hn[q] ? i + off[q] : i;
     const float mx = ys[i], my = ys[N + i], mz = ys[2 * N + i];
+    float nbx[6], nby[6], nbz[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      nbx[q] = ys[jn[q]];
+      nby[q] = ys[N + jn[q]];
+      nbz[q] = ys[2 * N + jn[q]];
+    }
+    const float msv = P.ms_map ? P.ms_map[i] : P.ms;
+    // Ku of the cell (2 Ku below; halving the uniform value is exact)
+    const float kum = P.ku_map ? P.ku_map[i] : 0.5f * P.ku2;
+    // neighbours outside the geometry (Ms = 0) are omitted like those
+    // outside the grid
+    const float* g = (GEN && P.masked) ? P.ms_map : nullptr;
+    float gn[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) gn[q] = g ? g[jn[q]] : 1.f;
+    float kpx[6], kpy[6], kpz[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      kpx[j] = kpy[j] = kpz[j] = 0.f;
+      if (j < E.np) {
+        kpx[j] = E.kp[j][i];
+        kpy[j] = E.kp[j][N + i];
+        kpz[j] = E.kp[j][2 * N + i];
+      }
+    }
+    float ynx = 0.f, yny = 0.f, ynz = 0.f;
+    if (E.kind == 1 || E.kind == 2) {
+      ynx = E.yn[i];
+      yny = E.yn[N + i];
+      ynz = E.yn[2 * N + i];
+    }
     if (E.commit) {
       E.commit[i] = mx; E.commit[N + i] = my; E.commit[2 * N + i] = mz;
     }
-    const float msv = P.ms_map ? P.ms_map[i] : P.ms;
     float Bx = bex + bcx, By = bey + bcy, Bz = bez + bcz;
     if (bmap) {   // per-cell vacuum field of the mode
       Bx = bex + bmap[i] * gcav;
@@ -1466,17 +1509,22 @@ __device__ __forceinline__ void field_cells_t(const Prm& P,
       Bz += b.z;
     }
     if (msv > 0.f) {
+      // neighbour j exists (inside the grid and the geometry)
+      bool w[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) w[q] = hn[q] && gn[q] > 0.f;
       // exchange: (2A/Ms) sum over existing neighbours (m_j - m_i)/d^2
       float lx = 0.f, ly = 0.f, lz = 0.f;
-      // neighbours outside the geometry (Ms = 0) are omitted like those
-      // outside the grid
-      const float* g = (GEN && P.masked) ? P.ms_map : nullptr;
-      if (x > 0 && (!g || g[i - 1] > 0.f)) { lx += (ys[i - 1] - mx) * P.idx2; ly += (ys[N + i - 1] - my) * P.idx2; lz += (ys[2 * N + i - 1] - mz) * P.idx2; }
-      if (x < nx - 1 && (!g || g[i + 1] > 0.f)) { lx += (ys[i + 1] - mx) * P.idx2; ly += (ys[N + i + 1] - my) * P.idx2; lz += (ys[2 * N + i + 1] - mz) * P.idx2; }
-      if (y > 0 && (!g || g[i - nx] > 0.f)) { lx += (ys[i - nx] - mx) * P.idy2; ly += (ys[N + i - nx] - my) * P.idy2; lz += (ys[2 * N + i - nx] - mz) * P.idy2; }
-      if (y < ny - 1 && (!g || g[i + nx] > 0.f)) { lx += (ys[i + nx] - mx) * P.idy2; ly += (ys[N + i + nx] - my) * P.idy2; lz += (ys[2 * N + i + nx] - mz) * P.idy2; }
-      if (z > 0 && (!g || g[i - plane] > 0.f)) { lx += (ys[i - plane] - mx) * P.idz2; ly += (ys[N + i - plane] - my) * P.idz2; lz += (ys[2 * N + i - plane] - mz) * P.idz2; }
-      if (z < nz - 1 && (!g || g[i + plane] > 0.f)) { lx += (ys[i + plane] - mx) * P.idz2; ly += (ys[N + i + plane] - my) * P.idz2; lz += (ys[2 * N + i + plane] - mz) * P.idz2; }
+      const float id2[3] = {P.idx2, P.idy2, P.idz2};
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const float dx = w[q] ? nbx[q] - mx : 0.f;
+        const float dy = w[q] ? nby[q] - my : 0.f;
+        const float dz = w[q] ? nbz[q] - mz : 0.f;
+        lx += dx * id2[q >> 1];
+        ly += dy * id2[q >> 1];
+        lz += dz * id2[q >> 1];
+      }
       const float ce = P.aex2 / msv;
       Bx += ce * lx; By += ce * ly; Bz += ce * lz;
       if (GEN && (P.dmi_i != 0.f || P.dmi_b != 0.f)) {
@@ -1487,12 +1535,12 @@ __device__ __forceinline__ void field_cells_t(const Prm& P,
         float ax = 0.f, ay = 0.f, az = 0.f;   // x bonds
         float bx = 0.f, by = 0.f, bz = 0.f;   // y bonds
         float cx = 0.f, cy = 0.f, cz = 0.f;   // z bonds
-        if (x < nx - 1 && (!g || g[i + 1] > 0.f)) { ax += ys[i + 1]; ay += ys[N + i + 1]; az += ys[2 * N + i + 1]; }
-        if (x > 0 && (!g || g[i - 1] > 0.f)) { ax -= ys[i - 1]; ay -= ys[N + i - 1]; az -= ys[2 * N + i - 1]; }
-        if (y < ny - 1 && (!g || g[i + nx] > 0.f)) { bx += ys[i + nx]; by += ys[N + i + nx]; bz += ys[2 * N + i + nx]; }
-        if (y > 0 && (!g || g[i - nx] > 0.f)) { bx -= ys[i - nx]; by -= ys[N + i - nx]; bz -= ys[2 * N + i - nx]; }
-        if (z < nz - 1 && (!g || g[i + plane] > 0.f)) { cx += ys[i + plane]; cy += ys[N + i + plane]; cz += ys[2 * N + i + plane]; }
-        if (z > 0 && (!g || g[i - plane] > 0.f)) { cx -= ys[i - plane]; cy -= ys[N + i - plane]; cz -= ys[2 * N + i - plane]; }
+        if (w[1]) { ax += nbx[1]; ay += nby[1]; az += nbz[1]; }
+        if (w[0]) { ax -= nbx[0]; ay -= nby[0]; az -= nbz[0]; }
+        if (w[3]) { bx += nbx[3]; by += nby[3]; bz += nbz[3]; }
+        if (w[2]) { bx -= nbx[2]; by -= nby[2]; bz -= nbz[2]; }
+        if (w[5]) { cx += nbx[5]; cy += nby[5]; cz += nbz[5]; }
+        if (w[4]) { cx -= nbx[4]; cy -= nby[4]; cz -= nbz[4]; }
         const float di = P.dmi_i / msv, db = P.dmi_b / msv;
         // x bonds: c = (-D_bulk, D_int, 0)/dx
         const float x0 = -db * P.idx1, x1 = di * P.idx1;
@@ -1505,7 +1553,7 @@ __device__ __forceinline__ void field_cells_t(const Prm& P,
         Bx -= z2 * cy; By += z2 * cx;
       }
       // uniaxial anisotropy (2 Ku / Ms) (u.m) u
-      const float kuv = P.ku_map ? 2.f * P.ku_map[i] : P.ku2;
+      const float kuv = 2.f * kum;
       const float um = P.ux * mx + P.uy * my + P.uz * mz;
       const float ca =
           GEN ? (kuv * um + P.ku4 * um * um * um) / msv : (kuv * um) / msv;
@@ -1534,11 +1582,14 @@ __device__ __forceinline__ void field_cells_t(const Prm& P,
     if (E.bout) { E.bout[i] = Bx; E.bout[N + i] = By; E.bout[2 * N + i] = Bz; }
     if (E.kind == 0) continue;
     float sx = E.cself * kx, sy = E.cself * ky, sz = E.cself * kz;
-    for (int j = 0; j < E.np; ++j) {
-      const float cj = E.ca[j];
-      sx += cj * E.kp[j][i];
-      sy += cj * E.kp[j][N + i];
-      sz += cj * E.kp[j][2 * N + i];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      if (j < E.np) {
+        const float cj = E.ca[j];
+        sx += cj * kpx[j];
+        sy += cj * kpy[j];
+        sz += cj * kpz[j];
+      }
     }
     if (E.kind == 3) {
       const float ex = dt * sx, ey = dt * sy, ez = dt * sz;
@@ -1546,8 +1597,7 @@ __device__ __forceinline__ void field_cells_t(const Prm& P,
       emax = (en == en) ? fmaxf(emax, en) : INFINITY;   // NaN -> reject
       continue;
     }
-    float nxv = E.yn[i] + dt * sx, nyv = E.yn[N + i] + dt * sy,
-          nzv = E.yn[2 * N + i] + dt * sz;
+    float nxv = ynx + dt * sx, nyv = yny + dt * sy, nzv = ynz + dt * sz;
     if (E.kind == 2) {
       const float nrm = sqrtf(nxv * nxv + nyv * nyv + nzv * nzv);
       if (E.nout) E.nout[i] = nrm;
