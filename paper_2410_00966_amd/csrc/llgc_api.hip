@@ -65,6 +65,8 @@ struct llgc_ctx {
   bool force_fuse = false;  // LLGC_FUSE: fused passes on any grid
   bool fused_run = false;   // launches of a chunk with fused passes
   bool yhalf = false;    // LDS spectral pass split by ky parity (k_yspec_h)
+  bool no_ypersist = false;  // LLGC_NO_YPERSIST: one spectral block per workgroup
+  int ncu = 0;           // compute units of the device
   int Tyh = 512;         // its workgroup size
   size_t lds_yh = 0;     // its LDS bytes
   int Rw = 2;            // rows per tile of the wavefront field kernel
@@ -276,17 +278,54 @@ int launch_xfwd(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
 
 // The LDS FFT kernels are specialised on the transform length for the
 // long transforms they serve (LP = log2 length; 0 = any length).
+// Workgroups of `f` (T threads, `lds` bytes of dynamic LDS) resident on one
+// CU at a time (cached per kernel and size).
+int blocks_per_cu(const void* f, int T, size_t lds) {
+  static std::map<std::pair<const void*, size_t>, int> cache;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lock(mu);
+  auto key = std::make_pair(f, lds);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, T, lds) !=
+      hipSuccess)
+    nb = 0;
+  (void)hipGetLastError();
+  cache[key] = nb;
+  return nb;
+}
+
 template <int T, int LP>
 void yspec_nz_lp(llgc_ctx* c, Ctl* ctl, dim3 g, int stage, int mode) {
   const int nf = (int)xgrid(c, fwd_rows(c)).x;
+  const int nblk = (int)g.x;
+  // Fewer workgroups than blocks, each stepping through several and loading
+  // the next block's input during the current block's inverse transform:
+  // as many as are resident at once (the blocks' lower halves must fit the
+  // kernel's prefetch registers).
+  auto grid_for = [&](const void* f) {
+    const int hp = c->Py >> 2;
+    if (!yspec_steps(T, c->nz) || c->no_ypersist || c->ncu <= 0 ||
+        c->Py < 4 || c->W * 3 * c->nz * hp > kPf * T)
+      return g;
+    const int per = blocks_per_cu(f, T, c->lds_y);
+    if (per <= 0) return g;
+    return dim3((unsigned)std::min(nblk, per * c->ncu));
+  };
 #define LLGC_YSPEC_ARGS c->P, c->spec, c->K, ctl, c->W, c->tw, c->logTw, \
-                        c->partials, nf, stage, mode
+                        c->partials, nf, stage, mode, nblk
+#define LLGC_YS(NZ)                                                         \
+  hipLaunchKernelGGL((k_yspec<T, NZ, LP>),                                  \
+                     grid_for((const void*)k_yspec<T, NZ, LP>), dim3(T),    \
+                     c->lds_y, c->stream, LLGC_YSPEC_ARGS)
   switch (c->nz) {
-    case 1: hipLaunchKernelGGL((k_yspec<T, 1, LP>), g, dim3(T), c->lds_y, c->stream, LLGC_YSPEC_ARGS); break;
-    case 2: hipLaunchKernelGGL((k_yspec<T, 2, LP>), g, dim3(T), c->lds_y, c->stream, LLGC_YSPEC_ARGS); break;
-    case 3: hipLaunchKernelGGL((k_yspec<T, 3, LP>), g, dim3(T), c->lds_y, c->stream, LLGC_YSPEC_ARGS); break;
-    default: hipLaunchKernelGGL((k_yspec<T, 4, LP>), g, dim3(T), c->lds_y, c->stream, LLGC_YSPEC_ARGS); break;
+    case 1: LLGC_YS(1); break;
+    case 2: LLGC_YS(2); break;
+    case 3: LLGC_YS(3); break;
+    default: LLGC_YS(4); break;
   }
+#undef LLGC_YS
 #undef LLGC_YSPEC_ARGS
 }
 
@@ -928,7 +967,16 @@ int plan_derive(llgc_ctx* c) {
   if (!c->use_wy && !c->yhalf) {
     yspec_attr<256>(c->lds_y);
     yspec_attr<512>(c->lds_y);
-    if constexpr (kTyMax >= 1024) yspec_attr<1024>(c->lds_y);
+    if constexpr (kTyMax >= 1024) {
+      yspec_attr<1024>(c->lds_y);
+      // residency of the block-stepping instances, queried here rather
+      // than at a launch that may be under stream capture
+      const void* fs[] = {
+          (const void*)k_yspec<1024, 1, 0>, (const void*)k_yspec<1024, 2, 0>,
+          (const void*)k_yspec<1024, 1, 10>, (const void*)k_yspec<1024, 2, 10>,
+          (const void*)k_yspec<1024, 1, 11>, (const void*)k_yspec<1024, 2, 11>};
+      for (const void* f : fs) blocks_per_cu(f, 1024, c->lds_y);
+    }
   }
   return LLGC_OK;
 }
@@ -1164,6 +1212,10 @@ int llgc_create_ex(const llgc_grid* g, void* stream, int flags,
   c->dx = g->dx; c->dy = g->dy; c->dz = g->dz;
   c->stream = (hipStream_t)stream;
   hipGetDevice(&c->device);
+  if (hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount,
+                            c->device) != hipSuccess)
+    c->ncu = 0;
+  c->no_ypersist = getenv("LLGC_NO_YPERSIST") != nullptr;
   c->no_fuse = getenv("LLGC_NO_FUSE") != nullptr;
   c->force_fuse = getenv("LLGC_FUSE") != nullptr;
   c->batch_plan = bplan;

@@ -63,7 +63,7 @@ __global__ __launch_bounds__(kBYT, 4) void kb_yspec(const BInst* __restrict__ I,
     return;
   }
 #define LLGC_BY_ARGS B.P, B.spec, B.K, B.ctl, B.W, B.tw, B.logTw, \
-                     B.partials, B.nf, stage, mode, w.y, lds
+                     B.partials, B.nf, stage, mode, w.y, w.y + 1, 1, lds
   switch (B.P.nz) {
     case 1: yspec_l_body<kBYT, 1, 0>(LLGC_BY_ARGS); break;
     case 2: yspec_l_body<kBYT, 2, 0>(LLGC_BY_ARGS); break;

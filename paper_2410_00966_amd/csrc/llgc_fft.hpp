@@ -170,7 +170,7 @@ template <int R, int NB, bool PIN = false, bool POUT = false, int PS = 4,
           bool TT = false>
 __device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
                                          int batch, const float2* tw,
-                                         int logTw, float dir) {
+                                         int logTw, float dir, int tid) {
   constexpr int logR = (R == 2) ? 1 : (R == 4) ? 2 : (R == 8) ? 3 : 4;
   const int logLr = logL - logR;
   const int Lr = 1 << logLr;
@@ -185,7 +185,7 @@ __device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
   // the powers w^q are formed in registers afterwards.
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    const int b = threadIdx.x + i * blockDim.x;
+    const int b = tid + i * blockDim.x;
     w1[i] = make_float2(1.f, 0.f);
     if (b < nbf) {
       const int t = b >> logLr, j = b & (Lr - 1);
@@ -200,7 +200,7 @@ __device__ __forceinline__ void fft_pass(float2* s, int logL, int logNs,
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    const int b = threadIdx.x + i * blockDim.x;
+    const int b = tid + i * blockDim.x;
     if (b < nbf) {
       const int t = b >> logLr, j = b & (Lr - 1);
       const int k = j & (Ns - 1);
@@ -313,12 +313,16 @@ __device__ __forceinline__ void fft_tt_build(float2* tt,
 }
 
 // TT (with LOGL > 0): `tw` holds the per-pass twiddle tables of
-// fft_tt_build instead of the plain table.
+// fft_tt_build instead of the plain table.  `tid`: the thread's index in
+// the workgroup (threadIdx.x if negative); a caller that loops over blocks
+// passes it through an opaque copy, so that the passes' address arithmetic
+// is formed where it is used rather than held across the loop.
 template <int VPT, bool R16 = false, int LOGL = 0, bool PIN = false,
           bool POUT = false, int PS = 4, bool TT = false>
 __device__ __forceinline__ void fft_lds(float2* s, int logL, int batch,
                                         const float2* tw,
-                        int logTw, float dir) {
+                        int logTw, float dir, int tid = -1) {
+  if (tid < 0) tid = threadIdx.x;
   static_assert(!TT || LOGL > 0, "twiddle tables need a fixed length");
   if constexpr (LOGL > 0) logL = LOGL;
   if (logL == 0) return;
@@ -336,16 +340,16 @@ __device__ __forceinline__ void fft_lds(float2* s, int logL, int batch,
     const float2* twp = TT ? tw + toff : tw;
     if (PIN && first && POUT && last)
       fft_pass<R, NB, PIN, POUT, PS, TT>(s, logL, logNs, batch, twp, logTw,
-                                         dir);
+                                         dir, tid);
     else if (PIN && first)
       fft_pass<R, NB, PIN, false, PS, TT>(s, logL, logNs, batch, twp, logTw,
-                                          dir);
+                                          dir, tid);
     else if (POUT && last)
       fft_pass<R, NB, false, POUT, PS, TT>(s, logL, logNs, batch, twp,
-                                           logTw, dir);
+                                           logTw, dir, tid);
     else
       fft_pass<R, NB, false, false, PS, TT>(s, logL, logNs, batch, twp,
-                                            logTw, dir);
+                                            logTw, dir, tid);
     if (logNs > 0) toff += (R - 1) << logNs;
     logNs += Log2C<R>::v;
     ++p;

@@ -941,15 +941,26 @@ __device__ __forceinline__ void kernel_product(const float* __restrict__ Kp,
   kernel_product_k<NZ>(kk, sy, M, Hf);
 }
 
-// Spectral pass of column block `blk` (a workgroup of T threads; LDS
-// `lds_all` as sized by the plan).  LP > 0: log2(Py) fixed at compile time
-// (specialised FFT addressing).
+// Spectral pass of column blocks blk0, blk0 + bstride, ... < nblk (a
+// workgroup of T threads; LDS `lds_all` as sized by the plan; block blk0
+// only unless yspec_steps(T, NZ)).  With more than one block per workgroup, the input of the
+// next block is loaded into registers before the inverse transform of the
+// current one, so that its latency overlaps that transform and the stores
+// (the host steps through blocks only where a block's lower half fits kPf
+// float4 per thread).  LP > 0: log2(Py) fixed at compile time (specialised
+// FFT addressing).
+constexpr int kPf = 4;
+// Workgroup sizes and layer counts whose spectral pass steps through blocks
+// (elsewhere the prefetch registers would cost occupancy or spill).
+__host__ __device__ constexpr bool yspec_steps(int T, int NZ) {
+  return NZ <= 2 && T == 1024;
+}
 template <int T, int NZ, int LP = 0>
 __device__ __forceinline__ void yspec_l_body(
     const Prm& P, float2* __restrict__ spec, const float* __restrict__ K,
     Ctl* __restrict__ ctl, int W, const float2* __restrict__ tw,
     int logTw, const double* __restrict__ partials, int nblk_f, int stage,
-    int mode, int blk, float2* lds_all) {
+    int mode, int blk0, int nblk, int bstride, float2* lds_all) {
   __shared__ double red[16];
   // compile-time lengths read per-pass twiddle tables (fewer VALU
   // operations); otherwise the first half of the plain table is staged
@@ -959,7 +970,7 @@ __device__ __forceinline__ void yspec_l_body(
   if constexpr (TT) fft_tt_build<VPTY, true, LP>(twl, tw, logTw);
   else stage_twiddles(twl, tw, logTw);
   // workgroup 0 also finishes the coupling sum of this stage
-  if (blk == 0 && !P.modes) {
+  if (blk0 == 0 && !P.modes) {
     finish_cavity(P, ctl, partials, nblk_f, stage, mode, red);
     __syncthreads();
   }
@@ -972,172 +983,217 @@ __device__ __forceinline__ void yspec_l_body(
   const bool pair = P.Px >= 2;
   const int hxn = P.Px >> 1;
   const int nslot = pair ? hxn : P.Hx;
-  const int kx0 = blk * W;
-  const int Wb = min(W, nslot - kx0);
-  const bool has_pair = pair && blk == 0;   // slot 0 in this block
-  const int ncol = Wb * nz3;
-  const float2* src = spec + (size_t)kx0 * nz3 * nyp;
   const float2* srcn = spec + (size_t)hxn * nz3 * nyp;
-  if (Py >= 4) {
-    // pairs of rows (y, y+1) per 16-byte load, lower half of each column
-    // only: rows >= Py/2 are zero padding and the first pass does not read
-    // them
-    const int hp = Py >> 2;
-    const int tot = ncol * hp;
-    constexpr int U = 8;
-    for (int e0 = threadIdx.x; e0 < tot; e0 += T * U) {
-      float4 v[U];
+  // lower halves, as pairs of rows (y, y+1) per 16-byte load: rows >= Py/2
+  // are zero padding and the first pass does not read them
+  const int hp = Py >> 2;
+  // Blocks are stepped through with prefetch where yspec_steps allows, one
+  // block per workgroup otherwise.  `blk`: the block; `tid`: the thread
+  // index; `nb`: the next block of this workgroup (>= nblk: none); `pf`: its
+  // input registers.
+  constexpr bool PF = yspec_steps(T, NZ);
+  float4 pf[kPf];
+  auto block = [&](const int blk, const int tid, const int nb) {
+    const int kx0 = blk * W;
+    const int Wb = min(W, nslot - kx0);
+    const bool has_pair = pair && blk == 0;   // slot 0 in this block
+    const int ncol = Wb * nz3;
+    const float2* src = spec + (size_t)kx0 * nz3 * nyp;
+    if (PF && Py >= 4 && blk != blk0) {
+      // this block's input, loaded during the previous block
+      const int tot = ncol * hp;
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int e = e0 + u * T;
+      for (int u = 0; u < kPf; ++u) {
+        const int e = tid + u * T;
         const int col = e >> (lpy - 2), y = (e & (hp - 1)) << 1;
-        v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (e < tot && y < ny) {
-          v[u] = *(const float4*)(src + (size_t)col * nyp + y);
-          if (has_pair && col < nz3) {
-            const float4 n = *(const float4*)(srcn + (size_t)col * nyp + y);
-            v[u] = make_float4(v[u].x, n.x, v[u].z, n.z);
+        if (e < tot) *(float4*)(lds + pidx(col * Py + y)) = pf[u];
+      }
+    } else if (Py >= 4) {
+      const int tot = ncol * hp;
+      constexpr int U = 8;
+      for (int e0 = tid; e0 < tot; e0 += T * U) {
+        float4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int e = e0 + u * T;
+          const int col = e >> (lpy - 2), y = (e & (hp - 1)) << 1;
+          v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (e < tot && y < ny) {
+            v[u] = *(const float4*)(src + (size_t)col * nyp + y);
+            if (has_pair && col < nz3) {
+              const float4 n = *(const float4*)(srcn + (size_t)col * nyp + y);
+              v[u] = make_float4(v[u].x, n.x, v[u].z, n.z);
+            }
           }
         }
-      }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int e = e0 + u * T;
+        for (int u = 0; u < U; ++u) {
+          const int e = e0 + u * T;
+          const int col = e >> (lpy - 2), y = (e & (hp - 1)) << 1;
+          if (e < tot) *(float4*)(lds + pidx(col * Py + y)) = v[u];
+        }
+      }
+    } else {
+      // Py = 1 or 2: row 0 is the only data row
+      for (int e = tid; e < ncol; e += T) {
+        float2 v = src[(size_t)e * nyp];
+        if (has_pair && e < nz3) v.y = srcn[(size_t)e * nyp].x;
+        lds[pidx(e * Py)] = v;
+      }
+    }
+    __syncthreads();
+    fft_lds<VPTY, true, LP, true, false, 4, TT>(lds, P.logPy, ncol, twl,
+                                               logTw, -1.f, tid);
+    // pointwise product, all 3*nz values at a (w, ky).  A thread takes the
+    // mirrored pair ky = kh, Py - kh (kh in 1 .. Py/2 - 1), which share the
+    // kernel row |ky| = kh (odd-in-ky parts flip), or for kh = 0 the two
+    // self-mirrored rows ky = 0 and Py/2.
+    const int Hy = P.Hy;
+    // (Py = 1: the single row ky = 0 only)
+    const int Ph = Py >> 1, nkh = Py >= 2 ? Ph : 1;
+    const int lph = Py >= 2 ? lpy - 1 : 0, nself = Py >= 2 ? 2 : 1;
+    for (int e = tid; e < Wb * nkh; e += T) {
+      const int w = e >> lph, kh = e & (nkh - 1);
+      float2 M[nz3], Hf[nz3];
+      if (has_pair && w == 0) {
+        // slot 0: split Z = X0 + i XN at (ky, -ky), apply each column's
+        // kernel, recombine; the results are real sequences, so
+        // W[-ky] = conj(Y0[ky]) + i conj(YN[ky]).  One pass per mirrored
+        // pair: ky = kh, and for kh = 0 also ky = Py/2.
+        // (Y0 is parked in LDS while YN is formed: fewer live registers)
+#pragma unroll 1
+        for (int r = 0; r < (kh == 0 ? nself : 1); ++r) {
+          const int ky = r == 0 ? kh : Ph;
+          const int km = (Py - ky) & (Py - 1);
+          float2 XN[nz3];
+#pragma unroll
+          for (int q = 0; q < nz3; ++q) {
+            const float2 z = lds[pidx(q * Py + ky)];
+            const float2 zm = lds[pidx(q * Py + km)];
+            M[q] = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
+            XN[q] = make_float2(0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x));
+          }
+          kernel_product<NZ>(K + (size_t)ky * 6 * NZ, 1.f, M, Hf);
+#pragma unroll
+          for (int q = 0; q < nz3; ++q) lds[pidx(q * Py + ky)] = Hf[q];
+          kernel_product<NZ>(K + ((size_t)hxn * Hy + ky) * 6 * NZ, 1.f, XN,
+                             Hf);
+#pragma unroll
+          for (int q = 0; q < nz3; ++q) {
+            const float2 y0 = lds[pidx(q * Py + ky)];
+            lds[pidx(q * Py + ky)] = make_float2(y0.x - Hf[q].y,
+                                                 y0.y + Hf[q].x);
+            if (km != ky)
+              lds[pidx(q * Py + km)] = make_float2(y0.x + Hf[q].y,
+                                                   -y0.y + Hf[q].x);
+          }
+        }
+        continue;
+      }
+      const int kx = kx0 + w;
+      const int base = w * nz3 * Py;
+      float kk[6 * NZ];
+      if (kh == 0) {
+        // ky = 0 and ky = Py/2: each its own mirror, even parts only
+#pragma unroll 1
+        for (int r = 0; r < nself; ++r) {
+          const int ky = r * Ph;
+          kernel_load<NZ>(K + ((size_t)kx * Hy + ky) * 6 * NZ, kk);
+#pragma unroll
+          for (int q = 0; q < nz3; ++q) M[q] = lds[pidx(base + q * Py + ky)];
+          kernel_product_k<NZ>(kk, 1.f, M, Hf);
+#pragma unroll
+          for (int q = 0; q < nz3; ++q) lds[pidx(base + q * Py + ky)] = Hf[q];
+        }
+        continue;
+      }
+      kernel_load<NZ>(K + ((size_t)kx * Hy + kh) * 6 * NZ, kk);
+#pragma unroll
+      for (int q = 0; q < nz3; ++q) M[q] = lds[pidx(base + q * Py + kh)];
+      kernel_product_k<NZ>(kk, 1.f, M, Hf);
+#pragma unroll
+      for (int q = 0; q < nz3; ++q) lds[pidx(base + q * Py + kh)] = Hf[q];
+      const int km = Py - kh;
+#pragma unroll
+      for (int q = 0; q < nz3; ++q) M[q] = lds[pidx(base + q * Py + km)];
+      kernel_product_k<NZ>(kk, -1.f, M, Hf);   // odd-in-ky parts flip
+#pragma unroll
+      for (int q = 0; q < nz3; ++q) lds[pidx(base + q * Py + km)] = Hf[q];
+    }
+    __syncthreads();
+    // next block's input (it never holds slot 0: blk + bstride > 0)
+    if (PF && Py >= 4 && nb < nblk) {
+      const int totn = min(W, nslot - nb * W) * nz3 * hp;
+      const float2* srcb = spec + (size_t)nb * W * nz3 * nyp;
+#pragma unroll
+      for (int u = 0; u < kPf; ++u) {
+        const int e = tid + u * T;
         const int col = e >> (lpy - 2), y = (e & (hp - 1)) << 1;
-        if (e < tot) *(float4*)(lds + pidx(col * Py + y)) = v[u];
+        pf[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (e < totn && y < ny)
+          pf[u] = *(const float4*)(srcb + (size_t)col * nyp + y);
       }
     }
-  } else {
-    // Py = 1 or 2: row 0 is the only data row
-    for (int e = threadIdx.x; e < ncol; e += T) {
-      float2 v = src[(size_t)e * nyp];
-      if (has_pair && e < nz3) v.y = srcn[(size_t)e * nyp].x;
-      lds[pidx(e * Py)] = v;
-    }
-  }
-  __syncthreads();
-  fft_lds<VPTY, true, LP, true, false, 4, TT>(lds, P.logPy, ncol, twl, logTw,
-                                             -1.f);
-  // pointwise product, all 3*nz values at a (w, ky).  A thread takes the
-  // mirrored pair ky = kh, Py - kh (kh in 1 .. Py/2 - 1), which share the
-  // kernel row |ky| = kh (odd-in-ky parts flip), or for kh = 0 the two
-  // self-mirrored rows ky = 0 and Py/2.
-  const int Hy = P.Hy;
-  // (Py = 1: the single row ky = 0 only)
-  const int Ph = Py >> 1, nkh = Py >= 2 ? Ph : 1;
-  const int lph = Py >= 2 ? lpy - 1 : 0, nself = Py >= 2 ? 2 : 1;
-  for (int e = threadIdx.x; e < Wb * nkh; e += T) {
-    const int w = e >> lph, kh = e & (nkh - 1);
-    float2 M[nz3], Hf[nz3];
-    if (has_pair && w == 0) {
-      // slot 0: split Z = X0 + i XN at (ky, -ky), apply each column's
-      // kernel, recombine; the results are real sequences, so
-      // W[-ky] = conj(Y0[ky]) + i conj(YN[ky]).  One pass per mirrored
-      // pair: ky = kh, and for kh = 0 also ky = Py/2.
-      // (Y0 is parked in LDS while YN is formed: fewer live registers)
-#pragma unroll 1
-      for (int r = 0; r < (kh == 0 ? nself : 1); ++r) {
-        const int ky = r == 0 ? kh : Ph;
-        const int km = (Py - ky) & (Py - 1);
-        float2 XN[nz3];
-#pragma unroll
-        for (int q = 0; q < nz3; ++q) {
-          const float2 z = lds[pidx(q * Py + ky)];
-          const float2 zm = lds[pidx(q * Py + km)];
-          M[q] = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
-          XN[q] = make_float2(0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x));
+    fft_lds<VPTY, true, LP, false, true, 4, TT>(lds, P.logPy, ncol, twl,
+                                               logTw, 1.f, tid);
+    float2* dst = spec + (size_t)kx0 * nz3 * nyp;
+    float2* dstn = spec + (size_t)hxn * nz3 * nyp;
+    if (Py >= 4) {
+      // row pairs of the lower half; those at y >= nyp are not stored
+      const int hq = Py >> 2;
+      const int tot = ncol * hq;
+      for (int e = tid; e < tot; e += T) {
+        const int col = e >> (lpy - 2), y = (e & (hq - 1)) << 1;
+        if (y >= nyp) continue;
+        float4 v = *(const float4*)(lds + pidx(col * Py + y));
+        if (y + 1 >= ny) { v.z = 0.f; v.w = 0.f; }   // keep the pad zero
+        if (has_pair && col < nz3) {
+          *(float4*)(dstn + (size_t)col * nyp + y) =
+              make_float4(v.y, 0.f, v.w, 0.f);
+          v = make_float4(v.x, 0.f, v.z, 0.f);
         }
-        kernel_product<NZ>(K + (size_t)ky * 6 * NZ, 1.f, M, Hf);
-#pragma unroll
-        for (int q = 0; q < nz3; ++q) lds[pidx(q * Py + ky)] = Hf[q];
-        kernel_product<NZ>(K + ((size_t)hxn * Hy + ky) * 6 * NZ, 1.f, XN,
-                           Hf);
-#pragma unroll
-        for (int q = 0; q < nz3; ++q) {
-          const float2 y0 = lds[pidx(q * Py + ky)];
-          lds[pidx(q * Py + ky)] = make_float2(y0.x - Hf[q].y, y0.y + Hf[q].x);
-          if (km != ky)
-            lds[pidx(q * Py + km)] = make_float2(y0.x + Hf[q].y,
-                                                 -y0.y + Hf[q].x);
+        *(float4*)(dst + (size_t)col * nyp + y) = v;
+      }
+    } else {
+      // Py = 1 or 2: row 0 is the only data row (the pad row stays zero)
+      for (int e = tid; e < ncol; e += T) {
+        const float2 v = lds[pidx(e * Py)];
+        if (has_pair && e < nz3) {
+          dstn[(size_t)e * nyp] = make_float2(v.y, 0.f);
+          dst[(size_t)e * nyp] = make_float2(v.x, 0.f);
+        } else {
+          dst[(size_t)e * nyp] = v;
         }
       }
-      continue;
     }
-    const int kx = kx0 + w;
-    const int base = w * nz3 * Py;
-    float kk[6 * NZ];
-    if (kh == 0) {
-      // ky = 0 and ky = Py/2: each its own mirror, even parts only
-#pragma unroll 1
-      for (int r = 0; r < nself; ++r) {
-        const int ky = r * Ph;
-        kernel_load<NZ>(K + ((size_t)kx * Hy + ky) * 6 * NZ, kk);
-#pragma unroll
-        for (int q = 0; q < nz3; ++q) M[q] = lds[pidx(base + q * Py + ky)];
-        kernel_product_k<NZ>(kk, 1.f, M, Hf);
-#pragma unroll
-        for (int q = 0; q < nz3; ++q) lds[pidx(base + q * Py + ky)] = Hf[q];
-      }
-      continue;
-    }
-    kernel_load<NZ>(K + ((size_t)kx * Hy + kh) * 6 * NZ, kk);
-#pragma unroll
-    for (int q = 0; q < nz3; ++q) M[q] = lds[pidx(base + q * Py + kh)];
-    kernel_product_k<NZ>(kk, 1.f, M, Hf);
-#pragma unroll
-    for (int q = 0; q < nz3; ++q) lds[pidx(base + q * Py + kh)] = Hf[q];
-    const int km = Py - kh;
-#pragma unroll
-    for (int q = 0; q < nz3; ++q) M[q] = lds[pidx(base + q * Py + km)];
-    kernel_product_k<NZ>(kk, -1.f, M, Hf);   // odd-in-ky parts flip
-#pragma unroll
-    for (int q = 0; q < nz3; ++q) lds[pidx(base + q * Py + km)] = Hf[q];
-  }
-  __syncthreads();
-  fft_lds<VPTY, true, LP, false, true, 4, TT>(lds, P.logPy, ncol, twl, logTw,
-                                             1.f);
-  float2* dst = spec + (size_t)kx0 * nz3 * nyp;
-  float2* dstn = spec + (size_t)hxn * nz3 * nyp;
-  if (Py >= 4) {
-    // row pairs of the lower half; those at y >= nyp are not stored
-    const int hq = Py >> 2;
-    const int tot = ncol * hq;
-    for (int e = threadIdx.x; e < tot; e += T) {
-      const int col = e >> (lpy - 2), y = (e & (hq - 1)) << 1;
-      if (y >= nyp) continue;
-      float4 v = *(const float4*)(lds + pidx(col * Py + y));
-      if (y + 1 >= ny) { v.z = 0.f; v.w = 0.f; }   // keep the pad zero
-      if (has_pair && col < nz3) {
-        *(float4*)(dstn + (size_t)col * nyp + y) =
-            make_float4(v.y, 0.f, v.w, 0.f);
-        v = make_float4(v.x, 0.f, v.z, 0.f);
-      }
-      *(float4*)(dst + (size_t)col * nyp + y) = v;
+  };
+  if constexpr (PF) {
+    for (int blk = blk0; blk < nblk; blk += bstride) {
+      // thread index through an opaque copy: the address arithmetic of a
+      // block is formed where it is used, not held in registers across
+      // blocks
+      int tid = threadIdx.x;
+      asm volatile("" : "+v"(tid));
+      block(blk, tid, blk + bstride);
+      if (blk + bstride < nblk) __syncthreads();   // the LDS is refilled next
     }
   } else {
-    // Py = 1 or 2: row 0 is the only data row (the pad row stays zero)
-    for (int e = threadIdx.x; e < ncol; e += T) {
-      const float2 v = lds[pidx(e * Py)];
-      if (has_pair && e < nz3) {
-        dstn[(size_t)e * nyp] = make_float2(v.y, 0.f);
-        dst[(size_t)e * nyp] = make_float2(v.x, 0.f);
-      } else {
-        dst[(size_t)e * nyp] = v;
-      }
-    }
+    block(blk0, (int)threadIdx.x, nblk);
   }
 }
 
+// Grid: nblk workgroups (one block each), or fewer that step through the
+// blocks with stride gridDim.x.
 template <int T, int NZ, int LP = 0>
 __global__ __launch_bounds__(T) void k_yspec(
     Prm P, float2* __restrict__ spec, const float* __restrict__ K,
     Ctl* __restrict__ ctl, int W, const float2* __restrict__ tw,
     int logTw, const double* __restrict__ partials, int nblk_f, int stage,
-    int mode) {
+    int mode, int nblk) {
   extern __shared__ float2 lds_all[];
   if (ctl->done) return;
   yspec_l_body<T, NZ, LP>(P, spec, K, ctl, W, tw, logTw, partials, nblk_f,
-                          stage, mode, blockIdx.x, lds_all);
+                          stage, mode, blockIdx.x, nblk, gridDim.x, lds_all);
 }
 
 
