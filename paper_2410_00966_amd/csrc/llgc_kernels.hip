@@ -417,54 +417,70 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void k_x
   const double br[3] = {P.brxd, P.bryd, P.brzd};
   double facc[1] = {0.0};
   const float* msz = P.ms_map ? P.ms_map + (size_t)z * plane : nullptr;
+  // V4: quads of 4 consecutive x; row pair p: rows y0+2p (re), y0+2p+1
+  // (im); x < Px/2 only: the rest is zero padding the first pass does not
+  // read.  Quad pair q of component c, and the Ms values it is weighted by:
+  const int qpr = Px >> 3;               // quads per half row
+  const int nq = np * qpr;
+  auto load_qp = [&](int c, int q, float4& va, float4& vb) {
+    const float* yc = ys + (size_t)c * N + (size_t)z * plane;
+    const int p = q / qpr, x = (q - p * qpr) << 2;
+    const int ya = y0 + 2 * p;
+    va = vb = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (q < nq && x < nx) {
+      if (ya < ny) va = *(const float4*)(yc + ya * nx + x);
+      if (ya + 1 < ny) vb = *(const float4*)(yc + (ya + 1) * nx + x);
+    }
+  };
+  auto load_ms = [&](int q, float4& sa, float4& sb) {
+    const int p = q / qpr, x = (q - p * qpr) << 2;
+    const int ya = y0 + 2 * p;
+    sa = sb = make_float4(P.ms, P.ms, P.ms, P.ms);
+    if (msz && q < nq && x < nx) {
+      if (ya < ny) sa = *(const float4*)(msz + ya * nx + x);
+      if (ya + 1 < ny) sb = *(const float4*)(msz + (ya + 1) * nx + x);
+    }
+  };
+  // its coupling terms into fc and its products Ms m into the LDS rows
+  auto put_qp = [&](int q, const float4& va, const float4& vb,
+                    const float4& sa, const float4& sb, double& fc) {
+    const int p = q / qpr, x = (q - p * qpr) << 2;
+    fc += (double)sa.x * va.x + (double)sa.y * va.y + (double)sa.z * va.z +
+          (double)sa.w * va.w + (double)sb.x * vb.x + (double)sb.y * vb.y +
+          (double)sb.z * vb.z + (double)sb.w * vb.w;
+    if (P.demag) {
+      const int li = p * Px + x;
+      *(float4*)(lds + pidx(li)) = make_float4(sa.x * va.x, sb.x * vb.x,
+                                               sa.y * va.y, sb.y * vb.y);
+      *(float4*)(lds + pidx(li + 2)) = make_float4(sa.z * va.z, sb.z * vb.z,
+                                                   sa.w * va.w, sb.w * vb.w);
+    }
+  };
+  // the thread's first quad pair of the next component is loaded while the
+  // current component is transformed (registers nva, nvb)
+  float4 nva, nvb;
+  if (V4) load_qp(0, threadIdx.x, nva, nvb);
   for (int c = 0; c < 3; ++c) {
     const float* yc = ys + (size_t)c * N + (size_t)z * plane;
     double fc = 0.0;
     if (V4) {
-      // quads of 4 consecutive x; row pair p: rows y0+2p (re), y0+2p+1 (im);
-      // x < Px/2 only: the rest is zero padding the first pass does not read
-      const int qpr = Px >> 3;               // quads per half row
-      const int nq = np * qpr;
-      constexpr int U = 4;
-      for (int q0 = threadIdx.x; q0 < nq; q0 += T * U) {
+      if ((int)threadIdx.x < nq) {
+        float4 sa, sb;
+        load_ms(threadIdx.x, sa, sb);
+        put_qp(threadIdx.x, nva, nvb, sa, sb, fc);
+      }
+      // the remaining quad pairs, U per batch
+      constexpr int U = 2;
+      for (int q0 = threadIdx.x + T; q0 < nq; q0 += T * U) {
         float4 va[U], vb[U], sa[U], sb[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int q = q0 + u * T;
-          const int p = q / qpr, x = (q - p * qpr) << 2;
-          const int ya = y0 + 2 * p;
-          va[u] = vb[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-          sa[u] = sb[u] = make_float4(P.ms, P.ms, P.ms, P.ms);
-          if (q < nq && x < nx) {
-            if (ya < ny) {
-              va[u] = *(const float4*)(yc + ya * nx + x);
-              if (msz) sa[u] = *(const float4*)(msz + ya * nx + x);
-            }
-            if (ya + 1 < ny) {
-              vb[u] = *(const float4*)(yc + (ya + 1) * nx + x);
-              if (msz) sb[u] = *(const float4*)(msz + (ya + 1) * nx + x);
-            }
-          }
+          load_qp(c, q0 + u * T, va[u], vb[u]);
+          load_ms(q0 + u * T, sa[u], sb[u]);
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int q = q0 + u * T;
-          if (q >= nq) continue;
-          const int p = q / qpr, x = (q - p * qpr) << 2;
-          fc += (double)sa[u].x * va[u].x + (double)sa[u].y * va[u].y +
-                (double)sa[u].z * va[u].z + (double)sa[u].w * va[u].w +
-                (double)sb[u].x * vb[u].x + (double)sb[u].y * vb[u].y +
-                (double)sb[u].z * vb[u].z + (double)sb[u].w * vb[u].w;
-          if (P.demag) {
-            const int li = p * Px + x;
-            *(float4*)(lds + pidx(li)) =
-                make_float4(sa[u].x * va[u].x, sb[u].x * vb[u].x,
-                            sa[u].y * va[u].y, sb[u].y * vb[u].y);
-            *(float4*)(lds + pidx(li + 2)) =
-                make_float4(sa[u].z * va[u].z, sb[u].z * vb[u].z,
-                            sa[u].w * va[u].w, sb[u].w * vb[u].w);
-          }
-        }
+        for (int u = 0; u < U; ++u)
+          if (q0 + u * T < nq) put_qp(q0 + u * T, va[u], vb[u], sa[u], sb[u], fc);
       }
     } else {
       const int xl = Px > 1 ? Px >> 1 : 1;   // lower half of the row
@@ -491,9 +507,18 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void k_x
       }
     }
     facc[0] += fc * br[c];
-    if (!P.demag) continue;
+    if (!P.demag) {
+      if (V4 && c < 2) load_qp(c + 1, threadIdx.x, nva, nvb);
+      continue;
+    }
     __syncthreads();
-    fft_lds<VPT, false, LP, true, false>(lds, P.logPx, np, twl, logTw, -1.f);
+    if (V4 && c < 2) load_qp(c + 1, threadIdx.x, nva, nvb);
+    // thread index through an opaque copy: the transform's address
+    // arithmetic is formed per component, not held across the loop
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    fft_lds<VPT, false, LP, true, false>(lds, P.logPx, np, twl, logTw, -1.f,
+                                         tid);
     // split the two real transforms and write the half spectrum: rows
     // (y0+2p, y0+2p+1) are adjacent -> one 16-byte store per (kx, p)
     const int H = P.Hx;
