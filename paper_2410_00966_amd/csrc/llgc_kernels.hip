@@ -39,6 +39,25 @@ namespace llgc {
 constexpr int VPT = LLGC_VPT;
 constexpr int VPTY = LLGC_VPTY;
 
+// Accesses through a 32-bit unsigned offset from an array's uniform base
+// address: the load or store is then the base plus a 32-bit lane offset,
+// with no 64-bit address arithmetic per element (every array here stays far
+// below 4 GiB: at most 3 x 1024 x 1024 x 4 floats, a half spectrum of about
+// 100 MB).  ldf/stf: element i of a float array; ld4/st4: 16 bytes at byte
+// offset `off`.
+__device__ __forceinline__ float ldf(const float* p, unsigned i) {
+  return *(const float*)((const char*)p + (i << 2));
+}
+__device__ __forceinline__ void stf(float* p, unsigned i, float v) {
+  *(float*)((char*)p + (i << 2)) = v;
+}
+__device__ __forceinline__ float4 ld4(const void* p, unsigned off) {
+  return *(const float4*)((const char*)p + off);
+}
+__device__ __forceinline__ void st4(void* p, unsigned off, float4 v) {
+  *(float4*)((char*)p + off) = v;
+}
+
 // The Stockham passes of an L-point transform index the twiddle table at
 // k * Ltw / (Ns R) < Ltw / 2, so the first half of the table serves every
 // pass.  The LDS kernels copy it into the front of their LDS once, so that
@@ -423,22 +442,23 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void k_x
   const int qpr = Px >> 3;               // quads per half row
   const int nq = np * qpr;
   auto load_qp = [&](int c, int q, float4& va, float4& vb) {
-    const float* yc = ys + (size_t)c * N + (size_t)z * plane;
     const int p = q / qpr, x = (q - p * qpr) << 2;
     const int ya = y0 + 2 * p;
+    const unsigned o = (unsigned)(c * N + z * plane + ya * nx + x) << 2;
     va = vb = make_float4(0.f, 0.f, 0.f, 0.f);
     if (q < nq && x < nx) {
-      if (ya < ny) va = *(const float4*)(yc + ya * nx + x);
-      if (ya + 1 < ny) vb = *(const float4*)(yc + (ya + 1) * nx + x);
+      if (ya < ny) va = ld4(ys, o);
+      if (ya + 1 < ny) vb = ld4(ys, o + ((unsigned)nx << 2));
     }
   };
   auto load_ms = [&](int q, float4& sa, float4& sb) {
     const int p = q / qpr, x = (q - p * qpr) << 2;
     const int ya = y0 + 2 * p;
+    const unsigned o = (unsigned)(z * plane + ya * nx + x) << 2;
     sa = sb = make_float4(P.ms, P.ms, P.ms, P.ms);
     if (msz && q < nq && x < nx) {
-      if (ya < ny) sa = *(const float4*)(msz + ya * nx + x);
-      if (ya + 1 < ny) sb = *(const float4*)(msz + (ya + 1) * nx + x);
+      if (ya < ny) sa = ld4(P.ms_map, o);
+      if (ya + 1 < ny) sb = ld4(P.ms_map, o + ((unsigned)nx << 2));
     }
   };
   // its coupling terms into fc and its products Ms m into the LDS rows
@@ -537,8 +557,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void k_x
       if (ya < ny) {
         float4 v = AB;
         if (ya + 1 >= ny) { v.z = 0.f; v.w = 0.f; }   // keep the pad zero
-        float2* row = spec + ((size_t)(k * nz + z) * 3 + c) * nyp;
-        *(float4*)(row + ya) = v;
+        st4(spec, (unsigned)(((k * nz + z) * 3 + c) * nyp + ya) << 3, v);
       }
     }
     __syncthreads();
@@ -1044,9 +1063,10 @@ __device__ __forceinline__ void yspec_l_body(
           const int col = e >> (lpy - 2), y = (e & (hp - 1)) << 1;
           v[u] = make_float4(0.f, 0.f, 0.f, 0.f);
           if (e < tot && y < ny) {
-            v[u] = *(const float4*)(src + (size_t)col * nyp + y);
+            v[u] = ld4(spec, (unsigned)((kx0 * nz3 + col) * nyp + y) << 3);
             if (has_pair && col < nz3) {
-              const float4 n = *(const float4*)(srcn + (size_t)col * nyp + y);
+              const float4 n =
+                  ld4(spec, (unsigned)((hxn * nz3 + col) * nyp + y) << 3);
               v[u] = make_float4(v[u].x, n.x, v[u].z, n.z);
             }
           }
@@ -1149,14 +1169,14 @@ __device__ __forceinline__ void yspec_l_body(
     // next block's input (it never holds slot 0: blk + bstride > 0)
     if (PF && Py >= 4 && nb < nblk) {
       const int totn = min(W, nslot - nb * W) * nz3 * hp;
-      const float2* srcb = spec + (size_t)nb * W * nz3 * nyp;
+      const int c0 = nb * W * nz3;
 #pragma unroll
       for (int u = 0; u < kPf; ++u) {
         const int e = tid + u * T;
         const int col = e >> (lpy - 2), y = (e & (hp - 1)) << 1;
         pf[u] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (e < totn && y < ny)
-          pf[u] = *(const float4*)(srcb + (size_t)col * nyp + y);
+          pf[u] = ld4(spec, (unsigned)((c0 + col) * nyp + y) << 3);
       }
     }
     fft_lds<VPTY, true, LP, false, true, 4, TT>(lds, P.logPy, ncol, twl,
@@ -1173,11 +1193,11 @@ __device__ __forceinline__ void yspec_l_body(
         float4 v = *(const float4*)(lds + pidx(col * Py + y));
         if (y + 1 >= ny) { v.z = 0.f; v.w = 0.f; }   // keep the pad zero
         if (has_pair && col < nz3) {
-          *(float4*)(dstn + (size_t)col * nyp + y) =
-              make_float4(v.y, 0.f, v.w, 0.f);
+          st4(spec, (unsigned)((hxn * nz3 + col) * nyp + y) << 3,
+              make_float4(v.y, 0.f, v.w, 0.f));
           v = make_float4(v.x, 0.f, v.z, 0.f);
         }
-        *(float4*)(dst + (size_t)col * nyp + y) = v;
+        st4(spec, (unsigned)((kx0 * nz3 + col) * nyp + y) << 3, v);
       }
     } else {
       // Py = 1 or 2: row 0 is the only data row (the pad row stays zero)
@@ -1513,7 +1533,8 @@ __device__ __forceinline__ void field_cells_t(const Prm& P,
     if (xi >= nx) { xi -= nx; ++ri; }
     const int y = y0 + r;
     if (y >= ny) continue;
-    const int i = (z * ny + y) * nx + x;
+    const unsigned i = (unsigned)((z * ny + y) * nx + x);
+    const unsigned Nu = (unsigned)N, N2 = 2u * Nu;
     // Every global load of the cell is issued before the first use of any:
     // a missing neighbour's index falls back to the cell itself (its
     // difference is then zero and its weight below is 0), and the earlier
@@ -1522,66 +1543,66 @@ __device__ __forceinline__ void field_cells_t(const Prm& P,
     const bool hn[6] = {x > 0, x < nx - 1, y > 0, y < ny - 1, z > 0,
                         z < nz - 1};
     const int off[6] = {-1, 1, -nx, nx, -plane, plane};
-    int jn[6];
+    unsigned jn[6];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) jn[q] = hn[q] ? i + off[q] : i;
-    const float mx = ys[i], my = ys[N + i], mz = ys[2 * N + i];
+    for (int q = 0; q < 6; ++q) jn[q] = hn[q] ? i + (unsigned)off[q] : i;
+    const float mx = ldf(ys, i), my = ldf(ys, Nu + i), mz = ldf(ys, N2 + i);
     float nbx[6], nby[6], nbz[6];
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
-      nbx[q] = ys[jn[q]];
-      nby[q] = ys[N + jn[q]];
-      nbz[q] = ys[2 * N + jn[q]];
+      nbx[q] = ldf(ys, jn[q]);
+      nby[q] = ldf(ys, Nu + jn[q]);
+      nbz[q] = ldf(ys, N2 + jn[q]);
     }
-    const float msv = P.ms_map ? P.ms_map[i] : P.ms;
+    const float msv = P.ms_map ? ldf(P.ms_map, i) : P.ms;
     // Ku of the cell (2 Ku below; halving the uniform value is exact)
-    const float kum = P.ku_map ? P.ku_map[i] : 0.5f * P.ku2;
+    const float kum = P.ku_map ? ldf(P.ku_map, i) : 0.5f * P.ku2;
     // neighbours outside the geometry (Ms = 0) are omitted like those
     // outside the grid
     const float* g = (GEN && P.masked) ? P.ms_map : nullptr;
     float gn[6];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) gn[q] = g ? g[jn[q]] : 1.f;
+    for (int q = 0; q < 6; ++q) gn[q] = g ? ldf(g, jn[q]) : 1.f;
     float kpx[6], kpy[6], kpz[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
       kpx[j] = kpy[j] = kpz[j] = 0.f;
       if (j < E.np) {
-        kpx[j] = E.kp[j][i];
-        kpy[j] = E.kp[j][N + i];
-        kpz[j] = E.kp[j][2 * N + i];
+        kpx[j] = ldf(E.kp[j], i);
+        kpy[j] = ldf(E.kp[j], Nu + i);
+        kpz[j] = ldf(E.kp[j], N2 + i);
       }
     }
     float ynx = 0.f, yny = 0.f, ynz = 0.f;
     if (E.kind == 1 || E.kind == 2) {
-      ynx = E.yn[i];
-      yny = E.yn[N + i];
-      ynz = E.yn[2 * N + i];
+      ynx = ldf(E.yn, i);
+      yny = ldf(E.yn, Nu + i);
+      ynz = ldf(E.yn, N2 + i);
     }
     if (E.commit) {
-      E.commit[i] = mx; E.commit[N + i] = my; E.commit[2 * N + i] = mz;
+      stf(E.commit, i, mx); stf(E.commit, Nu + i, my); stf(E.commit, N2 + i, mz);
     }
     float Bx = bex + bcx, By = bey + bcy, Bz = bez + bcz;
     if (bmap) {   // per-cell vacuum field of the mode
-      Bx = bex + bmap[i] * gcav;
-      By = bey + bmap[N + i] * gcav;
-      Bz = bez + bmap[2 * N + i] * gcav;
+      Bx = bex + ldf(bmap, i) * gcav;
+      By = bey + ldf(bmap, Nu + i) * gcav;
+      Bz = bez + ldf(bmap, N2 + i) * gcav;
     }
     if (GEN && mmap) {   // per-cell fields of the modes that have maps
 #pragma unroll
       for (int k = 0; k < kMaxModes; ++k) {
         if (k >= nmodes) break;
         if (const float* b = P.modes->map[k]) {
-          Bx += b[i] * gk[k];
-          By += b[N + i] * gk[k];
-          Bz += b[2 * N + i] * gk[k];
+          Bx += ldf(b, i) * gk[k];
+          By += ldf(b, Nu + i) * gk[k];
+          Bz += ldf(b, N2 + i) * gk[k];
         }
       }
     }
     if (GEN && P.fdrive_map) {   // field drive shaped per cell
-      Bx += fd * P.fdrive_map[i];
-      By += fd * P.fdrive_map[N + i];
-      Bz += fd * P.fdrive_map[2 * N + i];
+      Bx += fd * ldf(P.fdrive_map, i);
+      By += fd * ldf(P.fdrive_map, Nu + i);
+      Bz += fd * ldf(P.fdrive_map, N2 + i);
     }
     if (P.demag) {
       const float3 b = bd(r, x);
@@ -1659,8 +1680,8 @@ __device__ __forceinline__ void field_cells_t(const Prm& P,
     const float kx = P.gpref * (pf * px + P.alpha * qx);
     const float ky = P.gpref * (pf * py + P.alpha * qy);
     const float kz = P.gpref * (pf * pz + P.alpha * qz);
-    if (E.kout) { E.kout[i] = kx; E.kout[N + i] = ky; E.kout[2 * N + i] = kz; }
-    if (E.bout) { E.bout[i] = Bx; E.bout[N + i] = By; E.bout[2 * N + i] = Bz; }
+    if (E.kout) { stf(E.kout, i, kx); stf(E.kout, Nu + i, ky); stf(E.kout, N2 + i, kz); }
+    if (E.bout) { stf(E.bout, i, Bx); stf(E.bout, Nu + i, By); stf(E.bout, N2 + i, Bz); }
     if (E.kind == 0) continue;
     float sx = E.cself * kx, sy = E.cself * ky, sz = E.cself * kz;
 #pragma unroll
@@ -1681,12 +1702,12 @@ __device__ __forceinline__ void field_cells_t(const Prm& P,
     float nxv = ynx + dt * sx, nyv = yny + dt * sy, nzv = ynz + dt * sz;
     if (E.kind == 2) {
       const float nrm = sqrtf(nxv * nxv + nyv * nyv + nzv * nzv);
-      if (E.nout) E.nout[i] = nrm;
+      if (E.nout) stf(E.nout, i, nrm);
       const float inv = nrm > 0.f ? 1.f / nrm : 0.f;   // empty cells stay 0
       nxv *= inv; nyv *= inv; nzv *= inv;
       acc[0] += nxv; acc[1] += nyv; acc[2] += nzv;
     }
-    E.ynext[i] = nxv; E.ynext[N + i] = nyv; E.ynext[2 * N + i] = nzv;
+    stf(E.ynext, i, nxv); stf(E.ynext, Nu + i, nyv); stf(E.ynext, N2 + i, nzv);
   }
   if (E.kind != 2 && E.kind != 3) return;
   if (E.kind == 2) {
@@ -1765,8 +1786,8 @@ __device__ __forceinline__ void xfield_l_body(
         pp[u] = p;
         const int ya = y0 + 2 * p;
         v[u] = (e < tot && ya < ny)
-                   ? *(const float4*)(spec +
-                                      ((size_t)(k * nz + z) * 3 + c) * nyp + ya)
+                   ? ld4(spec, (unsigned)(((k * nz + z) * 3 + c) * nyp + ya)
+                                   << 3)
                    : make_float4(0.f, 0.f, 0.f, 0.f);
       }
 #pragma unroll
@@ -2169,12 +2190,13 @@ __device__ __forceinline__ void begin_body(
     float4 m[3], k[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
+      const unsigned o = (unsigned)(c * N + 4 * q) << 2;
       if (pend) {
-        m[c] = ((const float4*)(y7 + (size_t)c * N))[q];
-        k[c] = ((const float4*)(k7 + (size_t)c * N))[q];
+        m[c] = ld4(y7, o);
+        k[c] = ld4(k7, o);
       } else {
-        m[c] = ((const float4*)(yn + (size_t)c * N))[q];
-        k[c] = ((const float4*)(k1 + (size_t)c * N))[q];
+        m[c] = ld4(yn, o);
+        k[c] = ld4(k1, o);
       }
     }
     if (pend) {
@@ -2188,8 +2210,9 @@ __device__ __forceinline__ void begin_body(
       }
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        ((float4*)(yn + (size_t)c * N))[q] = m[c];
-        ((float4*)(k1 + (size_t)c * N))[q] = k[c];
+        const unsigned o = (unsigned)(c * N + 4 * q) << 2;
+        st4(yn, o, m[c]);
+        st4(k1, o, k[c]);
       }
     }
     if (!done) {
@@ -2198,7 +2221,7 @@ __device__ __forceinline__ void begin_body(
         float4 o;
         o.x = m[c].x + c21 * k[c].x; o.y = m[c].y + c21 * k[c].y;
         o.z = m[c].z + c21 * k[c].z; o.w = m[c].w + c21 * k[c].w;
-        ((float4*)(y2 + (size_t)c * N))[q] = o;
+        st4(y2, (unsigned)(c * N + 4 * q) << 2, o);
       }
     }
   }
