@@ -537,8 +537,8 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void k_x
     // arithmetic is formed per component, not held across the loop
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    fft_lds<VPT, false, LP, true, false>(lds, P.logPx, np, twl, logTw, -1.f,
-                                         tid);
+    fft_lds<VPT, true, LP, true, false>(lds, P.logPx, np, twl, logTw, -1.f,
+                                        tid);
     // split the two real transforms and write the half spectrum: rows
     // (y0+2p, y0+2p+1) are adjacent -> one 16-byte store per (kx, p)
     const int H = P.Hx;
