@@ -915,7 +915,7 @@ int plan_derive(llgc_ctx* c) {
   const size_t twb = sizeof(float2) * lds_twiddles(c->logTw);  // LDS twiddles
   c->lds_f = twb + sizeof(float2) * padded_len((size_t)((c->batch_plan || c->x3) ? 3 : 1) *
                                                 (c->Rf / 2) * c->Px);
-  c->lds_i = sizeof(float2) * padded_len_s<6>((size_t)3 * (c->Ri / 2) * c->Px);
+  c->lds_i = sizeof(float2) * padded_len_s<kPsField>((size_t)3 * (c->Ri / 2) * c->Px);
   // the spectral pass is specialised on 1024 and 2048 points (yspec_nz)
   const int lpy = (c->logPy == 10 || c->logPy == 11) ? c->logPy : 0;
   c->lds_y = sizeof(float2) * (yspec_tw_len(lpy, c->logTw) +

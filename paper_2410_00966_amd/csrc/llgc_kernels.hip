@@ -1744,8 +1744,11 @@ __device__ __forceinline__ void field_cells(const Prm& P,
 // 1D grid of ceil(ny/R)*nz tiles (as k_xfwd); LDS: 3 * (R/2) * Px complex.
 // LP > 0: log2(Px) fixed at compile time (specialised FFT addressing).
 // Field pass of tile `tile` (partial sums into slot `slot`); LDS `lds`
-// holds the 3 (R/2) transforms only, lightly padded (2 slots per 64), so
-// that three workgroups fit a CU; twiddles are read from global memory.
+// holds the 3 (R/2) transforms only, padded with 2 slots every 2^kPsField
+// values; twiddles are read from global memory.  (The cell loop's registers
+// allow two 512-thread workgroups per CU, so the LDS is padded for fewer
+// bank conflicts rather than for a third workgroup.)
+constexpr int kPsField = 4;
 template <int T, int LP = 0>
 __device__ __forceinline__ void xfield_l_body(
     const Prm& P, const float* __restrict__ ys,
@@ -1753,7 +1756,7 @@ __device__ __forceinline__ void xfield_l_body(
     double* __restrict__ partials, int stage, int R, const Epi& E,
     const float2* __restrict__ tw, int logTw, int tile, int slot,
     float2* lds) {
-  constexpr int PS = 6;
+  constexpr int PS = kPsField;
   const int nz = P.nz;
   const int z = tile % nz;
   const int y0 = (tile / nz) * R;
@@ -1835,16 +1838,16 @@ __global__ __launch_bounds__(T) void k_xfield(
 // Forward x pass of one tile with the transform length fixed (LP = log2 Px)
 // and the three components transformed together: Ms * y for rows y0 ..
 // y0+R-1 of layer z, two rows per complex transform, into LDS laid out as
-// the field pass lays out its inverse (2 padding slots per 64, twiddles from
+// the field pass lays out its inverse (padding kPsField, twiddles from
 // global memory), so the field pass's LDS serves both; then the half
 // spectrum (16-byte stores of row pairs) and the tile's FP64 coupling sum
-// into partials[slot].  The arithmetic is k_xfwd's.
+// into partials[slot].  The arithmetic is k_xfwd's (the same radix passes).
 template <int T, int LP>
 __device__ __forceinline__ void xfwd3_fixed_body(
     const Prm& P, const float* __restrict__ ys, float2* __restrict__ spec,
     double* __restrict__ partials, int R, const float2* __restrict__ tw,
     int logTw, int tile, int slot, float2* lds) {
-  constexpr int PS = 6;
+  constexpr int PS = kPsField;
   constexpr int Px = 1 << LP, xl = Px >> 1, lxl = LP - 1;
   __shared__ double red[16];
   const int nz = P.nz;
@@ -1884,7 +1887,7 @@ __device__ __forceinline__ void xfwd3_fixed_body(
     facc[0] += fc * br[c];
   }
   __syncthreads();
-  fft_lds<VPT, false, LP, true, false, PS>(lds, LP, 3 * np, tw, logTw, -1.f);
+  fft_lds<VPT, true, LP, true, false, PS>(lds, LP, 3 * np, tw, logTw, -1.f);
   constexpr int H = xl + 1;
   const int totw = np * H;
   const int dk = T / np, dp = T - dk * np;
