@@ -1315,7 +1315,7 @@ int llgc_create_ex(const llgc_grid* g, void* stream, int flags,
   for (int j = 0; j < 7 && ok; ++j)
     ok = hipMalloc(&c->kb[j], n3 * 4) == hipSuccess;
   const size_t nspec = (size_t)c->Hx * c->nz * 3 * (c->ny + (c->ny & 1));
-  const size_t nK = (size_t)c->Hx * c->Hy * 6 * c->nz;
+  const size_t nK = (size_t)c->Hx * c->Hy * kentry(c->nz);
   ok = ok && hipMalloc(&c->spec, nspec * sizeof(float2)) == hipSuccess &&
        hipMalloc(&c->K, nK * sizeof(float)) == hipSuccess &&
        hipMalloc(&c->ctl, sizeof(Ctl)) == hipSuccess &&
@@ -2305,10 +2305,22 @@ int llgc_demag_kernel(llgc_ctx* c, float* out, int64_t cap, int32_t* dims) {
     dims[3] = c->Hy;
   }
   if (!out) return LLGC_OK;
-  const int64_t n = (int64_t)c->Hx * c->Hy * 6 * c->nz;
+  const int nz = c->nz, ke = kentry(nz);
+  const int64_t ne = (int64_t)c->Hx * c->Hy;
+  const int64_t n = ne * 6 * nz;
   if (cap < n) return fail(c, LLGC_E_ARG, "need %lld floats", (long long)n);
   if (!c->kernel_built) return fail(c, LLGC_E_STATE, "no demag kernel");
-  HIPCHK(c, hipMemcpy(out, c->K, sizeof(float) * n, hipMemcpyDeviceToHost));
+  // the stored entries omit xz and yz at dz = 0 (zero): expand
+  std::vector<float> packed((size_t)(ne * ke));
+  HIPCHK(c, hipMemcpy(packed.data(), c->K, sizeof(float) * packed.size(),
+                      hipMemcpyDeviceToHost));
+  for (int64_t e = 0; e < ne; ++e)
+    for (int comp = 0; comp < 6; ++comp)
+      for (int dz = 0; dz < nz; ++dz)
+        out[(e * 6 + comp) * nz + dz] =
+            (comp >= 4 && dz == 0) ? 0.f
+                                   : packed[(size_t)(e * ke +
+                                                     kslot(comp, dz, nz))];
   return LLGC_OK;
 }
 

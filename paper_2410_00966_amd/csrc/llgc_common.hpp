@@ -115,6 +115,15 @@ struct Epi {
                        // copied here, committing it as y_n (or null)
 };
 
+// Demag-kernel table entry: the real coefficients of one (kx, |ky|) for all
+// z offsets dz, comp = xx yy zz xy at dz = 0 .. nz-1, then xz yz at
+// dz = 1 .. nz-1 (odd in dz, they vanish at dz = 0 and are not stored):
+// 6 nz - 2 floats.
+__host__ __device__ constexpr int kentry(int nz) { return 6 * nz - 2; }
+__host__ __device__ constexpr int kslot(int comp, int dz, int nz) {
+  return comp < 4 ? comp * nz + dz : 4 * nz + (comp - 4) * (nz - 1) + dz - 1;
+}
+
 __host__ __device__ inline int ilog2(int v) {
   int r = 0;
   while ((1 << r) < v) ++r;

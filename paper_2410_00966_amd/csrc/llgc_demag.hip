@@ -14,8 +14,9 @@
 // components even in both offsets and purely imaginary or real by parity
 // otherwise, so it is built as separable cosine/sine sums of the
 // non-negative-offset octant (k_dct_x, k_dct_y) and stored mirror-reduced:
-// K[kx][ky][comp][dz], kx <= Px/2, ky <= Py/2, comp = xx yy zz xy xz yz
-// (xz and yz as coefficients of -i), scaled by -mu0/(Px Py).
+// K[kx][ky][kslot(comp, dz)], kx <= Px/2, ky <= Py/2, comp = xx yy zz xy xz
+// yz (xz and yz as coefficients of -i, not stored at dz = 0 where they
+// vanish), scaled by -mu0/(Px Py).
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -180,7 +181,8 @@ __global__ void k_dct_y(const double* __restrict__ o1, float* __restrict__ K,
   }
   // xy: both transforms odd -> (-i sin)(-i sin) = -sin sin
   const double sgn = (comp == 3) ? -1.0 : 1.0;
-  K[(((size_t)kx * Hy + ky) * 6 + comp) * nz + iz] =
+  if (comp >= 4 && iz == 0) return;   // xz, yz vanish at dz = 0
+  K[((size_t)kx * Hy + ky) * kentry(nz) + kslot(comp, iz, nz)] =
       (float)(scale * sgn * acc);
 }
 

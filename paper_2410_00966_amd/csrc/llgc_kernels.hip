@@ -930,11 +930,11 @@ __global__ __launch_bounds__(T) void k_finish_stage(
 
 // ================================================================= k_yspec
 // grid ceil(Hx/W); LDS: W * nz * 3 * Py complex.  Kernel layout
-// K[kx][ky][comp][dz] (comp: xx yy zz xy xz yz; xz, yz coefficients of -i),
-// ky in [0, Py/2]; scaled by -mu0/(Px Py).  Spectrum rows have nyp (even)
+// K[kx][ky][kslot(comp, dz)] (comp: xx yy zz xy xz yz; xz, yz coefficients
+// of -i, absent at dz = 0), ky in [0, Py/2]; scaled by -mu0/(Px Py).  Spectrum rows have nyp (even)
 // entries; entries at y >= ny are zero and stay zero.
-// 3x3 demag-kernel product at one (kx, ky) for all nz layers.  Kp points at
-// K[kx][|ky|] (6 components x NZ offsets); sy = -1 on the mirrored half
+// 3x3 demag-kernel product at one (kx, ky) for all nz layers.  kk holds
+// K[kx][|ky|] as kk[comp NZ + dz] (kernel_load); sy = -1 on the mirrored half
 // (xy and yz are odd in ky); xz, yz are odd in the z offset.
 template <int NZ>
 __device__ __forceinline__ void kernel_product_k(const float (&kk)[6 * NZ],
@@ -968,11 +968,19 @@ __device__ __forceinline__ void kernel_product_k(const float (&kk)[6 * NZ],
   }
 }
 
+// The entry at Kp (kentry(NZ) floats) into kk[comp NZ + dz], the vanishing
+// xz and yz coefficients at dz = 0 as zeros.
 template <int NZ>
 __device__ __forceinline__ void kernel_load(const float* __restrict__ Kp,
                                             float (&kk)[6 * NZ]) {
 #pragma unroll
-  for (int q = 0; q < 6 * NZ; ++q) kk[q] = Kp[q];
+  for (int q = 0; q < 4 * NZ; ++q) kk[q] = Kp[q];
+  kk[4 * NZ] = kk[5 * NZ] = 0.f;
+#pragma unroll
+  for (int dz = 1; dz < NZ; ++dz) {
+    kk[4 * NZ + dz] = Kp[kslot(4, dz, NZ)];
+    kk[5 * NZ + dz] = Kp[kslot(5, dz, NZ)];
+  }
 }
 
 template <int NZ>
@@ -1118,10 +1126,10 @@ __device__ __forceinline__ void yspec_l_body(
             M[q] = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
             XN[q] = make_float2(0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x));
           }
-          kernel_product<NZ>(K + (size_t)ky * 6 * NZ, 1.f, M, Hf);
+          kernel_product<NZ>(K + (size_t)ky * kentry(NZ), 1.f, M, Hf);
 #pragma unroll
           for (int q = 0; q < nz3; ++q) lds[pidx(q * Py + ky)] = Hf[q];
-          kernel_product<NZ>(K + ((size_t)hxn * Hy + ky) * 6 * NZ, 1.f, XN,
+          kernel_product<NZ>(K + ((size_t)hxn * Hy + ky) * kentry(NZ), 1.f, XN,
                              Hf);
 #pragma unroll
           for (int q = 0; q < nz3; ++q) {
@@ -1143,7 +1151,7 @@ __device__ __forceinline__ void yspec_l_body(
 #pragma unroll 1
         for (int r = 0; r < nself; ++r) {
           const int ky = r * Ph;
-          kernel_load<NZ>(K + ((size_t)kx * Hy + ky) * 6 * NZ, kk);
+          kernel_load<NZ>(K + ((size_t)kx * Hy + ky) * kentry(NZ), kk);
 #pragma unroll
           for (int q = 0; q < nz3; ++q) M[q] = lds[pidx(base + q * Py + ky)];
           kernel_product_k<NZ>(kk, 1.f, M, Hf);
@@ -1152,7 +1160,7 @@ __device__ __forceinline__ void yspec_l_body(
         }
         continue;
       }
-      kernel_load<NZ>(K + ((size_t)kx * Hy + kh) * 6 * NZ, kk);
+      kernel_load<NZ>(K + ((size_t)kx * Hy + kh) * kentry(NZ), kk);
 #pragma unroll
       for (int q = 0; q < nz3; ++q) M[q] = lds[pidx(base + q * Py + kh)];
       kernel_product_k<NZ>(kk, 1.f, M, Hf);
@@ -1313,7 +1321,7 @@ __global__ __launch_bounds__(T, 4) void k_yspec_h(
 #pragma unroll
       for (int q = 0; q < nz3; ++q)
         M[q] = lds[pidx(((w * nz3 + q) << lph) + k)];
-      kernel_product<NZ>(K + ((size_t)(kx0 + w) * P.Hy + kyi) * 6 * NZ,
+      kernel_product<NZ>(K + ((size_t)(kx0 + w) * P.Hy + kyi) * kentry(NZ),
                          lo ? 1.f : -1.f, M, Hf);
 #pragma unroll
       for (int q = 0; q < nz3; ++q)
@@ -1368,10 +1376,9 @@ __device__ __forceinline__ void yprod_chunks(
     const bool lo = ky <= (Py >> 1);
     const int kyi = lo ? ky : Py - ky;
     const float sy = lo ? 1.f : -1.f;
-    const float* Kp = K + ((size_t)kx * Hy + kyi) * 6 * NZ;
+    const float* Kp = K + ((size_t)kx * Hy + kyi) * kentry(NZ);
     float kk[6 * NZ];
-#pragma unroll
-    for (int q = 0; q < 6 * NZ; ++q) kk[q] = Kp[q];
+    kernel_load<NZ>(Kp, kk);
     float2 M[nz3], Hf[nz3];
 #pragma unroll
     for (int q = 0; q < nz3; ++q) {
