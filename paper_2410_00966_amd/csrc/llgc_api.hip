@@ -806,6 +806,7 @@ void fill_prm(llgc_ctx* c) {
   P.seed_lo = (unsigned int)(p.seed & 0xFFFFFFFFull);
   P.seed_hi = (unsigned int)(p.seed >> 32);
   P.ms = (float)p.ms;
+  P.ims = p.ms > 0 ? (float)(1.0 / p.ms) : 0.f;
   P.ms_map = c->ms_map;
   P.brms_map = c->brms_map;
   P.masked = c->masked ? 1 : 0;

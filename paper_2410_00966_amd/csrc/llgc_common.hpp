@@ -62,6 +62,7 @@ struct Prm {
   int Px, Py, Hx, Hy, logPx, logPy;
   float idx2, idy2, idz2;       // 1/d^2 per axis
   float ms;                     // uniform Ms (A/m) when ms_map == nullptr
+  float ims;                    // 1 / ms (0 if ms = 0)
   const float* ms_map;
   int masked;                   // ms_map has cells with Ms = 0 (geometry)
   double nmag;                  // magnetic cells (averages)

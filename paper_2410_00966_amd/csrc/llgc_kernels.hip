@@ -1634,7 +1634,9 @@ __device__ __forceinline__ void field_cells_t(const Prm& P,
         ly += dy * id2[q >> 1];
         lz += dz * id2[q >> 1];
       }
-      const float ce = P.aex2 / msv;
+      // 1/Ms: one division per cell only where Ms is a map
+      const float ims = P.ms_map ? 1.f / msv : P.ims;
+      const float ce = P.aex2 * ims;
       Bx += ce * lx; By += ce * ly; Bz += ce * lz;
       if (GEN && (P.dmi_i != 0.f || P.dmi_b != 0.f)) {
         // Dzyaloshinskii-Moriya: over the bonds to existing magnetic
@@ -1650,7 +1652,7 @@ __device__ __forceinline__ void field_cells_t(const Prm& P,
         if (w[2]) { bx -= nbx[2]; by -= nby[2]; bz -= nbz[2]; }
         if (w[5]) { cx += nbx[5]; cy += nby[5]; cz += nbz[5]; }
         if (w[4]) { cx -= nbx[4]; cy -= nby[4]; cz -= nbz[4]; }
-        const float di = P.dmi_i / msv, db = P.dmi_b / msv;
+        const float di = P.dmi_i * ims, db = P.dmi_b * ims;
         // x bonds: c = (-D_bulk, D_int, 0)/dx
         const float x0 = -db * P.idx1, x1 = di * P.idx1;
         Bx += x1 * az; By -= x0 * az; Bz += x0 * ay - x1 * ax;
@@ -1665,7 +1667,7 @@ __device__ __forceinline__ void field_cells_t(const Prm& P,
       const float kuv = 2.f * kum;
       const float um = P.ux * mx + P.uy * my + P.uz * mz;
       const float ca =
-          GEN ? (kuv * um + P.ku4 * um * um * um) / msv : (kuv * um) / msv;
+          GEN ? (kuv * um + P.ku4 * um * um * um) * ims : (kuv * um) * ims;
       Bx += ca * P.ux; By += ca * P.uy; Bz += ca * P.uz;
       if (GEN && P.therm > 0.0) {
         // Brown's field of this step, held over its stages: variance
