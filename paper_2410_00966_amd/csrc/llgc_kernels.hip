@@ -291,6 +291,13 @@ __device__ __forceinline__ void cavity_stage(const Prm& P, Ctl* c, int s,
   const double ts = c->t + stage_c(P, s) * dt;
   const double eps = P.camp * drive_shape(P.ckind, P.cw, ts);
   const double ar = c->as_re[s], ai = c->as_im[s];
+  // the earlier stage rates, loaded together (DP45 sums below)
+  double kar[8], kai[8];
+#pragma unroll
+  for (int j = 1; j <= 7; ++j) {
+    kar[j] = c->ka_re[j];
+    kai[j] = c->ka_im[j];
+  }
   const double kr = -P.kappa * ar + P.wc * ai;
   const double ki = -P.wc * ar - P.kappa * ai + P.vc_hbar * F - eps;
   c->ka_re[s] = kr;
@@ -303,24 +310,27 @@ __device__ __forceinline__ void cavity_stage(const Prm& P, Ctl* c, int s,
       c->as_im[s + 1] = c->a_im + h * ki;
     } else {
       c->anext_re = c->a_re + dt / 6.0 *
-          (c->ka_re[1] + 2.0 * c->ka_re[2] + 2.0 * c->ka_re[3] + kr);
+          (kar[1] + 2.0 * kar[2] + 2.0 * kar[3] + kr);
       c->anext_im = c->a_im + dt / 6.0 *
-          (c->ka_im[1] + 2.0 * c->ka_im[2] + 2.0 * c->ka_im[3] + ki);
+          (kai[1] + 2.0 * kai[2] + 2.0 * kai[3] + ki);
     }
   } else {
     if (s < 7) {
       double sr = 0.0, si = 0.0;
-      for (int j = 1; j <= s; ++j) {
-        sr += c_dp_a[s + 1][j - 1] * c->ka_re[j];
-        si += c_dp_a[s + 1][j - 1] * c->ka_im[j];
+#pragma unroll
+      for (int j = 1; j <= 6; ++j) {
+        if (j > s) break;
+        sr += c_dp_a[s + 1][j - 1] * (j == s ? kr : kar[j]);
+        si += c_dp_a[s + 1][j - 1] * (j == s ? ki : kai[j]);
       }
       c->as_re[s + 1] = c->a_re + dt * sr;
       c->as_im[s + 1] = c->a_im + dt * si;
     } else {
       double er = 0.0, ei = 0.0;
+#pragma unroll
       for (int j = 1; j <= 7; ++j) {
-        er += c_dp_e[j - 1] * c->ka_re[j];
-        ei += c_dp_e[j - 1] * c->ka_im[j];
+        er += c_dp_e[j - 1] * (j == 7 ? kr : kar[j]);
+        ei += c_dp_e[j - 1] * (j == 7 ? ki : kai[j]);
       }
       const double amag = sqrt(c->as_re[7] * c->as_re[7] +
                                c->as_im[7] * c->as_im[7]);
@@ -847,7 +857,18 @@ __device__ __forceinline__ void finish_cavity(const Prm& P, Ctl* ctl,
   // order does not depend on the workgroup size
   if (threadIdx.x >= 64) return;
   double F[1] = {0.0};
-  for (int b = threadIdx.x; b < nblk; b += 64) F[0] += partials[b];
+  // eight loads in flight per lane, added in the same order as one by one
+  for (int b0 = threadIdx.x; b0 < nblk; b0 += 64 * 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int b = b0 + 64 * u;
+      v[u] = b < nblk ? partials[b] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (b0 + 64 * u < nblk) F[0] += v[u];
+  }
   for (int o = 32; o > 0; o >>= 1) F[0] += __shfl_xor(F[0], o, 64);
   if (threadIdx.x != 0) return;
   if (mode == 0) {
