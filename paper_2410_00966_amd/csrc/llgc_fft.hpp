@@ -42,6 +42,12 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 __device__ __forceinline__ float2 cmul_si(float2 a, float s) {
   return make_float2(-s * a.y, s * a.x);
 }
+// multiply by (c h, s h), h = 1/sqrt(2), c, s = +-1 (the odd eighth roots of
+// unity): two additions and two products instead of a general product
+__device__ __forceinline__ float2 cmul_h(float2 a, float c, float s) {
+  const float h = 0.70710678118654752f;
+  return make_float2((c * a.x - s * a.y) * h, (c * a.y + s * a.x) * h);
+}
 
 template <int R>
 struct RadixTag {
@@ -80,10 +86,9 @@ __device__ __forceinline__ void dft_small<8>(float2* v, float s) {
   float2 o[4] = {v[1], v[3], v[5], v[7]};
   dft_small<4>(e, s);
   dft_small<4>(o, s);
-  const float h = 0.70710678118654752f;
-  // w8^p = exp(s i pi p / 4)
-  float2 w1 = make_float2(h, s * h), w3 = make_float2(-h, s * h);
-  float2 o1 = cmul(o[1], w1), o2 = cmul_si(o[2], s), o3 = cmul(o[3], w3);
+  // w8^p = exp(s i pi p / 4): (h, s h), s i, (-h, s h)
+  float2 o1 = cmul_h(o[1], 1.f, s), o2 = cmul_si(o[2], s),
+         o3 = cmul_h(o[3], -1.f, s);
   v[0] = cadd(e[0], o[0]);
   v[4] = csub(e[0], o[0]);
   v[1] = cadd(e[1], o1);
@@ -109,7 +114,12 @@ __device__ __forceinline__ void dft_small<16>(float2* v, float s) {
                        make_float2(-h, s * h),   make_float2(-c1, s * s1)};
 #pragma unroll
   for (int p = 0; p < 8; ++p) {
-    const float2 t = (p == 0) ? o[0] : cmul(o[p], w[p]);
+    // p = 2, 4, 6 are eighth roots of unity: cheaper products
+    const float2 t = (p == 0)   ? o[0]
+                     : (p == 4) ? cmul_si(o[4], s)
+                     : (p == 2) ? cmul_h(o[2], 1.f, s)
+                     : (p == 6) ? cmul_h(o[6], -1.f, s)
+                                : cmul(o[p], w[p]);
     v[p] = cadd(e[p], t);
     v[p + 8] = csub(e[p], t);
   }
@@ -134,9 +144,9 @@ __device__ __forceinline__ void dft_in_half(float2* v, float s) {
     if constexpr (R == 4) {
       o[1] = cmul_si(v[1], s);
     } else if constexpr (R == 8) {
-      o[1] = cmul(v[1], make_float2(h, s * h));
+      o[1] = cmul_h(v[1], 1.f, s);
       o[2] = cmul_si(v[2], s);
-      o[3] = cmul(v[3], make_float2(-h, s * h));
+      o[3] = cmul_h(v[3], -1.f, s);
     } else {
       static_assert(R == 16, "radix 2, 4, 8 or 16");
       const float2 w[8] = {make_float2(1.f, 0.f),  make_float2(c1, s * s1),
@@ -144,7 +154,11 @@ __device__ __forceinline__ void dft_in_half(float2* v, float s) {
                            make_float2(0.f, s),     make_float2(-s1, s * c1),
                            make_float2(-h, s * h),  make_float2(-c1, s * s1)};
 #pragma unroll
-      for (int q = 1; q < H; ++q) o[q] = cmul(v[q], w[q]);
+      for (int q = 1; q < H; ++q)
+        o[q] = (q == 4)   ? cmul_si(v[4], s)
+               : (q == 2) ? cmul_h(v[2], 1.f, s)
+               : (q == 6) ? cmul_h(v[6], -1.f, s)
+                          : cmul(v[q], w[q]);
     }
     dft_small<H>(e, s);
     dft_small<H>(o, s);
