@@ -35,8 +35,12 @@ __device__ __forceinline__ float2 cadd(float2 a, float2 b) {
 __device__ __forceinline__ float2 csub(float2 a, float2 b) {
   return make_float2(a.x - b.x, a.y - b.y);
 }
+// Complex product with its two fused multiply-adds written out, so that
+// every kernel the transforms are inlined into rounds them alike (left to
+// the compiler, which product of a.x b.x - a.y b.y is fused can differ from
+// one kernel to another).
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+  return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 // multiply by s*i with s = +-1
 __device__ __forceinline__ float2 cmul_si(float2 a, float s) {
