@@ -66,6 +66,8 @@ struct llgc_ctx {
   bool fused_run = false;   // launches of a chunk with fused passes
   bool yhalf = false;    // LDS spectral pass split by ky parity (k_yspec_h)
   bool no_ypersist = false;  // LLGC_NO_YPERSIST: one spectral block per workgroup
+  bool ysplit = false;   // two-layer spectral pass with half the LDS (k_yspec_z)
+  size_t lds_yz = 0;     // its dynamic LDS
   int ncu = 0;           // compute units of the device
   int Tyh = 512;         // its workgroup size
   size_t lds_yh = 0;     // its LDS bytes
@@ -433,6 +435,21 @@ int launch_yspec(llgc_ctx* c, Ctl* ctl, int stage, int mode) {
   // k_yspec pairs the real columns kx = 0 and Px/2 into one slot
   const int nslot = c->Px >= 2 ? c->Px / 2 : c->Hx;
   g = dim3((nslot + c->W - 1) / c->W);
+  if (c->ysplit) {
+    // one slot per workgroup
+    const int nf = (int)xgrid(c, fwd_rows(c)).x;
+    const dim3 gz((unsigned)nslot);
+#define LLGC_YZ_ARGS c->P, c->spec, c->K, ctl, c->tw, c->logTw, c->partials, \
+                     nf, stage, mode, nslot
+    if (c->logPy == 11)
+      hipLaunchKernelGGL(k_yspec_z<11>, gz, dim3(kYzT), c->lds_yz, c->stream,
+                         LLGC_YZ_ARGS);
+    else
+      hipLaunchKernelGGL(k_yspec_z<10>, gz, dim3(kYzT), c->lds_yz, c->stream,
+                         LLGC_YZ_ARGS);
+#undef LLGC_YZ_ARGS
+    return check_launch(c, "k_yspec_z");
+  }
   if constexpr (kTyMax >= 1024) {
     if (c->Ty == 1024) yspec_nz<1024>(c, ctl, g, stage, mode);
   }
@@ -921,6 +938,14 @@ int plan_derive(llgc_ctx* c) {
   const int lpy = (c->logPy == 10 || c->logPy == 11) ? c->logPy : 0;
   c->lds_y = sizeof(float2) * (yspec_tw_len(lpy, c->logTw) +
                                padded_len((size_t)W * col));
+  // two layers of 1024 or 2048 points, one kx slot per block: the split
+  // pass (k_yspec_z) needs LDS for three columns only, so two workgroups
+  // share a CU (film: 59.7 -> 57.0 us); LLGC_NO_YSPLIT keeps k_yspec
+  c->ysplit = getenv("LLGC_NO_YSPLIT") == nullptr && c->nz == 2 && W == 1 &&
+              lpy > 0 && !c->use_wy && !c->yhalf && !c->batch_plan &&
+              c->Px >= 2;
+  c->lds_yz = sizeof(float2) * (yspec_tw_len(lpy, c->logTw) +
+                                padded_len((size_t)3 * c->Py));
   int dev = 0, maxlds = 65536;
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock,
@@ -978,6 +1003,10 @@ int plan_derive(llgc_ctx* c) {
           (const void*)k_yspec<1024, 1, 11>, (const void*)k_yspec<1024, 2, 11>};
       for (const void* f : fs) blocks_per_cu(f, 1024, c->lds_y);
     }
+  }
+  if (c->ysplit) {
+    raise_lds_limit((const void*)k_yspec_z<10>, c->lds_yz);
+    raise_lds_limit((const void*)k_yspec_z<11>, c->lds_yz);
   }
   return LLGC_OK;
 }
@@ -1118,6 +1147,7 @@ std::vector<unsigned char> chunk_signature(const llgc_ctx* c) {
   };
   put(&c->P, sizeof(Prm));
   const int plan[] = {c->use_wy, c->use_wxf, c->use_wxi, c->yhalf, c->x3,
+                      c->ysplit,
                       c->Rf,     c->Ri,      c->W,       c->Ty,    c->Ww,
                       c->Rw,     c->Rwf,     c->Tyh,     (int)c->lds_f,
                       (int)c->lds_i, (int)c->lds_y, (int)c->lds_yh};

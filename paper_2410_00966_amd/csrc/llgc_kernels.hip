@@ -1271,6 +1271,200 @@ __global__ __launch_bounds__(T) void k_yspec(
 }
 
 
+// ============================================================== k_yspec_z
+// Spectral pass for two layers (nz = 2) and one kx slot per block, with
+// half the LDS of k_yspec: the three columns of layer 1 are transformed
+// first and their spectrum moves into registers (each thread keeps the rows
+// ky = kh, Py - kh of the mirrored pairs it multiplies later), then layer 0
+// is transformed in the same LDS; the 3x3 product with the z-offset sum
+// reads layer 0 from LDS and layer 1 from registers, writes H(layer 0) back
+// to LDS and keeps H(layer 1) in registers; layer 0 is inverse transformed
+// and stored, then layer 1 from the registers.  Two 512-thread workgroups
+// share a CU, so one can run its VALU-bound butterflies while the other
+// waits on LDS or memory.  Arithmetic per element as k_yspec's.  Grid: one
+// workgroup per kx slot (nblk of them).
+constexpr int kYzT = 512;
+template <int LP>
+__global__ __launch_bounds__(kYzT) __attribute__((amdgpu_waves_per_eu(4))) void k_yspec_z(
+    Prm P, float2* __restrict__ spec, const float* __restrict__ K,
+    Ctl* __restrict__ ctl, const float2* __restrict__ tw, int logTw,
+    const double* __restrict__ partials, int nblk_f, int stage, int mode,
+    int nblk) {
+  constexpr int T = kYzT, NZ = 2, nz3 = 6, Py = 1 << LP, Ph = Py >> 1;
+  constexpr int hp = Py >> 2;          // row pairs of a column's lower half
+  constexpr int NKH = Ph / T;          // mirrored pairs per thread (>= 1)
+  static_assert(NKH >= 1, "Py >= 2 T");
+  extern __shared__ float2 lds_all[];
+  __shared__ double red[16];
+  if (ctl->done) return;
+  float2* twl = lds_all;
+  float2* lds = lds_all + yspec_tw_len(LP, logTw);
+  fft_tt_build<VPTY, true, LP>(twl, tw, logTw);
+  const int blk0 = blockIdx.x;
+  if (blk0 == 0 && !P.modes) {
+    finish_cavity(P, ctl, partials, nblk_f, stage, mode, red);
+    __syncthreads();
+  }
+  const int ny = P.ny, nyp = P.nyp, Hy = P.Hy;
+  const int hxn = P.Px >> 1;   // slot 0 pairs kx = 0 and Px/2 (Px >= 2)
+  // layer-1 rows ky, km of the thread's mirrored pairs (kh = tid + i T):
+  // spectrum after the forward transform, then the product's output
+  float2 r1[NKH][2][3];
+  {
+    const int blk = blk0;
+    (void)nblk;
+    const int tid = threadIdx.x;
+    const bool has_pair = blk == 0;
+    const int kx = blk;   // one slot per block; slot 0 = (0, Px/2)
+    // lower halves of layer z's three columns into LDS (column c at c Py)
+    auto load_layer = [&](int z) {
+      for (int e = tid; e < 3 * hp; e += T) {
+        const int c = e / hp, y = (e - c * hp) << 1;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (y < ny) {
+          const int q = z * 3 + c;
+          v = ld4(spec, (unsigned)((kx * nz3 + q) * nyp + y) << 3);
+          if (has_pair) {
+            const float4 n = ld4(spec, (unsigned)((hxn * nz3 + q) * nyp + y)
+                                           << 3);
+            v = make_float4(v.x, n.x, v.z, n.z);
+          }
+        }
+        *(float4*)(lds + pidx(c * Py + y)) = v;
+      }
+    };
+    // rows (ky, km) of mirrored pair kh; kh = 0: the self-mirrored rows 0
+    // and Py/2
+    auto rows = [&](int kh, int& ky, int& km) {
+      ky = kh;
+      km = kh == 0 ? Ph : Py - kh;
+    };
+    auto store_layer = [&](int z) {
+      for (int e = tid; e < 3 * hp; e += T) {
+        const int c = e / hp, y = (e - c * hp) << 1;
+        if (y >= nyp) continue;
+        float4 v = *(const float4*)(lds + pidx(c * Py + y));
+        if (y + 1 >= ny) { v.z = 0.f; v.w = 0.f; }   // keep the pad zero
+        const int q = z * 3 + c;
+        if (has_pair) {
+          st4(spec, (unsigned)((hxn * nz3 + q) * nyp + y) << 3,
+              make_float4(v.y, 0.f, v.w, 0.f));
+          v = make_float4(v.x, 0.f, v.z, 0.f);
+        }
+        st4(spec, (unsigned)((kx * nz3 + q) * nyp + y) << 3, v);
+      }
+    };
+    // ---- layer 1: forward transform, spectrum into registers
+    load_layer(1);
+    __syncthreads();
+    fft_lds<VPTY, true, LP, true, false, 4, true>(lds, LP, 3, twl, logTw,
+                                                 -1.f, tid);
+#pragma unroll
+    for (int i = 0; i < NKH; ++i) {
+      int ky, km;
+      rows(tid + i * T, ky, km);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        r1[i][0][c] = lds[pidx(c * Py + ky)];
+        r1[i][1][c] = lds[pidx(c * Py + km)];
+      }
+    }
+    __syncthreads();
+    // ---- layer 0: forward transform in the same LDS
+    load_layer(0);
+    __syncthreads();
+    fft_lds<VPTY, true, LP, true, false, 4, true>(lds, LP, 3, twl, logTw,
+                                                 -1.f, tid);
+    // ---- product at (ky, km) of each of the thread's pairs; layer-0
+    // results go straight back to LDS, layer-1 results to registers
+#pragma unroll
+    for (int i = 0; i < NKH; ++i) {
+      const int kh = tid + i * T;
+      int ky, km;
+      rows(kh, ky, km);
+      float2 Ma[nz3], Mb[nz3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        Ma[c] = lds[pidx(c * Py + ky)];
+        Mb[c] = lds[pidx(c * Py + km)];
+        Ma[3 + c] = r1[i][0][c];
+        Mb[3 + c] = r1[i][1][c];
+      }
+      // result H at row y (j = 0: ky, j = 1: km)
+      auto put = [&](const float2 (&H)[nz3], int y, int j) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          lds[pidx(c * Py + y)] = H[c];
+          r1[i][j][c] = H[3 + c];
+        }
+      };
+      if (has_pair) {
+        // slot 0: Z = X0 + i XN; X0[ky] = (Z[ky] + conj Z[-ky]) / 2,
+        // XN[ky] = (Z[ky] - conj Z[-ky]) / (2i); each column's own kernel
+        // at |ky|, then W[ky] = Y0[ky] + i YN[ky], W[-ky] = conj Y0[ky] +
+        // i conj YN[ky] (real results)
+        for (int r = 0; r < (kh == 0 ? 2 : 1); ++r) {
+          const int y1 = r == 0 ? ky : km;
+          float2 X0[nz3], XN[nz3], Y0[nz3], YN[nz3];
+#pragma unroll
+          for (int q = 0; q < nz3; ++q) {
+            const float2 z = r == 0 ? Ma[q] : Mb[q];   // at y1
+            const float2 zm = kh == 0 ? z : Mb[q];     // at -y1
+            X0[q] = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
+            XN[q] = make_float2(0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x));
+          }
+          kernel_product<NZ>(K + (size_t)y1 * kentry(NZ), 1.f, X0, Y0);
+          kernel_product<NZ>(K + ((size_t)hxn * Hy + y1) * kentry(NZ), 1.f,
+                             XN, YN);
+          float2 W[nz3];
+#pragma unroll
+          for (int q = 0; q < nz3; ++q)
+            W[q] = make_float2(Y0[q].x - YN[q].y, Y0[q].y + YN[q].x);
+          put(W, y1, r);
+          if (kh != 0) {
+#pragma unroll
+            for (int q = 0; q < nz3; ++q)
+              W[q] = make_float2(Y0[q].x + YN[q].y, -Y0[q].y + YN[q].x);
+            put(W, km, 1);
+          }
+        }
+      } else {
+        float kk[6 * NZ];
+        float2 H[nz3];
+        // kh = 0: rows 0 and Py/2, each its own mirror (even parts only)
+        kernel_load<NZ>(K + ((size_t)kx * Hy + ky) * kentry(NZ), kk);
+        kernel_product_k<NZ>(kk, 1.f, Ma, H);
+        put(H, ky, 0);
+        if (kh == 0)
+          kernel_load<NZ>(K + ((size_t)kx * Hy + km) * kentry(NZ), kk);
+        kernel_product_k<NZ>(kk, kh == 0 ? 1.f : -1.f, Mb, H);
+        put(H, km, 1);   // odd-in-ky parts flip on the mirrored row
+      }
+    }
+    __syncthreads();
+    // ---- layer 0: inverse transform and store
+    fft_lds<VPTY, true, LP, false, true, 4, true>(lds, LP, 3, twl, logTw,
+                                                 1.f, tid);
+    store_layer(0);
+    __syncthreads();
+    // ---- layer 1: its product rows back into LDS, inverse, store
+#pragma unroll
+    for (int i = 0; i < NKH; ++i) {
+      int ky, km;
+      rows(tid + i * T, ky, km);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        lds[pidx(c * Py + ky)] = r1[i][0][c];
+        lds[pidx(c * Py + km)] = r1[i][1][c];
+      }
+    }
+    __syncthreads();
+    fft_lds<VPTY, true, LP, false, true, 4, true>(lds, LP, 3, twl, logTw,
+                                                 1.f, tid);
+    store_layer(1);
+  }
+}
+
 // ============================================================== k_yspec_h
 // Spectral pass split by ky parity.  A y column is zero beyond Py/2, so its
 // Py-point DFT splits exactly into the even-ky half (the Py/2-point DFT of
