@@ -66,7 +66,7 @@ def kernel_bytes(plan, prob, method, kernel, fused=False):
     if kernel == "k_xfield":
         per = [field(stages[-1])] if fused else [field(s) for s in stages]
         return sum(per) / len(per)
-    if kernel == "k_begin":
+    if kernel in ("k_begin", "k_step_begin"):
         return 5 * state
     if kernel == "k_record":
         return state

@@ -66,6 +66,9 @@ struct llgc_ctx {
   bool fused_run = false;   // launches of a chunk with fused passes
   bool yhalf = false;    // LDS spectral pass split by ky parity (k_yspec_h)
   bool no_ypersist = false;  // LLGC_NO_YPERSIST: one spectral block per workgroup
+  // Dormand-Prince controller fused into the next attempt's start
+  // (LLGC_NO_STEP_BEGIN: a separate one-workgroup k_finish_step)
+  bool step_begin = true;
   bool ysplit = false;   // two-layer spectral pass with half the LDS (k_yspec_z)
   size_t lds_yz = 0;     // its dynamic LDS
   int ncu = 0;           // compute units of the device
@@ -523,9 +526,11 @@ int field_rows(const llgc_ctx* c) { return c->use_wxi ? c->Rw : c->Ri; }
 // One right-hand side.  In a fused chunk (c->fused_run) the stage's
 // forward x pass was done by the previous stage's field pass unless
 // `first`, and `fuse_next` lets this stage's field pass do the next one's.
+// `end_in_begin`: a Dormand-Prince attempt's controller is left to the
+// k_step_begin launch that follows.
 int rhs_stage(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
               const Epi& E, int mode, bool first = true,
-              bool fuse_next = false) {
+              bool fuse_next = false, bool end_in_begin = false) {
   int r;
   if (first && (r = launch_xfwd(c, ys, ctl, stage, mode))) return r;
   if (c->P.modes) {
@@ -552,7 +557,7 @@ int rhs_stage(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
   }
   if ((r = launch_yspec(c, ctl, stage, mode))) return r;
   if ((r = launch_xfield(c, ys, ctl, stage, E, fuse_next))) return r;
-  if (E.kind == 2 || E.kind == 3) {
+  if (E.kind == 2 || (E.kind == 3 && !end_in_begin)) {
     Timed tm(c, "k_finish_step");
     hipLaunchKernelGGL(k_finish_step<kT>, dim3(1), dim3(kT), 0, c->stream,
                        c->P, ctl, c->partials,
@@ -568,6 +573,15 @@ int rhs_stage(llgc_ctx* c, const float* ys, Ctl* ctl, int stage,
 int begin_blocks(const llgc_ctx* c) {
   const int per = c->ncu > 0 ? 2 * c->ncu : 512;
   return std::max(1, std::min(per, (c->N / 4 + kT - 1) / kT));
+}
+
+// The end of an attempt (controller) fused with the next one's start.
+int launch_step_begin(llgc_ctx* c) {
+  Timed tm(c, "k_step_begin");
+  hipLaunchKernelGGL(k_step_begin<kT>, dim3(begin_blocks(c)), dim3(kT), 0,
+                     c->stream, c->P, c->yn, c->kb[0], c->yb[1], c->kb[6],
+                     c->yb[0], c->ctl, c->partials, c->rec);
+  return check_launch(c, "k_step_begin");
 }
 
 int launch_begin(llgc_ctx* c) {
@@ -1135,10 +1149,14 @@ int chunk_direct(llgc_ctx* c, int kind, int attempts = kDpChunk) {
     }
   } else {
     for (int b = 0; b < attempts && !r; ++b) {
-      for (int s = 2; s <= 7 && !r; ++s)
-        r = rhs_stage(c, c->yb[s % 2], c->ctl, s, epi_dp(c, s), 0,
-                      !fz || s == 2, fz && s < 7);
-      if (!r) r = launch_begin(c);
+      for (int s = 2; s <= 7 && !r; ++s) {
+        Epi E = epi_dp(c, s);
+        if (s == 7 && c->step_begin)
+          E.emax = (unsigned int*)((char*)c->ctl + offsetof(Ctl, emax_bits));
+        r = rhs_stage(c, c->yb[s % 2], c->ctl, s, E, 0, !fz || s == 2,
+                      fz && s < 7, c->step_begin);
+      }
+      if (!r) r = c->step_begin ? launch_step_begin(c) : launch_begin(c);
     }
   }
   c->fused_run = false;
@@ -1255,6 +1273,7 @@ int llgc_create_ex(const llgc_grid* g, void* stream, int flags,
                             c->device) != hipSuccess)
     c->ncu = 0;
   c->no_ypersist = getenv("LLGC_NO_YPERSIST") != nullptr;
+  c->step_begin = getenv("LLGC_NO_STEP_BEGIN") == nullptr;
   c->no_fuse = getenv("LLGC_NO_FUSE") != nullptr;
   c->force_fuse = getenv("LLGC_FUSE") != nullptr;
   c->batch_plan = bplan;
@@ -1880,6 +1899,7 @@ int run_prepare(llgc_ctx* c, int64_t nsteps, double t_end, int32_t rec_every,
   h.accepted = 0;
   h.rejected = 0;
   h.cnt_xfwd = h.cnt_field = h.cnt_begin = h.cnt_rec = 0;
+  h.emax_bits = 0;
   rp->rk4 = c->prm.method == LLGC_RK4;
   rp->evals = 0;
   if (rp->rk4) {

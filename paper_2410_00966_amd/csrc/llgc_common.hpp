@@ -35,7 +35,8 @@ struct Ctl {
   double rhs_dadt_re, rhs_dadt_im;
   long long accepted, rejected, rhs_evals, max_accepted;
   int pending_accept, done, status, prev_rej;
-  int nrec, rec_every, rec_cap, pad0;
+  int nrec, rec_every, rec_cap;
+  unsigned int emax_bits;   // Dormand-Prince error: atomic maximum (float bits)
   unsigned int cnt_xfwd, cnt_field, cnt_begin, cnt_rec;
   // optional: per-step cavity history (stage amplitudes a_1..a_4 and the
   // end-of-step amplitude, 5 complex per step) and the windowed loss
@@ -114,6 +115,8 @@ struct Epi {
   float* commit;       // RK4 stage 1 of a run: the stage input (the state
                        // the previous step left in a scratch register) is
                        // copied here, committing it as y_n (or null)
+  unsigned int* emax;  // DP45 error: also kept as the atomic maximum of the
+                       // workgroups' errors' float bits here (or null)
 };
 
 // Demag-kernel table entry: the real coefficients of one (kx, |ky|) for all

@@ -1943,7 +1943,11 @@ __device__ __forceinline__ void field_cells_t(const Prm& P,
     }
   } else {
     emax = block_max(emax, redf);
-    if (threadIdx.x == 0) partials[slot] = (double)emax;
+    if (threadIdx.x == 0) {
+      partials[slot] = (double)emax;
+      // non-negative floats (and +inf) order as their bit patterns
+      if (E.emax) atomicMax(E.emax, __float_as_uint(emax));
+    }
   }
 }
 
@@ -2261,6 +2265,81 @@ __global__ __launch_bounds__(NR >= 32 ? 512 : 1024) void k_xfield_w(
                     tile, tile, bdl);
 }
 
+// Dormand-Prince step controller: the decision on an attempt from the
+// largest per-cell error (errm) and the control block as the attempt left
+// it (dp_decide reads only), and its application (dp_commit writes).
+struct DpDecision {
+  bool accept, bad, done;
+  double err, t, dt;   // err of the attempt; t and next dt after it
+  int status;
+};
+__device__ inline void dp_decide(const Prm& P, const Ctl* c, double errm,
+                                 DpDecision& d) {
+  const double err = fmax(errm, c->err_a);
+  d.bad = !isfinite(err);
+  d.err = err;
+  const double h = c->dt;
+  double fac;
+  d.accept = !d.bad && err <= P.tol;
+  int acc = c->accepted;
+  d.t = c->t;
+  if (d.accept) {
+    fac = (err == 0.0) ? 5.0 : fmin(5.0, fmax(0.2, 0.9 * pow(P.tol / err, 0.2)));
+    if (c->prev_rej) fac = fmin(fac, 1.0);
+    d.t = c->t + h;
+    acc += 1;
+  } else {
+    fac = d.bad ? 0.2 : fmax(0.2, 0.9 * pow(P.tol / err, 0.2));
+  }
+  double dtn = fmin(P.dt_max, h * fac);
+  d.done = c->done || d.t >= c->t_end || acc >= c->max_accepted;
+  d.status = d.bad ? ST_NONFINITE : ST_OK;
+  if (dtn < P.dt_min) {
+    if (!d.bad) d.status = ST_UNDERFLOW;
+    d.done = true;
+  }
+  if (!d.done) dtn = fmin(dtn, c->t_end - d.t);
+  d.dt = dtn;
+}
+__device__ inline void dp_commit(const Prm& P, Ctl* c, const DpDecision& d) {
+  if (d.accept) {
+    c->t = d.t;
+    c->a_re = c->as_re[7];
+    c->a_im = c->as_im[7];
+    c->as_re[1] = c->a_re;
+    c->as_im[1] = c->a_im;
+    c->ka_re[1] = c->ka_re[7];
+    c->ka_im[1] = c->ka_im[7];
+    if (P.modes)
+      for (int k = 0; k < P.modes->n; ++k) {
+        c->ma_re[k] = c->mas_re[1][k] = c->mas_re[7][k];
+        c->ma_im[k] = c->mas_im[1][k] = c->mas_im[7][k];
+        c->mka_re[1][k] = c->mka_re[7][k];
+        c->mka_im[1][k] = c->mka_im[7][k];
+      }
+    c->accepted += 1;
+    c->pending_accept = 1;
+    c->prev_rej = 0;
+  } else {
+    c->prev_rej = 1;
+    c->rejected += 1;
+    c->pending_accept = 0;
+  }
+  c->last_err = d.bad ? INFINITY : d.err;
+  if (d.done) c->done = 1;
+  c->status = d.status;
+  const double dtn = d.dt;
+  c->dt = dtn;
+  // second stage amplitude of the next attempt
+  c->as_re[2] = c->a_re + dtn * c_dp_a[2][0] * c->ka_re[1];
+  c->as_im[2] = c->a_im + dtn * c_dp_a[2][0] * c->ka_im[1];
+  if (P.modes)
+    for (int k = 0; k < P.modes->n; ++k) {
+      c->mas_re[2][k] = c->ma_re[k] + dtn * c_dp_a[2][0] * c->mka_re[1][k];
+      c->mas_im[2][k] = c->ma_im[k] + dtn * c_dp_a[2][0] * c->mka_im[1][k];
+    }
+}
+
 // End of a step, one workgroup: RK4 commit and record (kind 2) or the
 // Dormand-Prince step controller (kind 3), from the k_xfield partials.
 // `ndone` (optional) counts the runs this call finishes.
@@ -2323,56 +2402,9 @@ __device__ __forceinline__ void finish_step_body(
       c->nrec += 1;
     }
   } else {
-    // Dormand-Prince step controller
-    double err = fmax(errm, c->err_a);
-    const bool bad = !isfinite(err);
-    const double h = c->dt;
-    double fac;
-    if (!bad && err <= P.tol) {
-      fac = (err == 0.0) ? 5.0 : fmin(5.0, fmax(0.2, 0.9 * pow(P.tol / err, 0.2)));
-      if (c->prev_rej) fac = fmin(fac, 1.0);
-      c->t = c->t + h;
-      c->a_re = c->as_re[7];
-      c->a_im = c->as_im[7];
-      c->as_re[1] = c->a_re;
-      c->as_im[1] = c->a_im;
-      c->ka_re[1] = c->ka_re[7];
-      c->ka_im[1] = c->ka_im[7];
-      if (P.modes)
-        for (int k = 0; k < P.modes->n; ++k) {
-          c->ma_re[k] = c->mas_re[1][k] = c->mas_re[7][k];
-          c->ma_im[k] = c->mas_im[1][k] = c->mas_im[7][k];
-          c->mka_re[1][k] = c->mka_re[7][k];
-          c->mka_im[1][k] = c->mka_im[7][k];
-        }
-      c->accepted += 1;
-      c->pending_accept = 1;
-      c->prev_rej = 0;
-    } else {
-      fac = bad ? 0.2 : fmax(0.2, 0.9 * pow(P.tol / err, 0.2));
-      c->prev_rej = 1;
-      c->rejected += 1;
-      c->pending_accept = 0;
-      if (bad) c->status = ST_NONFINITE;
-    }
-    c->last_err = bad ? INFINITY : err;
-    double dtn = fmin(P.dt_max, h * fac);
-    if (c->t >= c->t_end || c->accepted >= c->max_accepted) c->done = 1;
-    if (!bad) c->status = ST_OK;
-    if (dtn < P.dt_min) {
-      if (!bad) c->status = ST_UNDERFLOW;
-      c->done = 1;
-    }
-    if (!c->done) dtn = fmin(dtn, c->t_end - c->t);
-    c->dt = dtn;
-    // second stage amplitude of the next attempt
-    c->as_re[2] = c->a_re + dtn * c_dp_a[2][0] * c->ka_re[1];
-    c->as_im[2] = c->a_im + dtn * c_dp_a[2][0] * c->ka_im[1];
-    if (P.modes)
-      for (int k = 0; k < P.modes->n; ++k) {
-        c->mas_re[2][k] = c->ma_re[k] + dtn * c_dp_a[2][0] * c->mka_re[1][k];
-        c->mas_im[2][k] = c->ma_im[k] + dtn * c_dp_a[2][0] * c->mka_im[1][k];
-      }
+    DpDecision d;
+    dp_decide(P, c, errm, d);
+    dp_commit(P, c, d);
   }
   if (ndone && c->done) atomicAdd(ndone, 1);
 }
@@ -2390,24 +2422,16 @@ __global__ __launch_bounds__(T) void k_finish_step(
 // y7 into y_n, FSAL k7 -> k1, record), form y2 = y_n + dt a21 k1.
 // Requires N % 4 == 0 for the vector path (scalar tail otherwise).
 // Workgroup `blk` of `nblk` (grid-stride over the cells of one run).
+// The cell work of an attempt's start: with `pend` (an accepted step) y_n =
+// y7 renormalised and k1 = k7 (FSAL), summing y_n into acc; unless `done`,
+// y2 = y_n + c21 k1.  Workgroup `blk` of `nblk`.
 template <int T>
-__device__ __forceinline__ void begin_body(
+__device__ __forceinline__ void begin_cells(
     const Prm& P, float* __restrict__ yn, float* __restrict__ k1,
     const float* __restrict__ y7, const float* __restrict__ k7,
-    float* __restrict__ y2, Ctl* __restrict__ ctl,
-    double* __restrict__ partials, double* __restrict__ rec, int blk,
-    int nblk) {
-  __shared__ double red[16 * 3];
-  __shared__ bool amlast;
-  const int pend = ctl->pending_accept;
-  const int done = ctl->done;
-  if (done && !pend) return;
-  // the average is reduced only when this accepted step is recorded
-  const bool rec_due = pend && ctl->rec_every > 0 && ctl->nrec < ctl->rec_cap &&
-                       (ctl->accepted % ctl->rec_every) == 0;
+    float* __restrict__ y2, bool pend, bool done, float c21, int blk,
+    int nblk, double (&acc)[3]) {
   const int N = P.ncell;
-  const float c21 = (float)(ctl->dt * c_dp_a[2][0]);
-  double acc[3] = {0.0, 0.0, 0.0};
   const int n4 = N >> 2;
   const int stride = nblk * T;
   // component planes as float4 (N % 4 == 0 checked by the host; the
@@ -2472,6 +2496,26 @@ __device__ __forceinline__ void begin_body(
       y2[2 * N + i] = mz + c21 * kz;
     }
   }
+}
+
+template <int T>
+__device__ __forceinline__ void begin_body(
+    const Prm& P, float* __restrict__ yn, float* __restrict__ k1,
+    const float* __restrict__ y7, const float* __restrict__ k7,
+    float* __restrict__ y2, Ctl* __restrict__ ctl,
+    double* __restrict__ partials, double* __restrict__ rec, int blk,
+    int nblk) {
+  __shared__ double red[16 * 3];
+  __shared__ bool amlast;
+  const int pend = ctl->pending_accept;
+  const int done = ctl->done;
+  if (done && !pend) return;
+  // the average is reduced only when this accepted step is recorded
+  const bool rec_due = pend && ctl->rec_every > 0 && ctl->nrec < ctl->rec_cap &&
+                       (ctl->accepted % ctl->rec_every) == 0;
+  const float c21 = (float)(ctl->dt * c_dp_a[2][0]);
+  double acc[3] = {0.0, 0.0, 0.0};
+  begin_cells<T>(P, yn, k1, y7, k7, y2, pend, done, c21, blk, nblk, acc);
   if (!pend) return;
   if (!rec_due) {
     // every block saw pend = 1; clear it from the last one to arrive, once
@@ -2517,6 +2561,78 @@ __global__ __launch_bounds__(T) void k_begin(
     double* __restrict__ partials, double* __restrict__ rec) {
   begin_body<T>(P, yn, k1, y7, k7, y2, ctl, partials, rec, blockIdx.x,
                 gridDim.x);
+}
+
+// End of a Dormand-Prince attempt and start of the next in one launch (one
+// run): every workgroup takes the step controller's decision from the
+// attempt's largest error (the field pass's atomic maximum in the control
+// block) and the control block as the attempt left it, then does the
+// start's cell work with it.  The last workgroup to arrive -- every other
+// one is past its reads of the control block by then -- commits the
+// decision, clears the maximum and writes the record row.
+template <int T>
+__global__ __launch_bounds__(T) void k_step_begin(
+    Prm P, float* __restrict__ yn, float* __restrict__ k1,
+    const float* __restrict__ y7, const float* __restrict__ k7,
+    float* __restrict__ y2, Ctl* __restrict__ ctl,
+    double* __restrict__ partials, double* __restrict__ rec) {
+  __shared__ double red[16 * 3];
+  __shared__ bool amlast;
+  __shared__ int sflag[3];
+  __shared__ float sc21;
+  if (ctl->done) return;
+  const int blk = blockIdx.x, nblk = gridDim.x;
+  DpDecision d;
+  if (threadIdx.x == 0) {
+    dp_decide(P, ctl, (double)__uint_as_float(ctl->emax_bits), d);
+    sflag[0] = d.accept;
+    sflag[1] = d.done;
+    sflag[2] = d.accept && ctl->rec_every > 0 && ctl->nrec < ctl->rec_cap &&
+               ((ctl->accepted + 1) % ctl->rec_every) == 0;
+    sc21 = (float)(d.dt * c_dp_a[2][0]);
+  }
+  __syncthreads();
+  // wave-uniform (scalar) copies, so that the cell loops branch as k_begin's
+  const bool pend = __builtin_amdgcn_readfirstlane(sflag[0]) != 0;
+  const bool done = __builtin_amdgcn_readfirstlane(sflag[1]) != 0;
+  const bool rec_due = __builtin_amdgcn_readfirstlane(sflag[2]) != 0;
+  const float c21 = __int_as_float(
+      __builtin_amdgcn_readfirstlane(__float_as_int(sc21)));
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (pend || !done)
+    begin_cells<T>(P, yn, k1, y7, k7, y2, pend, done, c21, blk, nblk, acc);
+  double S[3] = {0.0, 0.0, 0.0};
+  if (rec_due) {
+    // the record's sums are published to the last workgroup (fenced)
+    block_sum<3>(acc, red);
+    if (threadIdx.x == 0) {
+      partials[3 * blk + 0] = acc[0];
+      partials[3 * blk + 1] = acc[1];
+      partials[3 * blk + 2] = acc[2];
+    }
+    if (!last_block(&ctl->cnt_begin, nblk, &amlast)) return;
+    sum_partials<3>(partials, nblk, S, red);
+    if (threadIdx.x != 0) return;
+  } else {
+    // nothing to publish: every wave of this workgroup read the control
+    // block before the barrier above, so a bare count suffers no device
+    // fence (which would write back this XCD's L2)
+    if (threadIdx.x != 0) return;
+    if (atomicAdd(&ctl->cnt_begin, 1u) != (unsigned int)nblk - 1) return;
+  }
+  dp_commit(P, ctl, d);
+  ctl->pending_accept = 0;
+  ctl->emax_bits = 0u;
+  if (rec_due) {
+    double* row = rec + (size_t)P.recw * ctl->nrec;
+    row[0] = ctl->t;
+    row[1] = S[0] / P.nmag;
+    row[2] = S[1] / P.nmag;
+    row[3] = S[2] / P.nmag;
+    record_amplitudes(P, ctl, row);
+    ctl->nrec += 1;
+  }
+  ctl->cnt_begin = 0;
 }
 
 // ========================================================== k_torque_stats
