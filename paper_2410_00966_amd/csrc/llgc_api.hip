@@ -953,8 +953,10 @@ int plan_derive(llgc_ctx* c) {
   if (!c->use_wy && !c->yhalf && W * col > ycap)
     return fail(c, LLGC_E_UNSUPPORTED, "column set exceeds one workgroup");
   const size_t twb = sizeof(float2) * lds_twiddles(c->logTw);  // LDS twiddles
-  c->lds_f = twb + sizeof(float2) * padded_len((size_t)((c->batch_plan || c->x3) ? 3 : 1) *
-                                                (c->Rf / 2) * c->Px);
+  const size_t fcol = (size_t)(c->Rf / 2) * c->Px;   // one forward tile
+  c->lds_f = twb + sizeof(float2) * ((c->batch_plan || c->x3)
+                                         ? padded_len(3 * fcol)
+                                         : padded_len_s<kXfPs>(fcol));
   c->lds_i = sizeof(float2) * padded_len_s<kPsField>((size_t)3 * (c->Ri / 2) * c->Px);
   // the spectral pass is specialised on 1024 and 2048 points (yspec_nz)
   const int lpy = (c->logPy == 10 || c->logPy == 11) ? c->logPy : 0;
@@ -967,7 +969,7 @@ int plan_derive(llgc_ctx* c) {
               lpy > 0 && !c->use_wy && !c->yhalf && !c->batch_plan &&
               c->Px >= 2;
   c->lds_yz = sizeof(float2) * (yspec_tw_len(lpy, c->logTw) +
-                                padded_len((size_t)3 * c->Py));
+                                padded_len_s<kYzPs>((size_t)3 * c->Py));
   int dev = 0, maxlds = 65536;
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock,

@@ -424,6 +424,8 @@ __device__ __forceinline__ void record_amplitudes(const Prm& P, const Ctl* c,
 // V4: nx % 4 == 0 and 16-byte aligned planes (vector loads).
 // LP > 0: log2(Px) fixed at compile time (specialised FFT addressing).
 // At most 128 VGPRs (four waves per SIMD): two 512-thread workgroups per CU.
+// LDS padding of the forward x pass: 2 slots every 2^kXfPs values
+constexpr int kXfPs = 4;
 template <int T, bool V4, int LP = 0>
 __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void k_xfwd(
     Prm P, const float* __restrict__ ys, float2* __restrict__ spec,
@@ -480,9 +482,9 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void k_x
           (double)sb.z * vb.z + (double)sb.w * vb.w;
     if (P.demag) {
       const int li = p * Px + x;
-      *(float4*)(lds + pidx(li)) = make_float4(sa.x * va.x, sb.x * vb.x,
+      *(float4*)(lds + pidx_s<kXfPs>(li)) = make_float4(sa.x * va.x, sb.x * vb.x,
                                                sa.y * va.y, sb.y * vb.y);
-      *(float4*)(lds + pidx(li + 2)) = make_float4(sa.z * va.z, sb.z * vb.z,
+      *(float4*)(lds + pidx_s<kXfPs>(li + 2)) = make_float4(sa.z * va.z, sb.z * vb.z,
                                                    sa.w * va.w, sb.w * vb.w);
     }
   };
@@ -533,7 +535,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void k_x
             fc += (double)msv * (double)mv;
           }
         }
-        if (P.demag) lds[pidx(p * Px + x)] = v;
+        if (P.demag) lds[pidx_s<kXfPs>(p * Px + x)] = v;
       }
     }
     facc[0] += fc * br[c];
@@ -547,7 +549,7 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void k_x
     // arithmetic is formed per component, not held across the loop
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    fft_lds<VPT, true, LP, true, false>(lds, P.logPx, np, twl, logTw, -1.f,
+    fft_lds<VPT, true, LP, true, false, kXfPs>(lds, P.logPx, np, twl, logTw, -1.f,
                                         tid);
     // split the two real transforms and write the half spectrum: rows
     // (y0+2p, y0+2p+1) are adjacent -> one 16-byte store per (kx, p)
@@ -558,8 +560,8 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(4))) void k_x
     int k = threadIdx.x / np, p = threadIdx.x - k * np;
     for (int e = threadIdx.x; e < totw;
          e += T, k += dk, p += dp, (p >= np ? (p -= np, ++k) : 0)) {
-      const float2 z1 = lds[pidx(p * Px + k)];
-      const float2 z2 = lds[pidx(p * Px + ((Px - k) & (Px - 1)))];
+      const float2 z1 = lds[pidx_s<kXfPs>(p * Px + k)];
+      const float2 z2 = lds[pidx_s<kXfPs>(p * Px + ((Px - k) & (Px - 1)))];
       // A = (Z[k] + conj Z[-k]) / 2 ; B = (Z[k] - conj Z[-k]) / (2i)
       const float4 AB = make_float4(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y),
                                     0.5f * (z1.y + z2.y), -0.5f * (z1.x - z2.x));
@@ -1284,6 +1286,8 @@ __global__ __launch_bounds__(T) void k_yspec(
 // waits on LDS or memory.  Arithmetic per element as k_yspec's.  Grid: one
 // workgroup per kx slot (nblk of them).
 constexpr int kYzT = 512;
+// LDS padding of the two-layer pass: 2 slots every 2^kYzPs values
+constexpr int kYzPs = 5;
 template <int LP>
 __global__ __launch_bounds__(kYzT) __attribute__((amdgpu_waves_per_eu(4))) void k_yspec_z(
     Prm P, float2* __restrict__ spec, const float* __restrict__ K,
@@ -1330,7 +1334,7 @@ __global__ __launch_bounds__(kYzT) __attribute__((amdgpu_waves_per_eu(4))) void 
             v = make_float4(v.x, n.x, v.z, n.z);
           }
         }
-        *(float4*)(lds + pidx(c * Py + y)) = v;
+        *(float4*)(lds + pidx_s<kYzPs>(c * Py + y)) = v;
       }
     };
     // rows (ky, km) of mirrored pair kh; kh = 0: the self-mirrored rows 0
@@ -1343,7 +1347,7 @@ __global__ __launch_bounds__(kYzT) __attribute__((amdgpu_waves_per_eu(4))) void 
       for (int e = tid; e < 3 * hp; e += T) {
         const int c = e / hp, y = (e - c * hp) << 1;
         if (y >= nyp) continue;
-        float4 v = *(const float4*)(lds + pidx(c * Py + y));
+        float4 v = *(const float4*)(lds + pidx_s<kYzPs>(c * Py + y));
         if (y + 1 >= ny) { v.z = 0.f; v.w = 0.f; }   // keep the pad zero
         const int q = z * 3 + c;
         if (has_pair) {
@@ -1357,7 +1361,7 @@ __global__ __launch_bounds__(kYzT) __attribute__((amdgpu_waves_per_eu(4))) void 
     // ---- layer 1: forward transform, spectrum into registers
     load_layer(1);
     __syncthreads();
-    fft_lds<VPTY, true, LP, true, false, 4, true>(lds, LP, 3, twl, logTw,
+    fft_lds<VPTY, true, LP, true, false, kYzPs, true>(lds, LP, 3, twl, logTw,
                                                  -1.f, tid);
 #pragma unroll
     for (int i = 0; i < NKH; ++i) {
@@ -1365,15 +1369,15 @@ __global__ __launch_bounds__(kYzT) __attribute__((amdgpu_waves_per_eu(4))) void 
       rows(tid + i * T, ky, km);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        r1[i][0][c] = lds[pidx(c * Py + ky)];
-        r1[i][1][c] = lds[pidx(c * Py + km)];
+        r1[i][0][c] = lds[pidx_s<kYzPs>(c * Py + ky)];
+        r1[i][1][c] = lds[pidx_s<kYzPs>(c * Py + km)];
       }
     }
     __syncthreads();
     // ---- layer 0: forward transform in the same LDS
     load_layer(0);
     __syncthreads();
-    fft_lds<VPTY, true, LP, true, false, 4, true>(lds, LP, 3, twl, logTw,
+    fft_lds<VPTY, true, LP, true, false, kYzPs, true>(lds, LP, 3, twl, logTw,
                                                  -1.f, tid);
     // ---- product at (ky, km) of each of the thread's pairs; layer-0
     // results go straight back to LDS, layer-1 results to registers
@@ -1385,8 +1389,8 @@ __global__ __launch_bounds__(kYzT) __attribute__((amdgpu_waves_per_eu(4))) void 
       float2 Ma[nz3], Mb[nz3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        Ma[c] = lds[pidx(c * Py + ky)];
-        Mb[c] = lds[pidx(c * Py + km)];
+        Ma[c] = lds[pidx_s<kYzPs>(c * Py + ky)];
+        Mb[c] = lds[pidx_s<kYzPs>(c * Py + km)];
         Ma[3 + c] = r1[i][0][c];
         Mb[3 + c] = r1[i][1][c];
       }
@@ -1394,7 +1398,7 @@ __global__ __launch_bounds__(kYzT) __attribute__((amdgpu_waves_per_eu(4))) void 
       auto put = [&](const float2 (&H)[nz3], int y, int j) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          lds[pidx(c * Py + y)] = H[c];
+          lds[pidx_s<kYzPs>(c * Py + y)] = H[c];
           r1[i][j][c] = H[3 + c];
         }
       };
@@ -1443,7 +1447,7 @@ __global__ __launch_bounds__(kYzT) __attribute__((amdgpu_waves_per_eu(4))) void 
     }
     __syncthreads();
     // ---- layer 0: inverse transform and store
-    fft_lds<VPTY, true, LP, false, true, 4, true>(lds, LP, 3, twl, logTw,
+    fft_lds<VPTY, true, LP, false, true, kYzPs, true>(lds, LP, 3, twl, logTw,
                                                  1.f, tid);
     store_layer(0);
     __syncthreads();
@@ -1454,12 +1458,12 @@ __global__ __launch_bounds__(kYzT) __attribute__((amdgpu_waves_per_eu(4))) void 
       rows(tid + i * T, ky, km);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        lds[pidx(c * Py + ky)] = r1[i][0][c];
-        lds[pidx(c * Py + km)] = r1[i][1][c];
+        lds[pidx_s<kYzPs>(c * Py + ky)] = r1[i][0][c];
+        lds[pidx_s<kYzPs>(c * Py + km)] = r1[i][1][c];
       }
     }
     __syncthreads();
-    fft_lds<VPTY, true, LP, false, true, 4, true>(lds, LP, 3, twl, logTw,
+    fft_lds<VPTY, true, LP, false, true, kYzPs, true>(lds, LP, 3, twl, logTw,
                                                  1.f, tid);
     store_layer(1);
   }
